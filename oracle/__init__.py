@@ -1,0 +1,254 @@
+"""FP64 CPU oracle of the batched 3DGS training step: TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The product path never does.
+
+It follows the paper's pipeline (section "Background on 3D Gaussian
+Training": Gaussian transformation, rendering, loss, back-propagation) and
+the Adam scaling rules of section "Scaling Hyperparameters for Batched
+Training" (eqs. "lambda" and "beta"). The arithmetic lives in ``oracle.c``;
+this module marshals numpy arrays and writes the L1 loss, which is one line.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ONF = 12          # projected fields per (view, Gaussian)
+TILE = 16
+F_U, F_V, F_DEPTH, F_A, F_B, F_C, F_OPAC, F_R, F_G, F_BL, F_RADIUS, F_REXACT = range(ONF)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        d, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.oracle_project.argtypes = [d, i64, d, d]
+        L.oracle_tiles_touched.argtypes = [d, d, d, i64, i32, d, d, d]
+        L.oracle_tiles_touched.restype = i64
+        L.oracle_bin.argtypes = [d, d, d, d, i64, i32, d, d, i64, d, d, d]
+        L.oracle_bin.restype = i64
+        L.oracle_render.argtypes = [d, i64, i32, i32, d, d, d, d, i32, d, d, d, d, d, d]
+        L.oracle_render_brute.argtypes = [d, i64, i32, i32, d, d, d, d]
+        L.oracle_render_bwd.argtypes = [d, i64, i32, i32, d, d, d, d, d]
+        L.oracle_render_bwd.restype = C.c_int
+        L.oracle_project_bwd.argtypes = [d, i64, d, d, d]
+        L.oracle_adam.argtypes = [d, d, d, d, i64, d, C.c_double, C.c_double, C.c_double, i32, i64]
+        L.oracle_sh_basis.argtypes = [d, i64, d, d]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def pack_camera(cam: dict) -> np.ndarray:
+    return np.concatenate([
+        [cam["width"], cam["height"], cam["fx"], cam["fy"], cam["cx"], cam["cy"]],
+        np.asarray(cam["R"], dtype=np.float64).reshape(9),
+        np.asarray(cam["t"], dtype=np.float64).reshape(3),
+        [cam["znear"]],
+    ]).astype(np.float64)
+
+
+def tiles_xy(cam: dict):
+    return (cam["width"] + TILE - 1) // TILE, (cam["height"] + TILE - 1) // TILE
+
+
+def tile_base(cams: list) -> list:
+    base, out = 0, []
+    for c in cams:
+        out.append(base)
+        tx, ty = tiles_xy(c)
+        base += tx * ty
+    out.append(base)
+    return out
+
+
+# ----------------------------------------------------------------------------- steps
+def sh_basis(dirs: np.ndarray, with_grad: bool = False):
+    dirs = _f64(dirs).reshape(-1, 3)
+    n = dirs.shape[0]
+    Y = np.zeros((n, 16))
+    dY = np.zeros((n, 16, 3)) if with_grad else None
+    lib().oracle_sh_basis(_p(dirs), n, _p(Y), _p(dY) if with_grad else None)
+    return (Y, dY) if with_grad else Y
+
+
+def project(P, cam: dict) -> np.ndarray:
+    """Gaussian transformation of every Gaussian for one view: [ONF][N]."""
+    P = _f64(P)
+    N = P.shape[1]
+    out = np.zeros((ONF, N))
+    lib().oracle_project(_p(P), N, _p(pack_camera(cam)), _p(out))
+    return out
+
+
+def _f32(a) -> np.ndarray:
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def tiles_touched(u, v, r, cams: list) -> np.ndarray:
+    """Tiles touched per (view, Gaussian) from FP32 u, v, radius ([V][N])."""
+    u, v, r = _f32(u), _f32(v), _f32(r)
+    V, N = u.shape
+    Ws = np.array([c["width"] for c in cams], dtype=np.int32)
+    Hs = np.array([c["height"] for c in cams], dtype=np.int32)
+    out = np.zeros((V, N), dtype=np.int32)
+    lib().oracle_tiles_touched(_p(u), _p(v), _p(r), N, V, _p(Ws), _p(Hs), _p(out))
+    return out
+
+
+def bin_sort(u, v, r, depth, cams: list):
+    """Sorted instances: keys (u64: global tile << 32 | FP32 depth bits), ids
+    (Gaussian index) and per-global-tile [start, end) ranges."""
+    u, v, r, depth = _f32(u), _f32(v), _f32(r), _f32(depth)
+    V, N = u.shape
+    K = int(tiles_touched(u, v, r, cams).astype(np.int64).sum())
+    Ws = np.array([c["width"] for c in cams], dtype=np.int32)
+    Hs = np.array([c["height"] for c in cams], dtype=np.int32)
+    T = tile_base(cams)[-1]
+    keys = np.zeros(max(K, 1), dtype=np.uint64)
+    ids = np.zeros(max(K, 1), dtype=np.uint32)
+    ranges = np.zeros((T, 2), dtype=np.uint32)
+    got = lib().oracle_bin(_p(u), _p(v), _p(r), _p(depth), N, V, _p(Ws), _p(Hs), K, _p(keys), _p(ids), _p(ranges))
+    assert got == K, (got, K)
+    return keys[:K], ids[:K], ranges
+
+
+def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, depth_check=False) -> dict:
+    """Tiled render of one view from projected fields [ONF][N] (FP64)."""
+    proj = _f64(proj)
+    N = proj.shape[1]
+    W, H = cam["width"], cam["height"]
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    ranges_view = np.ascontiguousarray(ranges_view, dtype=np.uint32)
+    bgv = np.asarray(bg, dtype=np.float64)
+    rgb = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    last = np.zeros((H, W), dtype=np.uint32)
+    nc = np.zeros((H, W), dtype=np.uint32)
+    amb = np.zeros((H, W), dtype=np.uint8)
+    counts = np.zeros(2, dtype=np.int64)
+    fr = None if fragile is None else np.ascontiguousarray(fragile, dtype=np.uint8)
+    lib().oracle_render(_p(proj), N, W, H, _p(ids) if ids.size else None, _p(ranges_view), _p(bgv),
+                        _p(fr) if fr is not None else None, int(depth_check),
+                        _p(rgb), _p(T), _p(last), _p(nc), _p(amb), _p(counts))
+    return {"rgb": rgb, "T": T, "last": last, "ncontrib": nc, "amb": amb,
+            "evaluated": int(counts[0]), "blended": int(counts[1])}
+
+
+def render_brute(proj, cam: dict, bg=(0.0, 0.0, 0.0)) -> dict:
+    proj = _f64(proj)
+    N = proj.shape[1]
+    W, H = cam["width"], cam["height"]
+    rgb = np.zeros((3, H, W))
+    T = np.zeros((H, W))
+    nc = np.zeros((H, W), dtype=np.uint32)
+    bgv = np.asarray(bg, dtype=np.float64)
+    lib().oracle_render_brute(_p(proj), N, W, H, _p(bgv), _p(rgb), _p(T), _p(nc))
+    return {"rgb": rgb, "T": T, "ncontrib": nc}
+
+
+def render_bwd(proj, cam: dict, ids, ranges_view, dL_drgb, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """d/d(u, v, conic a, b, c, opacity, r, g, b) per Gaussian of one view: [9][N]."""
+    proj = _f64(proj)
+    N = proj.shape[1]
+    W, H = cam["width"], cam["height"]
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    ranges_view = np.ascontiguousarray(ranges_view, dtype=np.uint32)
+    g = _f64(dL_drgb).reshape(3, H, W)
+    out = np.zeros((9, N))
+    bgv = np.asarray(bg, dtype=np.float64)
+    rc = lib().oracle_render_bwd(_p(proj), N, W, H, _p(ids) if ids.size else None, _p(ranges_view),
+                                 _p(bgv), _p(g), _p(out))
+    assert rc == 0
+    return out
+
+
+def project_bwd(P, cam: dict, dproj) -> np.ndarray:
+    P = _f64(P)
+    N = P.shape[1]
+    dproj = _f64(dproj)
+    grad = np.zeros((59, N))
+    lib().oracle_project_bwd(_p(P), N, _p(pack_camera(cam)), _p(dproj), _p(grad))
+    return grad
+
+
+def adam(p, g, m, v, lr6, beta1: float, beta2: float, eps: float, batch: int, t: int) -> None:
+    """In-place Adam step on [59][N] float64 arrays with the batch scaling rules."""
+    for a in (p, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    N = p.shape[1]
+    lr = np.asarray(lr6, dtype=np.float64)
+    lib().oracle_adam(_p(p), _p(g), _p(m), _p(v), N, _p(lr), beta1, beta2, eps, batch, t)
+
+
+def l1_loss(images: list, targets: list):
+    """Mean absolute error over the 3HW values of each view, averaged over the
+    views of the batch (the batch gradient is the mean of per-view gradients);
+    returns (loss, [dL/dimage per view]) with sign(0) = 0."""
+    V = len(images)
+    loss, grads = 0.0, []
+    for im, tg in zip(images, targets):
+        d = _f64(im) - _f64(tg)
+        loss += np.abs(d).mean() / V
+        grads.append(np.sign(d) / (d.size * V))
+    return loss, grads
+
+
+# ----------------------------------------------------------------------------- pipelines
+def rounded_for_binning(proj: np.ndarray):
+    """FP32 copies of (u, v, radius, depth): binning decides in FP32."""
+    return (proj[F_U].astype(np.float32), proj[F_V].astype(np.float32),
+            proj[F_RADIUS].astype(np.float32), proj[F_DEPTH].astype(np.float32))
+
+
+def forward(P, cams: list, bg=(0.0, 0.0, 0.0), fragile_tol: float = 0.0) -> dict:
+    """Whole forward for a batch of views from the oracle's own projection."""
+    projs = [project(P, c) for c in cams]
+    parts = [rounded_for_binning(pr) for pr in projs]
+    u, v, r, d = (np.stack([p[j] for p in parts]) for j in range(4))
+    keys, ids, ranges = bin_sort(u, v, r, d, cams)
+    base = tile_base(cams)
+    views = []
+    for vi, (pr, c) in enumerate(zip(projs, cams)):
+        fragile = None
+        if fragile_tol > 0.0:
+            re = pr[F_REXACT]
+            fragile = (np.abs(re - np.round(re)) <= fragile_tol * np.maximum(re, 1.0)).astype(np.uint8)
+        views.append(render(pr, c, ids, ranges[base[vi]:base[vi + 1]], bg, fragile, depth_check=fragile_tol > 0.0))
+    return {"proj": projs, "keys": keys, "ids": ids, "ranges": ranges, "views": views, "tile_base": base}
+
+
+def backward(P, cams: list, fwd: dict, dL_drgb: list, bg=(0.0, 0.0, 0.0)):
+    """Gradient of the loss w.r.t. the [59][N] parameters, summed over views;
+    also returns the per-view [9][N] projected-space gradients."""
+    P64 = _f64(P)
+    grad = np.zeros_like(P64)
+    dprojs = []
+    base = fwd["tile_base"]
+    for vi, c in enumerate(cams):
+        dp = render_bwd(fwd["proj"][vi], c, fwd["ids"], fwd["ranges"][base[vi]:base[vi + 1]], dL_drgb[vi], bg)
+        dprojs.append(dp)
+        grad += project_bwd(P64, c, dp)
+    return grad, dprojs

@@ -1,0 +1,249 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) batched 3D Gaussian Splatting
+ * training step: Gaussians x cameras -> images, loss -> parameter gradients,
+ * and the optimizer step with the batch-size scaling rules.
+ *
+ * Paper: "On Scaling Up 3D Gaussian Splatting Training" (arXiv 2406.18533).
+ * Each entry point cites the passage that defines the operation it runs.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All pointers are DEVICE memory unless marked [host]. The caller allocates
+ *   and owns every buffer; the library never allocates on these paths and
+ *   keeps no pointer after a call returns (a captured HIP graph keeps the
+ *   pointers, so the caller keeps those buffers alive while it replays).
+ * - Every call is stream-ordered on `stream` and returns without waiting for
+ *   the device, except gs_bin_sort with check = 1.
+ * - dtype selects the arithmetic type of every floating-point buffer of the
+ *   call: GS_F32 (the training path) or GS_F64 (used for finite-difference
+ *   checks). Index and count buffers are integers whatever dtype is.
+ * - Errors: a call returns GS_OK or a negative gs_status and then leaves its
+ *   outputs unspecified; gs_last_error() returns a message for the calling
+ *   thread. No C++ exception crosses this boundary.
+ *
+ * Gaussian parameters (section 2 "3D Gaussian Splatting", four learnable
+ * quantities per Gaussian: position, scale + rotation, opacity, 48 SH values)
+ * are one planar block params[59][n] (row-major, row stride n):
+ *   rows 0-2 mean (world), 3-5 log-scale, 6-9 quaternion (w, x, y, z; it is
+ *   normalised inside), 10 opacity logit, 11 + 3k + c the degree-3 SH
+ *   coefficient k = l*l + l + m of colour channel c.
+ * Gradients and both Adam moments use the same layout.
+ *
+ * Images: views are concatenated in call order; view v holds rgb [3][H][W]
+ * and one value per pixel [H][W] for final transmittance and last position.
+ * Pixel (x, y) has its centre at (x + 1/2, y + 1/2).
+ *
+ * Tiles: 16x16 pixel blocks (section 3.1 "Pixel-wise Distribution"),
+ * serialised across the batch: global tile id = tiles of earlier views +
+ * ty * ceil(W/16) + tx.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_VERSION_STRING "gsmi 1.0 gfx950"
+#define GS_TILE 16
+#define GS_MAX_VIEWS 64
+#define GS_PARAM_ROWS 59
+#define GS_REC 12           /* scalars per projected record and per projected-gradient record */
+
+typedef enum {
+    GS_OK = 0,
+    GS_ERR_ARG = -1,          /* invalid argument (null pointer, size, view count, dtype) */
+    GS_ERR_CAPACITY = -2,     /* more sorted instances than bins->capacity */
+    GS_ERR_HIP = -3,          /* a HIP runtime call or kernel launch failed */
+    GS_ERR_UNSUPPORTED = -4   /* device is not gfx950 */
+} gs_status;
+
+typedef enum { GS_F32 = 0, GS_F64 = 1 } gs_dtype;
+
+/* A pinhole camera. R is world -> camera (row-major), t its translation, so a
+ * world point x maps to R x + t in the camera frame (+x right, +y down, +z
+ * forward); the camera centre is -R^T t. Pixels project to
+ * (fx X/Z + cx, fy Y/Z + cy). Gaussians with Z <= znear are culled. */
+typedef struct gs_camera {
+    int32_t width, height;
+    double fx, fy, cx, cy;
+    double R[9];
+    double t[3];
+    double znear;
+} gs_camera;
+
+/* Sorted instance buffers: the per-pixel depth-ordered lists of intersecting
+ * Gaussians that the paper calls the Z-buffer (appendix A.2 "Z-buffer"),
+ * stored per 16x16 tile. */
+typedef struct gs_bins {
+    int64_t capacity;         /* entries of tile_keys and ids; < 2^32 */
+    uint32_t *tile_keys;      /* [capacity] global tile id of each sorted instance */
+    uint32_t *ids;            /* [capacity] Gaussian index of each sorted instance */
+    uint32_t *ranges;         /* [total_tiles][2] start, end into ids; (0, 0) when empty */
+    int64_t *n_instances;     /* [1] instance count K (may exceed capacity) */
+    int32_t *overflow;        /* [1] 1 if K > capacity, else 0 */
+    void *workspace;          /* gs_bin_workspace_bytes(n, views, capacity, total_tiles) */
+    size_t workspace_bytes;
+} gs_bins;
+
+#define GS_SCHED_PER_TILE 0    /* one workgroup per tile, XCD-aware tile order */
+#define GS_SCHED_PERSISTENT 1  /* persistent workgroups, cost-balanced chunks + stealing */
+
+/* Launch shape of the two render kernels and the state of the persistent
+ * scheduler (the single-GPU counterpart of section 3.2 "Iterative Workload
+ * Rebalancing" and Algorithm 1 "Calculation of Division Points"). In
+ * persistent mode each gs_render_fwd / gs_render_bwd call first runs
+ * Algorithm 1 on tile_cost (see gs_sched_plan), then launches `workers`
+ * workgroups that take tiles from the `queues` cost-balanced chunks. */
+typedef struct gs_sched {
+    int32_t mode;             /* GS_SCHED_PER_TILE or GS_SCHED_PERSISTENT */
+    int32_t px_per_thread;    /* 1, 2 or 4: 256, 128 or 64 threads per 16x16 tile */
+    int32_t chunk;            /* records staged in LDS per step: 32, 64, 128 or 256 */
+    int32_t workers;          /* persistent workgroups (0 = as many as fit on the GPU at once) */
+    int32_t queues;           /* Algorithm 1 chunks, a multiple of 8 (0 = 64) */
+    int32_t reserved;
+    const uint32_t *tile_cost;/* [total_tiles] estimated cost per tile (NULL = uniform) */
+    void *workspace;          /* gs_sched_workspace_bytes(total_tiles, queues) */
+    size_t workspace_bytes;
+} gs_sched;
+
+/* Adam hyper-parameters [host]. lr[g] is the base learning rate of group g:
+ * 0 rows 0-2 (mean), 1 rows 3-5 (log-scale), 2 rows 6-9 (quaternion),
+ * 3 row 10 (opacity), 4 rows 11-13 (SH degree 0), 5 rows 14-58 (SH degree >= 1). */
+typedef struct gs_adam_hparams {
+    double lr[6];
+    double beta1, beta2, eps;
+    int32_t batch_size;       /* b: lr * sqrt(b), beta^b */
+    int32_t zero_grad;        /* 1: write 0 into grad after the update */
+} gs_adam_hparams;
+
+/* ------------------------------------------------------------------ library */
+const char *gs_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char *gs_last_error(void);
+/* Checks that `device` is a gfx950 GPU and makes it current for later calls
+ * from this thread. GS_ERR_UNSUPPORTED otherwise. */
+gs_status gs_init(int32_t device);
+
+/* ------------------------------------------------------------------ sizes */
+/* Bytes of a projected-record buffer: views * n records of GS_REC scalars. */
+size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views);
+/* Sum over the views of ceil(W/16) * ceil(H/16) [host cameras]. */
+int64_t gs_total_tiles(const gs_camera *cams_host, int32_t views);
+/* Total pixels over the views [host cameras]. */
+int64_t gs_total_pixels(const gs_camera *cams_host, int32_t views);
+size_t gs_bin_workspace_bytes(int64_t n, int32_t views, int64_t capacity, int64_t total_tiles);
+size_t gs_sched_workspace_bytes(int64_t total_tiles, int32_t queues);
+size_t gs_loss_workspace_bytes(const gs_camera *cams_host, int32_t views);
+
+/* ------------------------------------------------------------------ forward */
+/* Gaussian transformation (section 2.1, step 1): for every view v and
+ * Gaussian i, the on-screen position x_{v,i}, depth_{v,i}, footprint radius
+ * radius_{v,i} and view-dependent colour c_{v,i}. Writes projected
+ * [views][n][GS_REC] records:
+ *   0 u, 1 v, 2-4 conic (a, b, c) = inverse of the 2x2 screen covariance,
+ *   5 opacity, 6-8 rgb, 9 radius (integer valued), 10 depth, 11 tiles touched.
+ * The screen covariance is J W Sigma W^T J^T + 0.3 I with Sigma =
+ * R(q) diag(exp(2 l)) R(q)^T and J the perspective Jacobian at the centre
+ * (its x/z, y/z clamped to 1.3x the half field of view); radius =
+ * ceil(3 sqrt(largest eigenvalue)); rgb = max(0, SH(direction) + 1/2).
+ * A record with radius 0 is culled (behind znear or non-finite); then only
+ * radius and tiles touched (0) are defined.
+ * params: [59][n]. cams_dev: [views] cameras in device memory (read by the
+ * kernel, so a captured graph sees updated poses); cams_host: the same
+ * cameras [host] (image sizes). Requires 1 <= views <= GS_MAX_VIEWS,
+ * views * n < 2^32. */
+gs_status gs_project(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
+                     const gs_camera *cams_host, int32_t views, void *projected, void *stream);
+
+/* Z-buffer construction (section 2.1 step 2 intersection test; appendix A.2):
+ * every (view, Gaussian) with tiles touched > 0 emits one instance per tile
+ * of its footprint rectangle, and the instances are sorted by
+ * (global tile, FP32 bits of depth, Gaussian index) - a (view, tile, depth)
+ * radix sort - then [start, end) is found for every tile.
+ * The rectangle is the bounding box of the footprint circle over pixel
+ * centres clipped to the image, decided in FP32:
+ *   x in [ceil(u - r - 1/2), floor(u + r - 1/2)], likewise y.
+ * If K > capacity nothing is written past capacity, *overflow = 1 and the
+ * bins are unusable. check = 1 waits for the stream and returns
+ * GS_ERR_CAPACITY in that case; check = 0 never synchronises (graph-safe).
+ * projected: output of gs_project for the same n and cameras. */
+gs_status gs_bin_sort(gs_dtype dtype, const void *projected, int64_t n, const gs_camera *cams_host,
+                      int32_t views, gs_bins *bins, int32_t check, void *stream);
+
+/* Test helper: 64-bit keys (tile << 32 | FP32 depth bits) of the first
+ * min(K, capacity) sorted instances into keys_out [capacity]. */
+gs_status gs_bins_keys64(gs_dtype dtype, const void *projected, int64_t n, const gs_camera *cams_host,
+                         int32_t views, const gs_bins *bins, uint64_t *keys_out, void *stream);
+
+/* Rendering (section 2.1 step 2): per pixel, walk its tile's list in order;
+ * a Gaussian intersects the pixel if the pixel centre lies within radius of
+ * (u, v); alpha = min(0.99, opacity exp(-(a dx^2 + c dy^2)/2 - b dx dy)) is
+ * skipped below 1/255; the walk stops before a Gaussian that would bring the
+ * transmittance T below 1e-4; otherwise C += rgb alpha T, T *= 1 - alpha.
+ * Writes rgb = C + T bg, final_T and last (list position after the last
+ * blended Gaussian) for every pixel. Optional (nullable) per global tile:
+ * tile_work_fwd = list entries walked, tile_work_bwd = max of last; the
+ * scheduler uses them as the next cost estimates. bg: [host] 3 floats.
+ * sched: launch shape; NULL = per-tile, 256 threads, chunk 64. */
+gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                        const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
+                        void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd,
+                        uint32_t *tile_work_bwd, void *stream);
+
+/* Back-propagation through rendering and transformation (section 2.1,
+ * "standard approaches to backpropagation"; appendix A.3: render backward is
+ * pixel-wise, transformation backward Gaussian-wise). Given dL/drgb it
+ * recomputes the blend in reverse from final_T and last, accumulates the
+ * per-(view, Gaussian) gradients of (u, v, a, b, c, opacity, r, g, b) into
+ * dprojected [views][n][GS_REC] (zeroed by this call first), then adds
+ * (+=) the parameter gradients into grad [59][n]. Depth, radius and the tile
+ * rectangle carry no gradient. bins, final_T and last must come from the
+ * gs_bin_sort / gs_render_fwd of the same projected buffer. */
+gs_status gs_render_bwd(gs_dtype dtype, const void *params, int64_t n, const void *projected,
+                        const gs_bins *bins, const gs_camera *cams_dev, const gs_camera *cams_host,
+                        int32_t views, const float *bg, const gs_sched *sched, const void *final_T,
+                        const uint32_t *last, const void *dL_drgb, void *dprojected, void *grad,
+                        void *stream);
+
+/* Loss (section 2.1 step 3, L1 part): loss = (1/views) sum_v mean over the
+ * 3 H W values of |rgb - target|, the batch loss being the mean of per-view
+ * losses (section 4, g = sum_k g_k / b). Writes dL_drgb = sign(rgb -
+ * target) / (3 H W views) (sign(0) = 0) and *loss_dev (one double, device).
+ * workspace: gs_loss_workspace_bytes. Deterministic. */
+gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host,
+                     int32_t views, void *dL_drgb, double *loss_dev, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------ optimizer */
+/* Adam with the batch scaling rules of section 4: learning rate
+ * lr * sqrt(batch_size) (eq. "lambda") and beta1^b, beta2^b (eq. "beta").
+ * Every element of params/grad/m/v ([59][n]) is updated (dense):
+ *   t = ++(*step_dev); m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+ *   p -= (lr' / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+ * step_dev: [1] device step counter, incremented on the device so graph
+ * replays advance it. scratch: [2] device doubles for the bias corrections.
+ * h: [host]. */
+gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *v, int64_t n,
+                       const gs_adam_hparams *h, int64_t *step_dev, double *scratch, void *stream);
+
+/* ------------------------------------------------------------------ scheduler */
+/* Algorithm 1 ("Calculation of Division Points") on the device with G =
+ * Q = sched->queues: CT = cumsum(ET) with ET_j = tile_cost[j] + 1,
+ * thresholds q * CT[last] / Q, DP = left searchsorted, DP[Q] = total tiles.
+ * Queue q = serialised tiles [DP[q], DP[q+1]) belongs to XCD q div (Q/8), so
+ * consecutive (spatially adjacent) chunks share an XCD's L2; an idle
+ * persistent workgroup steals from the other queues of its XCD first, then
+ * from other XCDs. Resets the queue cursors. The render calls run it
+ * themselves in persistent mode; it is exported for tests.
+ * dp_out: optional [queues + 1] int32 copy of DP (device). */
+gs_status gs_sched_plan(const gs_sched *sched, const gs_camera *cams_host, int32_t views,
+                        int32_t *dp_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

@@ -469,8 +469,9 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
         ev++;
         if (e.amb) am = 1;
         if (fragile && fragile[id]) {
-            double r = proj[10 * N + id];
-            if (e.dx * e.dx + e.dy * e.dy >= (r - 1.0) * (r - 1.0)) am = 1;
+            /* an FP32 radius one off changes the circle test only on this annulus */
+            double r = proj[10 * N + id], d2 = e.dx * e.dx + e.dy * e.dy;
+            if (d2 >= (r - 1.0) * (r - 1.0) && d2 <= (r + 1.0) * (r + 1.0)) am = 1;
         }
         if (!e.inside) continue;
         double Tn = T * (1.0 - e.alpha);

@@ -1,0 +1,374 @@
+// C ABI entry points: argument checks, view tables, dtype dispatch.
+// Every entry point returns a gs_status; no exception leaves this file.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "common.hpp"
+
+namespace gs {
+
+template <typename T> hipError_t launch_project_fwd(const void *, int64_t, const gs_camera *, int32_t, void *, hipStream_t);
+template <typename T>
+hipError_t launch_project_bwd(const void *, int64_t, const gs_camera *, int32_t, const void *, const void *, void *,
+                              hipStream_t);
+template <typename T>
+hipError_t launch_bin_sort(const void *, int64_t, const ViewTable &, gs_bins *, bool, int *, hipStream_t);
+template <typename T>
+hipError_t launch_keys64(const void *, int64_t, const ViewTable &, const gs_bins *, uint64_t *, hipStream_t);
+size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws);
+template <typename T>
+hipError_t launch_render_fwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
+                             const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *, hipStream_t);
+template <typename T>
+hipError_t launch_render_bwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
+                             const LaunchShape &, const void *, const uint32_t *, const void *, void *, hipStream_t);
+hipError_t launch_plan(const uint32_t *, int32_t, int32_t, uint64_t *, int32_t *, int32_t *, int32_t *, hipStream_t);
+template <typename T>
+hipError_t launch_adam(void *, void *, void *, void *, int64_t, const gs_adam_hparams *, int64_t *, double *,
+                       hipStream_t);
+template <typename T>
+hipError_t launch_l1(const void *, const void *, const ViewTable &, void *, double *, void *, hipStream_t);
+size_t loss_ws_bytes(int32_t views);
+
+ViewTable make_view_table(const gs_camera *cams, int32_t views)
+{
+    ViewTable vt;
+    memset(&vt, 0, sizeof vt);
+    vt.nviews = views;
+    int32_t tb = 0;
+    int64_t pb = 0;
+    for (int v = 0; v < views; v++) {
+        int tx = (cams[v].width + TILE - 1) / TILE, ty = (cams[v].height + TILE - 1) / TILE;
+        vt.tile_base[v] = tb;
+        vt.tiles_x[v] = tx;
+        vt.width[v] = cams[v].width;
+        vt.height[v] = cams[v].height;
+        vt.pix_base[v] = pb;
+        tb += tx * ty;
+        pb += (int64_t)cams[v].width * cams[v].height;
+    }
+    vt.tile_base[views] = tb;
+    vt.pix_base[views] = pb;
+    vt.total_tiles = tb;
+    return vt;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+static thread_local std::string g_err;
+
+static gs_status fail(gs_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+static gs_status hip_status(hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return GS_OK;
+    return fail(GS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static bool cams_ok(const gs_camera *cams, int32_t views, std::string &why)
+{
+    if (!cams) { why = "null host cameras"; return false; }
+    if (views < 1 || views > GS_MAX_VIEWS) { why = "views must be in [1, 64]"; return false; }
+    int64_t tiles = 0;
+    for (int v = 0; v < views; v++) {
+        const gs_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 65536 || c.height > 65536) { why = "bad image size"; return false; }
+        if (!(c.fx > 0) || !(c.fy > 0) || !isfinite(c.cx) || !isfinite(c.cy) || !(c.znear > 0)) {
+            why = "bad intrinsics";
+            return false;
+        }
+        tiles += (int64_t)((c.width + 15) / 16) * ((c.height + 15) / 16);
+    }
+    if (tiles >= (int64_t(1) << 31)) { why = "too many tiles"; return false; }
+    return true;
+}
+
+static bool dtype_ok(gs_dtype d) { return d == GS_F32 || d == GS_F64; }
+
+#define CHECK_ARG(cond, msg) \
+    do { if (!(cond)) return fail(GS_ERR_ARG, msg); } while (0)
+
+static int g_cus = 0;
+
+static int cu_count()
+{
+    if (g_cus > 0) return g_cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) g_cus = p.multiProcessorCount;
+    if (g_cus <= 0) g_cus = 256;
+    return g_cus;
+}
+
+extern "C" {
+
+const char *gs_version(void) { return GS_VERSION_STRING; }
+
+const char *gs_last_error(void) { return g_err.c_str(); }
+
+gs_status gs_init(int32_t device)
+{
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_status(e, "hipSetDevice");
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, device);
+    if (e != hipSuccess) return hip_status(e, "hipGetDeviceProperties");
+    if (strncmp(p.gcnArchName, "gfx950", 6) != 0)
+        return fail(GS_ERR_UNSUPPORTED, std::string("device is ") + p.gcnArchName + ", this library is built for gfx950");
+    g_cus = p.multiProcessorCount;
+    return GS_OK;
+}
+
+size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views)
+{
+    if (n < 0 || views < 0 || !dtype_ok(dtype)) return 0;
+    return (size_t)n * (size_t)views * GS_REC * (dtype == GS_F64 ? 8 : 4);
+}
+
+int64_t gs_total_tiles(const gs_camera *cams, int32_t views)
+{
+    std::string why;
+    if (!cams_ok(cams, views, why)) return -1;
+    return make_view_table(cams, views).total_tiles;
+}
+
+int64_t gs_total_pixels(const gs_camera *cams, int32_t views)
+{
+    std::string why;
+    if (!cams_ok(cams, views, why)) return -1;
+    return make_view_table(cams, views).pix_base[views];
+}
+
+size_t gs_bin_workspace_bytes(int64_t n, int32_t views, int64_t capacity, int64_t total_tiles)
+{
+    (void)total_tiles;
+    if (n < 0 || views < 1 || capacity < 0) return 0;
+    return bin_ws_layout(n * views, capacity, nullptr, nullptr);
+}
+
+size_t gs_sched_workspace_bytes(int64_t total_tiles, int32_t queues)
+{
+    if (queues <= 0) queues = 64;
+    return 256 + (size_t)8 * (size_t)(total_tiles > 0 ? total_tiles : 1) + (size_t)4 * (2 * (size_t)queues + 1) + 256;
+}
+
+size_t gs_loss_workspace_bytes(const gs_camera *cams, int32_t views)
+{
+    (void)cams;
+    if (views < 1) return 0;
+    return loss_ws_bytes(views);
+}
+
+gs_status gs_project(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
+                     const gs_camera *cams_host, int32_t views, void *projected, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(n >= 0 && (uint64_t)n * (uint64_t)views < (uint64_t(1) << 32), "n * views must be < 2^32");
+    CHECK_ARG(n == 0 || (params && cams_dev && projected), "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_project_fwd<float>(params, n, cams_dev, views, projected, s)
+                                   : launch_project_fwd<double>(params, n, cams_dev, views, projected, s);
+    return hip_status(e, "gs_project");
+}
+
+static bool bins_ok(const gs_bins *b, int64_t n, int32_t views, std::string &why)
+{
+    if (!b) { why = "null bins"; return false; }
+    if (b->capacity < 0 || b->capacity >= (int64_t(1) << 32) - 1) { why = "capacity must be < 2^32 - 1"; return false; }
+    if (!b->tile_keys || !b->ids || !b->ranges || !b->n_instances || !b->overflow) { why = "null bins buffer"; return false; }
+    if (!b->workspace || b->workspace_bytes < bin_ws_layout(n * views, b->capacity, nullptr, nullptr)) {
+        why = "bins workspace too small";
+        return false;
+    }
+    return true;
+}
+
+gs_status gs_bin_sort(gs_dtype dtype, const void *projected, int64_t n, const gs_camera *cams_host, int32_t views,
+                      gs_bins *bins, int32_t check, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(n >= 0 && (uint64_t)n * (uint64_t)views < (uint64_t(1) << 32), "n * views must be < 2^32");
+    CHECK_ARG(bins_ok(bins, n, views, why), why);
+    CHECK_ARG(n == 0 || projected, "null projected");
+    ViewTable vt = make_view_table(cams_host, views);
+    int cap_err = 0;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_bin_sort<float>(projected, n, vt, bins, check != 0, &cap_err, s)
+                                   : launch_bin_sort<double>(projected, n, vt, bins, check != 0, &cap_err, s);
+    if (e != hipSuccess) return hip_status(e, "gs_bin_sort");
+    if (cap_err) return fail(GS_ERR_CAPACITY, "more instances than bins->capacity");
+    return GS_OK;
+}
+
+gs_status gs_bins_keys64(gs_dtype dtype, const void *projected, int64_t n, const gs_camera *cams_host, int32_t views,
+                         const gs_bins *bins, uint64_t *keys_out, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(bins_ok(bins, n, views, why), why);
+    CHECK_ARG(keys_out && projected, "null pointer");
+    ViewTable vt = make_view_table(cams_host, views);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_keys64<float>(projected, n, vt, bins, keys_out, s)
+                                   : launch_keys64<double>(projected, n, vt, bins, keys_out, s);
+    return hip_status(e, "gs_bins_keys64");
+}
+
+static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh, std::string &why)
+{
+    sh.mode = GS_SCHED_PER_TILE;
+    sh.px = 1;
+    sh.chunk = 64;
+    sh.workers = 0;
+    sh.S.cursor = nullptr;
+    sh.S.dp = nullptr;
+    sh.S.queues = 0;
+    if (!sc) return true;
+    if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT) { why = "bad sched mode"; return false; }
+    if (sc->px_per_thread != 1 && sc->px_per_thread != 2 && sc->px_per_thread != 4) { why = "px_per_thread"; return false; }
+    if (sc->chunk != 32 && sc->chunk != 64 && sc->chunk != 128 && sc->chunk != 256) { why = "chunk"; return false; }
+    sh.mode = sc->mode;
+    sh.px = sc->px_per_thread;
+    sh.chunk = sc->chunk;
+    if (sh.mode == GS_SCHED_PERSISTENT) {
+        int q = sc->queues > 0 ? sc->queues : 64;
+        if (q % 8 != 0 || q > (1 << 16)) { why = "queues must be a positive multiple of 8"; return false; }
+        if (!sc->workspace || sc->workspace_bytes < gs_sched_workspace_bytes(total_tiles, q)) {
+            why = "sched workspace too small";
+            return false;
+        }
+        if (sc->workers < 0 || sc->workers % 8 != 0) { why = "workers must be a multiple of 8"; return false; }
+        char *w = (char *)sc->workspace;
+        sh.S.queues = q;
+        sh.S.cursor = (int32_t *)(w);
+        sh.S.dp = (int32_t *)(w + ((4 * (size_t)q + 255) & ~(size_t)255));
+        int wk = sc->workers;
+        if (wk == 0) wk = cu_count() * 8 * sh.px;  // about 32 wavefronts per CU
+        sh.workers = wk;
+    }
+    return true;
+}
+
+static uint64_t *sched_ct(const gs_sched *sc)
+{
+    int q = sc->queues > 0 ? sc->queues : 64;
+    size_t off = ((4 * (size_t)q + 255) & ~(size_t)255) + ((4 * (size_t)(q + 1) + 255) & ~(size_t)255);
+    return (uint64_t *)((char *)sc->workspace + off);
+}
+
+static hipError_t run_plan(const gs_sched *sc, const LaunchShape &sh, int32_t total_tiles, int32_t *dp_out,
+                           hipStream_t s)
+{
+    return launch_plan(sc->tile_cost, total_tiles, sh.S.queues, sched_ct(sc), sh.S.dp, sh.S.cursor, dp_out, s);
+}
+
+gs_status gs_sched_plan(const gs_sched *sched, const gs_camera *cams_host, int32_t views, int32_t *dp_out, void *stream)
+{
+    std::string why;
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(sched && sched->mode == GS_SCHED_PERSISTENT, "gs_sched_plan needs a persistent sched");
+    ViewTable vt = make_view_table(cams_host, views);
+    LaunchShape sh;
+    CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
+    return hip_status(run_plan(sched, sh, vt.total_tiles, dp_out, (hipStream_t)stream), "gs_sched_plan");
+}
+
+gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                        const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched, void *rgb,
+                        void *final_T, uint32_t *last, uint32_t *tile_work_fwd, uint32_t *tile_work_bwd, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(bins_ok(bins, n, views, why), why);
+    CHECK_ARG(bg && rgb && final_T && last && projected, "null pointer");
+    ViewTable vt = make_view_table(cams_host, views);
+    LaunchShape sh;
+    CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
+    hipStream_t s = (hipStream_t)stream;
+    if (sh.mode == GS_SCHED_PERSISTENT) {
+        hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
+        if (e != hipSuccess) return hip_status(e, "gs_render_fwd plan");
+    }
+    hipError_t e = dtype == GS_F32
+                       ? launch_render_fwd<float>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
+                                                  tile_work_bwd, s)
+                       : launch_render_fwd<double>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
+                                                   tile_work_bwd, s);
+    return hip_status(e, "gs_render_fwd");
+}
+
+gs_status gs_render_bwd(gs_dtype dtype, const void *params, int64_t n, const void *projected, const gs_bins *bins,
+                        const gs_camera *cams_dev, const gs_camera *cams_host, int32_t views, const float *bg,
+                        const gs_sched *sched, const void *final_T, const uint32_t *last, const void *dL_drgb,
+                        void *dprojected, void *grad, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(bins_ok(bins, n, views, why), why);
+    CHECK_ARG(bg && final_T && last && dL_drgb && dprojected && grad && params && projected && cams_dev,
+              "null pointer");
+    ViewTable vt = make_view_table(cams_host, views);
+    LaunchShape sh;
+    CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
+    hipStream_t s = (hipStream_t)stream;
+    if (sh.mode == GS_SCHED_PERSISTENT) {
+        hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
+        if (e != hipSuccess) return hip_status(e, "gs_render_bwd plan");
+    }
+    hipError_t e = dtype == GS_F32
+                       ? launch_render_bwd<float>(vt, projected, n, bins, bg, sh, final_T, last, dL_drgb, dprojected, s)
+                       : launch_render_bwd<double>(vt, projected, n, bins, bg, sh, final_T, last, dL_drgb, dprojected,
+                                                   s);
+    if (e != hipSuccess) return hip_status(e, "gs_render_bwd render");
+    e = dtype == GS_F32 ? launch_project_bwd<float>(params, n, cams_dev, views, projected, dprojected, grad, s)
+                        : launch_project_bwd<double>(params, n, cams_dev, views, projected, dprojected, grad, s);
+    return hip_status(e, "gs_render_bwd transform");
+}
+
+gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host, int32_t views,
+                     void *dL_drgb, double *loss_dev, void *workspace, size_t workspace_bytes, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(rgb && target && dL_drgb && loss_dev && workspace, "null pointer");
+    CHECK_ARG(workspace_bytes >= loss_ws_bytes(views), "loss workspace too small");
+    ViewTable vt = make_view_table(cams_host, views);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_l1<float>(rgb, target, vt, dL_drgb, loss_dev, workspace, s)
+                                   : launch_l1<double>(rgb, target, vt, dL_drgb, loss_dev, workspace, s);
+    return hip_status(e, "gs_loss_l1");
+}
+
+gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *v, int64_t n,
+                       const gs_adam_hparams *h, int64_t *step_dev, double *scratch, void *stream)
+{
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(h && step_dev && scratch, "null pointer");
+    CHECK_ARG(n >= 0, "n < 0");
+    CHECK_ARG(n == 0 || (params && grad && m && v), "null pointer");
+    CHECK_ARG(h->batch_size >= 1, "batch_size must be >= 1");
+    CHECK_ARG(h->beta1 >= 0 && h->beta1 < 1 && h->beta2 >= 0 && h->beta2 < 1 && h->eps >= 0, "bad betas / eps");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_adam<float>(params, grad, m, v, n, h, step_dev, scratch, s)
+                                   : launch_adam<double>(params, grad, m, v, n, h, step_dev, scratch, s);
+    return hip_status(e, "gs_adam_step");
+}
+
+}  // extern "C"

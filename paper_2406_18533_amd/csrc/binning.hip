@@ -1,0 +1,526 @@
+// Z-buffer construction (appendix A.2): per-tile depth-ordered instance lists.
+//
+// The order is lexicographic in (global tile, FP32 depth bits, Gaussian
+// index). It is produced as a least-significant-digit-first radix sort whose
+// low digits (depth) are sorted BEFORE the instances are duplicated per tile:
+//   1. compact the (view, Gaussian) pairs that touch at least one tile,
+//      keeping (view-major, index) order;
+//   2. stable radix sort of those pairs by FP32 depth bits (4 passes);
+//   3. exclusive scan of their tile counts in that order -> instance offsets;
+//   4. emit (global tile id, Gaussian index) per tile of each pair's rectangle;
+//   5. stable radix sort of the instances by global tile id (2-3 passes).
+// Stability of step 5 keeps step 2's (depth, index) order inside each tile,
+// and a tile id already names its view. Only step 5 runs over the duplicated
+// instances, so the wide depth digits cost passes over the pairs, not over
+// the (typically 5-10x larger) instance set.
+#include "common.hpp"
+
+namespace gs {
+
+constexpr int SB = 256;          // threads per block in the scan / sort kernels
+constexpr int SITEMS = 16;       // items per thread
+constexpr int STILE = SB * SITEMS;
+
+__device__ __forceinline__ int64_t count_of(const int64_t *n_dev, int64_t n_max)
+{
+    if (!n_dev) return n_max;
+    int64_t n = *n_dev;
+    return n < n_max ? n : n_max;
+}
+
+template <typename U> __device__ __forceinline__ U wave_incl_scan(U x)
+{
+    int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        U y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan across the 256 threads of a block; `total` gets the sum.
+template <typename U> __device__ __forceinline__ U block_excl_scan(U x, U &total)
+{
+    __shared__ U s_w[SB / 64];
+    U inc = wave_incl_scan(x);
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    U off = 0;
+    total = 0;
+    for (int j = 0; j < SB / 64; j++) {
+        U t = s_w[j];
+        if (j < w) off += t;
+        total += t;
+    }
+    __syncthreads();
+    return off + inc - x;
+}
+
+// ---------------------------------------------------------------- generic scan
+template <typename U, typename Load>
+__global__ void __launch_bounds__(SB) scan_reduce_kernel(Load load, const int64_t *n_dev, int64_t n_max, U *partial)
+{
+    int64_t n = count_of(n_dev, n_max);
+    int64_t base = (int64_t)blockIdx.x * STILE;
+    U acc = 0;
+    for (int j = 0; j < SITEMS; j++) {
+        int64_t idx = base + (int64_t)j * SB + threadIdx.x;
+        if (idx < n) acc += load(idx);
+    }
+    U total;
+    block_excl_scan(acc, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+template <typename U>
+__global__ void __launch_bounds__(SB) scan_partials_kernel(U *partial, int64_t nb, int64_t *total_out)
+{
+    int64_t per = (nb + SB - 1) / SB;
+    int64_t b0 = threadIdx.x * per;
+    U acc = 0;
+    for (int64_t j = 0; j < per; j++)
+        if (b0 + j < nb) acc += partial[b0 + j];
+    U total;
+    U run = block_excl_scan(acc, total);
+    for (int64_t j = 0; j < per; j++)
+        if (b0 + j < nb) {
+            U t = partial[b0 + j];
+            partial[b0 + j] = run;
+            run += t;
+        }
+    if (threadIdx.x == 0 && total_out) *total_out = (int64_t)total;
+}
+
+template <typename U, typename Load, typename Store>
+__global__ void __launch_bounds__(SB) scan_down_kernel(Load load, Store store, const int64_t *n_dev, int64_t n_max,
+                                                       const U *partial)
+{
+    int64_t n = count_of(n_dev, n_max);
+    int64_t base = (int64_t)blockIdx.x * STILE;
+    if (base >= n) return;
+    int64_t t0 = base + (int64_t)threadIdx.x * SITEMS;
+    U vals[SITEMS];
+    U acc = 0;
+    for (int j = 0; j < SITEMS; j++) {
+        vals[j] = (t0 + j < n) ? load(t0 + j) : U(0);
+        acc += vals[j];
+    }
+    U total;
+    U run = block_excl_scan(acc, total) + partial[blockIdx.x];
+    for (int j = 0; j < SITEMS; j++) {
+        if (t0 + j < n) store(t0 + j, run, vals[j]);
+        run += vals[j];
+    }
+}
+
+template <typename U, typename Load, typename Store>
+static hipError_t device_scan(Load load, Store store, const int64_t *n_dev, int64_t n_max, U *partial,
+                              int64_t *total_out, hipStream_t s)
+{
+    int64_t nb = (n_max + STILE - 1) / STILE;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL((scan_reduce_kernel<U, Load>), dim3((unsigned)nb), dim3(SB), 0, s, load, n_dev, n_max, partial);
+    hipLaunchKernelGGL((scan_partials_kernel<U>), dim3(1), dim3(SB), 0, s, partial, nb, total_out);
+    hipLaunchKernelGGL((scan_down_kernel<U, Load, Store>), dim3((unsigned)nb), dim3(SB), 0, s, load, store, n_dev,
+                       n_max, (const U *)partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- functors
+template <typename T> struct FlagLoad {
+    const T *proj;
+    __device__ uint32_t operator()(int64_t f) const { return proj[f * REC + R_TILES] > T(0) ? 1u : 0u; }
+};
+
+__device__ __forceinline__ uint32_t depth_bits(float d) { return __float_as_uint(d); }
+
+template <typename T> struct CompactStore {
+    const T *proj;
+    uint32_t *keys, *vals;
+    __device__ void operator()(int64_t f, uint32_t pos, uint32_t flag) const
+    {
+        if (!flag) return;
+        keys[pos] = depth_bits((float)proj[f * REC + R_DEPTH]);
+        vals[pos] = (uint32_t)f;
+    }
+};
+
+template <typename T> struct CountLoad {
+    const T *proj;
+    const uint32_t *flat;
+    __device__ uint64_t operator()(int64_t j) const { return (uint64_t)proj[(int64_t)flat[j] * REC + R_TILES]; }
+};
+
+struct U64Store {
+    uint64_t *out;
+    __device__ void operator()(int64_t j, uint64_t pos, uint64_t) const { out[j] = pos; }
+};
+
+struct U32Load {
+    const uint32_t *p;
+    __device__ uint32_t operator()(int64_t j) const { return p[j]; }
+};
+
+struct U32Store {
+    uint32_t *out;
+    __device__ void operator()(int64_t j, uint32_t pos, uint32_t) const { out[j] = pos; }
+};
+
+// ---------------------------------------------------------------- radix sort
+// One stable LSD pass over 32-bit keys with 32-bit values, BITS-wide digits.
+// A block owns STILE consecutive elements; wave w owns the w-th quarter and
+// walks it in rounds of 64. Lanes with equal digits find each other with
+// BITS ballots; their order inside the wave and the wave's running per-digit
+// count give each element its rank among equal digits, in input order.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < BITS; b++) {
+        bool bit = (d >> b) & 1u;
+        uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+template <int BITS>
+__global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restrict__ kin, const int64_t *n_dev,
+                                                         int64_t n_max, int shift, uint32_t *__restrict__ hist,
+                                                         int64_t nbmax)
+{
+    constexpr int RADIX = 1 << BITS;
+    __shared__ uint32_t s_cnt[SB / 64][RADIX];
+    int64_t n = count_of(n_dev, n_max);
+    int64_t base = (int64_t)blockIdx.x * STILE;
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
+    __syncthreads();
+    if (base < n) {
+        uint64_t lt = (1ull << lane) - 1ull;
+        for (int it = 0; it < SITEMS; it++) {
+            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
+            bool valid = idx < n;
+            uint32_t k = valid ? kin[idx] : 0u;
+            uint32_t d = (k >> shift) & (RADIX - 1);
+            uint64_t peers = match_digit<BITS>(d, valid);
+            if (valid && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+        }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < RADIX; d += SB) {
+        uint32_t c = 0;
+        for (int j = 0; j < SB / 64; j++) c += s_cnt[j][d];
+        hist[(int64_t)d * nbmax + blockIdx.x] = c;
+    }
+}
+
+template <int BITS>
+__global__ void __launch_bounds__(SB) radix_scatter_kernel(const uint32_t *__restrict__ kin,
+                                                           const uint32_t *__restrict__ vin,
+                                                           uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                           const int64_t *n_dev, int64_t n_max, int shift,
+                                                           const uint32_t *__restrict__ offs, int64_t nbmax)
+{
+    constexpr int RADIX = 1 << BITS;
+    constexpr int PER = (RADIX + SB - 1) / SB;
+    __shared__ uint32_t s_key[STILE];
+    __shared__ uint32_t s_val[STILE];
+    __shared__ uint32_t s_cnt[SB / 64][RADIX];
+    __shared__ uint32_t s_start[RADIX];
+    __shared__ uint32_t s_goff[RADIX];
+    int64_t n = count_of(n_dev, n_max);
+    int64_t base = (int64_t)blockIdx.x * STILE;
+    if (base >= n) return;
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
+    for (int d = threadIdx.x; d < RADIX; d += SB) s_goff[d] = offs[(int64_t)d * nbmax + blockIdx.x];
+    __syncthreads();
+    uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
+    uint64_t lt = (1ull << lane) - 1ull;
+    for (int it = 0; it < SITEMS; it++) {
+        int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
+        bool valid = idx < n;
+        uint32_t k = valid ? kin[idx] : 0u;
+        uint32_t v = valid ? vin[idx] : 0u;
+        uint32_t d = (k >> shift) & (RADIX - 1);
+        uint64_t peers = match_digit<BITS>(d, valid);
+        uint32_t before = s_cnt[w][d];
+        if (valid && (peers & lt) == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
+        rank[it] = before + (uint32_t)__popcll(peers & lt);
+        key[it] = k;
+        val[it] = v;
+    }
+    __syncthreads();
+    // wave prefixes per digit, then block-local digit starts
+    uint32_t tot[PER];
+    uint32_t mysum = 0;
+    for (int j = 0; j < PER; j++) {
+        int d = threadIdx.x * PER + j;
+        uint32_t t = 0;
+        if (d < RADIX) {
+            uint32_t run = 0;
+            for (int q = 0; q < SB / 64; q++) {
+                uint32_t c = s_cnt[q][d];
+                s_cnt[q][d] = run;
+                run += c;
+            }
+            t = run;
+        }
+        tot[j] = t;
+        mysum += t;
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(mysum, total);
+    for (int j = 0; j < PER; j++) {
+        int d = threadIdx.x * PER + j;
+        if (d < RADIX) s_start[d] = run;
+        run += tot[j];
+    }
+    __syncthreads();
+    for (int it = 0; it < SITEMS; it++) {
+        int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
+        if (idx < n) {
+            uint32_t d = (key[it] >> shift) & (RADIX - 1);
+            uint32_t pos = s_start[d] + s_cnt[w][d] + rank[it];
+            s_key[pos] = key[it];
+            s_val[pos] = val[it];
+        }
+    }
+    __syncthreads();
+    int64_t cnt = n - base < STILE ? n - base : STILE;
+    for (int p = threadIdx.x; p < cnt; p += SB) {
+        uint32_t k = s_key[p];
+        uint32_t d = (k >> shift) & (RADIX - 1);
+        int64_t g = (int64_t)s_goff[d] + (p - (int64_t)s_start[d]);
+        kout[g] = k;
+        vout[g] = s_val[p];
+    }
+}
+
+template <int BITS>
+static void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *ko, uint32_t *vo, const int64_t *n_dev,
+                       int64_t n_max, int shift, uint32_t *hist, uint32_t *partial, int64_t nbmax, hipStream_t s)
+{
+    int64_t hn = (int64_t)(1 << BITS) * nbmax;
+    hipLaunchKernelGGL(radix_count_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, n_dev, n_max, shift, hist,
+                       nbmax);
+    (void)device_scan<uint32_t>(U32Load{hist}, U32Store{hist}, nullptr, hn, partial, nullptr, s);
+    hipLaunchKernelGGL(radix_scatter_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, vin, ko, vo, n_dev,
+                       n_max, shift, (const uint32_t *)hist, nbmax);
+}
+
+// Sorts (keys, vals) over their lowest `bits` key bits; the result lands back
+// in keys/vals (an even number of passes through the alternate buffers). The
+// element count is min(*n_dev, n_max).
+static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uint32_t *valt, const int64_t *n_dev,
+                             int64_t n_max, int bits, uint32_t *hist, uint32_t *partial, hipStream_t s)
+{
+    int64_t nbmax = (n_max + STILE - 1) / STILE;
+    if (nbmax == 0) return hipSuccess;
+    int passes = (bits + 8) / 9;
+    if (passes & 1) passes++;
+    int digit = (bits + passes - 1) / passes;
+    uint32_t *kin = keys, *vin = vals, *ko = kalt, *vo = valt;
+    for (int p = 0; p < passes; p++) {
+        int shift = p * digit;
+        switch (digit) {
+        case 1: radix_pass<1>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 2: radix_pass<2>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 3: radix_pass<3>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 4: radix_pass<4>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 5: radix_pass<5>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 6: radix_pass<6>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 7: radix_pass<7>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 8: radix_pass<8>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        default: radix_pass<9>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        }
+        uint32_t *tk = kin, *tv = vin;
+        kin = ko; vin = vo; ko = tk; vo = tv;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- emit and ranges
+template <typename T>
+__global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, int64_t n, ViewTable vt,
+                                                   const uint32_t *__restrict__ flat, const uint64_t *__restrict__ off,
+                                                   const int64_t *m_dev, int64_t m_max, uint32_t *__restrict__ tile_out,
+                                                   uint32_t *__restrict__ id_out, int64_t capacity)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t m = count_of(m_dev, m_max);
+    if (j >= m) return;
+    uint32_t f = flat[j];
+    uint32_t v = f / (uint32_t)n;
+    uint32_t i = f - v * (uint32_t)n;
+    const T *rec = proj + (int64_t)f * REC;
+    TileRect r;
+    if (!tile_rect((float)rec[R_U], (float)rec[R_V], (float)rec[R_RADIUS], vt.width[v], vt.height[v], r)) return;
+    uint64_t o = off[j];
+    uint32_t tb = (uint32_t)vt.tile_base[v];
+    uint32_t tx = (uint32_t)vt.tiles_x[v];
+    for (int ty = r.y0; ty <= r.y1; ty++)
+        for (int tx2 = r.x0; tx2 <= r.x1; tx2++) {
+            if (o < (uint64_t)capacity) {
+                tile_out[o] = tb + (uint32_t)ty * tx + (uint32_t)tx2;
+                id_out[o] = i;
+            }
+            o++;
+        }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) p[j] = value;
+}
+
+__global__ void ranges_kernel(const uint32_t *__restrict__ tiles, const int64_t *k_dev, int64_t cap,
+                              int64_t n_tiles, uint32_t *__restrict__ ranges)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t K = count_of(k_dev, cap);
+    if (k >= K) return;
+    uint32_t t = tiles[k];
+    if (t >= (uint32_t)n_tiles) return;
+    if (k == 0 || tiles[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
+    if (k == K - 1 || tiles[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+}
+
+__global__ void overflow_kernel(const int64_t *k_dev, int64_t cap, int32_t *overflow)
+{
+    *overflow = *k_dev > cap ? 1 : 0;
+}
+
+template <typename T>
+__global__ void keys64_kernel(const T *__restrict__ proj, int64_t n, ViewTable vt, const uint32_t *tiles,
+                              const uint32_t *ids, const int64_t *k_dev, int64_t cap, uint64_t *out)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count_of(k_dev, cap)) return;
+    uint32_t t = tiles[k];
+    int v = view_of_tile(vt, (int32_t)t);
+    float d = (float)proj[((int64_t)v * n + ids[k]) * REC + R_DEPTH];
+    out[k] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(d);
+}
+
+// ---------------------------------------------------------------- workspace
+struct BinWS {
+    uint32_t *k1, *v1, *k1b, *v1b;   // [VN] depth keys / flat indices and alternates
+    uint64_t *off;                   // [VN] instance offsets
+    uint32_t *talt, *ialt;           // [cap] alternate tile keys / ids
+    uint32_t *hist;                  // [512 * nbmax]
+    uint64_t *partial;               // scan partials
+    int64_t *m_dev;                  // visible pair count
+};
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws)
+{
+    int64_t big = vn > cap ? vn : cap;
+    int64_t nbmax = (big + STILE - 1) / STILE + 1;
+    int64_t hist_n = 512 * nbmax;
+    int64_t part_n = (hist_n + STILE - 1) / STILE + (big + STILE - 1) / STILE + 8;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return base ? (void *)(base + at) : nullptr; };
+    BinWS w;
+    w.k1 = (uint32_t *)take(4 * vn);
+    w.v1 = (uint32_t *)take(4 * vn);
+    w.k1b = (uint32_t *)take(4 * vn);
+    w.v1b = (uint32_t *)take(4 * vn);
+    w.off = (uint64_t *)take(8 * vn);
+    w.talt = (uint32_t *)take(4 * cap);
+    w.ialt = (uint32_t *)take(4 * cap);
+    w.hist = (uint32_t *)take(4 * hist_n);
+    w.partial = (uint64_t *)take(8 * part_n);
+    w.m_dev = (int64_t *)take(64);
+    if (ws) *ws = w;
+    return o;
+}
+
+template <typename T>
+hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs_bins *b, bool check, int *capacity_err,
+                           hipStream_t s)
+{
+    const T *proj = (const T *)projv;
+    int64_t vn = (int64_t)vt.nviews * n;
+    int64_t cap = b->capacity;
+    BinWS ws;
+    bin_ws_layout(vn, cap, (char *)b->workspace, &ws);
+    hipError_t e;
+    *capacity_err = 0;
+    int64_t T_all = vt.total_tiles;
+    // ranges start empty
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((2 * T_all + 255) / 256)), dim3(256), 0, s, b->ranges,
+                       2 * T_all, 0u);
+    // 1. compaction of pairs that touch a tile
+    e = device_scan<uint32_t>(FlagLoad<T>{proj}, CompactStore<T>{proj, ws.k1, ws.v1}, nullptr, vn,
+                              (uint32_t *)ws.partial, ws.m_dev, s);
+    if (e != hipSuccess) return e;
+    // 2. stable sort by FP32 depth bits (positive depths: 31 significant bits)
+    e = radix_sort(ws.k1, ws.v1, ws.k1b, ws.v1b, ws.m_dev, vn, 32, ws.hist, (uint32_t *)ws.partial, s);
+    if (e != hipSuccess) return e;
+    // 3. instance offsets in depth order
+    e = device_scan<uint64_t>(CountLoad<T>{proj, ws.v1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap, b->overflow);
+    if (check) {
+        int64_t K = 0;
+        e = hipMemcpyAsync(&K, b->n_instances, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        if (K > cap) {
+            *capacity_err = 1;
+            return hipSuccess;
+        }
+    }
+    // 4. emission
+    if (vn > 0)
+        hipLaunchKernelGGL(emit_kernel<T>, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj, n, vt,
+                           (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
+                           b->tile_keys, b->ids, cap);
+    // 5. stable sort by global tile id
+    int bits = 1;
+    while ((int64_t(1) << bits) < T_all) bits++;
+    e = radix_sort(b->tile_keys, b->ids, ws.talt, ws.ialt, b->n_instances, cap, bits, ws.hist, (uint32_t *)ws.partial,
+                   s);
+    if (e != hipSuccess) return e;
+    if (cap > 0)
+        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s,
+                           (const uint32_t *)b->tile_keys, (const int64_t *)b->n_instances, cap, T_all, b->ranges);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_keys64(const void *proj, int64_t n, const ViewTable &vt, const gs_bins *b, uint64_t *out,
+                         hipStream_t s)
+{
+    int64_t cap = b->capacity;
+    if (cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(keys64_kernel<T>, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, (const T *)proj, n, vt,
+                       (const uint32_t *)b->tile_keys, (const uint32_t *)b->ids, (const int64_t *)b->n_instances, cap,
+                       out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_bin_sort<float>(const void *, int64_t, const ViewTable &, gs_bins *, bool, int *, hipStream_t);
+template hipError_t launch_bin_sort<double>(const void *, int64_t, const ViewTable &, gs_bins *, bool, int *,
+                                            hipStream_t);
+template hipError_t launch_keys64<float>(const void *, int64_t, const ViewTable &, const gs_bins *, uint64_t *,
+                                         hipStream_t);
+template hipError_t launch_keys64<double>(const void *, int64_t, const ViewTable &, const gs_bins *, uint64_t *,
+                                          hipStream_t);
+
+// Exposed for the scheduler (cumulative tile cost).
+hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace gs

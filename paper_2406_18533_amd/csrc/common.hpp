@@ -1,0 +1,146 @@
+// Device-side building blocks shared by the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs.h"
+
+namespace gs {
+
+constexpr int TILE = GS_TILE;
+constexpr int MAXV = GS_MAX_VIEWS;
+constexpr int REC = GS_REC;
+
+// Record slots of a projected (view, Gaussian) entry.
+enum : int { R_U = 0, R_V = 1, R_A = 2, R_B = 3, R_C = 4, R_OPAC = 5, R_RGB = 6, R_RADIUS = 9, R_DEPTH = 10, R_TILES = 11 };
+// Slots of a projected-gradient entry.
+enum : int { D_U = 0, D_V = 1, D_A = 2, D_B = 3, D_C = 4, D_OPAC = 5, D_RGB = 6 };
+
+// Per-view image geometry, passed by value as a kernel argument.
+struct ViewTable {
+    int32_t nviews;
+    int32_t total_tiles;
+    int32_t tile_base[MAXV + 1];
+    int32_t tiles_x[MAXV];
+    int32_t width[MAXV];
+    int32_t height[MAXV];
+    int64_t pix_base[MAXV + 1];
+};
+
+ViewTable make_view_table(const gs_camera *cams, int32_t views);
+
+// Persistent-scheduler state inside the caller's workspace.
+struct SchedState {
+    int32_t *cursor;   // [queues] next tile of each queue
+    int32_t *dp;       // [queues + 1] division points
+    int32_t queues;    // multiple of 8
+};
+
+// Resolved launch shape of the render kernels.
+struct LaunchShape {
+    int mode, px, chunk, workers;
+    SchedState S;
+};
+
+struct BinWS;
+
+__device__ __forceinline__ int view_of_tile(const ViewTable &vt, int32_t g)
+{
+    int v = 0;
+    while (v + 1 < vt.nviews && g >= vt.tile_base[v + 1]) v++;
+    return v;
+}
+
+// Footprint rectangle in tiles, decided in FP32: pixels whose centre
+// x + 1/2 lies in [u - r, u + r] (and likewise y), clipped to the image.
+struct TileRect { int x0, x1, y0, y1; };
+
+__device__ __forceinline__ bool tile_rect(float u, float v, float r, int W, int H, TileRect &t)
+{
+    if (!(r > 0.0f)) return false;
+    float xlo = ceilf(__fsub_rn(__fsub_rn(u, r), 0.5f));
+    float xhi = floorf(__fsub_rn(__fadd_rn(u, r), 0.5f));
+    float ylo = ceilf(__fsub_rn(__fsub_rn(v, r), 0.5f));
+    float yhi = floorf(__fsub_rn(__fadd_rn(v, r), 0.5f));
+    xlo = fmaxf(xlo, 0.0f);
+    ylo = fmaxf(ylo, 0.0f);
+    xhi = fminf(xhi, (float)(W - 1));
+    yhi = fminf(yhi, (float)(H - 1));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) return false;
+    t.x0 = (int)xlo / TILE;
+    t.x1 = (int)xhi / TILE;
+    t.y0 = (int)ylo / TILE;
+    t.y1 = (int)yhi / TILE;
+    return true;
+}
+
+// Rasterizer constants (alpha clamp, skip threshold, transmittance stop).
+template <typename T> struct K;
+template <> struct K<float> {
+    static constexpr float alpha_max = 0.99f;
+    static constexpr float alpha_min = 1.0f / 255.0f;
+    static constexpr float t_min = 1e-4f;
+};
+template <> struct K<double> {
+    static constexpr double alpha_max = 0.99;
+    static constexpr double alpha_min = 1.0 / 255.0;
+    static constexpr double t_min = 1e-4;
+};
+
+__device__ __forceinline__ float exp_t(float x) { return __expf(x); }
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+
+// One (pixel, Gaussian) pair: circle test, Gaussian falloff, alpha with
+// clamp and skip. Returns false if the Gaussian does not touch the pixel.
+// The forward and backward kernels both call this, so their decisions agree
+// bit for bit.
+template <typename T>
+__device__ __forceinline__ bool eval_alpha(T pxc, T pyc, T u, T v, T r2, T a, T b, T c, T o,
+                                           T &dx, T &dy, T &G, T &og, T &alpha)
+{
+    dx = pxc - u;
+    dy = pyc - v;
+    T d2 = dx * dx + dy * dy;
+    if (d2 > r2) return false;
+    T power = T(-0.5) * (a * dx * dx + c * dy * dy) - b * dx * dy;
+    if (power > T(0)) return false;
+    G = exp_t(power);
+    og = o * G;
+    alpha = og < K<T>::alpha_max ? og : K<T>::alpha_max;
+    return !(alpha < K<T>::alpha_min);
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <int CTRL, int ROW_MASK> __device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over the 64 lanes of a wavefront; the result is valid in every lane.
+__device__ __forceinline__ float wave_sum(float x)
+{
+    // Row-local inclusive scan (rows of 16 lanes), then carry rows into
+    // later rows with the GFX9 row broadcasts; lane 63 ends with the total.
+    x += dpp_move<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_move<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_move<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_move<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_move<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_move<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace gs

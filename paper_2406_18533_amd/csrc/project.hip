@@ -1,0 +1,442 @@
+// Gaussian transformation forward and backward (paper section 2.1 step 1;
+// appendix A.3: both are Gaussian-wise). One thread per Gaussian, fused over
+// all views of the batch: the parameters are read once (planar rows, so a
+// wavefront reads 64 consecutive floats per row) and every view's record is
+// written by the same thread.
+#include "common.hpp"
+
+namespace gs {
+
+template <typename T> struct Camera {
+    T R[9], t[3], cen[3];
+    T fx, fy, cx, cy, znear, limx, limy;
+    int W, H;
+};
+
+template <typename T> __device__ __forceinline__ Camera<T> load_camera(const gs_camera *c)
+{
+    Camera<T> k;
+    for (int j = 0; j < 9; j++) k.R[j] = (T)c->R[j];
+    for (int j = 0; j < 3; j++) k.t[j] = (T)c->t[j];
+    for (int j = 0; j < 3; j++)
+        k.cen[j] = (T)(-(c->R[j] * c->t[0] + c->R[3 + j] * c->t[1] + c->R[6 + j] * c->t[2]));
+    k.fx = (T)c->fx; k.fy = (T)c->fy; k.cx = (T)c->cx; k.cy = (T)c->cy;
+    k.znear = (T)c->znear;
+    // Guard band of the Jacobian: 1.3x the tangent of the half field of view.
+    k.limx = (T)(1.3 * (0.5 * c->width / c->fx));
+    k.limy = (T)(1.3 * (0.5 * c->height / c->fy));
+    k.W = c->width;
+    k.H = c->height;
+    return k;
+}
+
+// View-independent part: scale, rotation, 3D covariance, opacity.
+template <typename T> struct Shape {
+    T s[3], q[4], qn, Rq[9], Sig[6];  // Sig: 00 01 02 11 12 22
+    T opac;
+    bool ok;
+};
+
+template <typename T> __device__ __forceinline__ void quat_matrix(const T q[4], T R[9])
+{
+    T w = q[0], x = q[1], y = q[2], z = q[3];
+    R[0] = T(1) - T(2) * (y * y + z * z); R[1] = T(2) * (x * y - w * z); R[2] = T(2) * (x * z + w * y);
+    R[3] = T(2) * (x * y + w * z); R[4] = T(1) - T(2) * (x * x + z * z); R[5] = T(2) * (y * z - w * x);
+    R[6] = T(2) * (x * z - w * y); R[7] = T(2) * (y * z + w * x); R[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+template <typename T> __device__ __forceinline__ bool finite(T x) { return isfinite(x); }
+
+template <typename T>
+__device__ __forceinline__ void make_shape(const T *P, int64_t n, int64_t i, Shape<T> &S)
+{
+    T ls[3], qr[4];
+    for (int j = 0; j < 3; j++) ls[j] = P[(3 + j) * n + i];
+    for (int j = 0; j < 4; j++) qr[j] = P[(6 + j) * n + i];
+    T logit = P[10 * n + i];
+    S.ok = finite(ls[0]) && finite(ls[1]) && finite(ls[2]) && finite(qr[0]) && finite(qr[1]) && finite(qr[2]) &&
+           finite(qr[3]) && finite(logit);
+    for (int j = 0; j < 3; j++) S.s[j] = exp(ls[j]);
+    S.qn = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+    S.ok = S.ok && S.qn > T(0);
+    T iq = T(1) / S.qn;
+    for (int j = 0; j < 4; j++) S.q[j] = qr[j] * iq;
+    quat_matrix(S.q, S.Rq);
+    T M[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
+    const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+    for (int e = 0; e < 6; e++) {
+        int r = rr[e], c = cc[e];
+        S.Sig[e] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+    }
+    S.opac = T(1) / (T(1) + exp(-logit));
+}
+
+template <typename T> __device__ __forceinline__ T sig_at(const T Sig[6], int r, int c)
+{
+    // full symmetric 3x3 from the 6 stored entries
+    const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    return Sig[idx[3 * r + c]];
+}
+
+// Per-view geometry of one Gaussian.
+template <typename T> struct Geo {
+    T y[3], iz, xi, eta;
+    bool xi_cl, eta_cl;
+    T J00, J02, J11, J12;
+    T Tm[6];
+    T A, B, C, det;
+    T u, v, conic[3], radius;
+    bool visible;   // in front of znear, finite
+    int tiles;
+    TileRect rect;
+};
+
+template <typename T>
+__device__ __forceinline__ void make_geo(const T x[3], const Shape<T> &S, const Camera<T> &k, Geo<T> &g)
+{
+    g.visible = false;
+    g.tiles = 0;
+    for (int r = 0; r < 3; r++) g.y[r] = k.R[3 * r] * x[0] + k.R[3 * r + 1] * x[1] + k.R[3 * r + 2] * x[2] + k.t[r];
+    T z = g.y[2];
+    if (!S.ok || !(z > k.znear)) return;
+    g.iz = T(1) / z;
+    g.u = k.fx * g.y[0] * g.iz + k.cx;
+    g.v = k.fy * g.y[1] * g.iz + k.cy;
+    T xr = g.y[0] * g.iz, yr = g.y[1] * g.iz;
+    g.xi_cl = xr < -k.limx || xr > k.limx;
+    g.eta_cl = yr < -k.limy || yr > k.limy;
+    g.xi = fmin(fmax(xr, -k.limx), k.limx);
+    g.eta = fmin(fmax(yr, -k.limy), k.limy);
+    g.J00 = k.fx * g.iz;
+    g.J02 = -k.fx * g.xi * g.iz;
+    g.J11 = k.fy * g.iz;
+    g.J12 = -k.fy * g.eta * g.iz;
+    for (int c = 0; c < 3; c++) {
+        g.Tm[c] = g.J00 * k.R[c] + g.J02 * k.R[6 + c];
+        g.Tm[3 + c] = g.J11 * k.R[3 + c] + g.J12 * k.R[6 + c];
+    }
+    // S' = Tm Sig Tm^T
+    T TS[6];
+    for (int r = 0; r < 2; r++)
+        for (int c = 0; c < 3; c++)
+            TS[3 * r + c] = g.Tm[3 * r] * sig_at(S.Sig, 0, c) + g.Tm[3 * r + 1] * sig_at(S.Sig, 1, c) +
+                            g.Tm[3 * r + 2] * sig_at(S.Sig, 2, c);
+    T s00 = TS[0] * g.Tm[0] + TS[1] * g.Tm[1] + TS[2] * g.Tm[2];
+    T s01 = TS[0] * g.Tm[3] + TS[1] * g.Tm[4] + TS[2] * g.Tm[5];
+    T s11 = TS[3] * g.Tm[3] + TS[4] * g.Tm[4] + TS[5] * g.Tm[5];
+    g.A = s00 + T(0.3);
+    g.B = s01;
+    g.C = s11 + T(0.3);
+    g.det = g.A * g.C - g.B * g.B;
+    if (!(g.det > T(0)) || !finite(g.det)) return;
+    T id = T(1) / g.det;
+    g.conic[0] = g.C * id;
+    g.conic[1] = -g.B * id;
+    g.conic[2] = g.A * id;
+    T mid = T(0.5) * (g.A + g.C);
+    T disc = mid * mid - g.det;
+    T lmax = mid + sqrt(disc > T(0) ? disc : T(0));
+    g.radius = ceil(T(3) * sqrt(lmax));
+    if (!finite(g.radius) || !finite(g.u) || !finite(g.v)) return;
+    g.visible = true;
+    if (tile_rect((float)g.u, (float)g.v, (float)g.radius, k.W, k.H, g.rect))
+        g.tiles = (g.rect.x1 - g.rect.x0 + 1) * (g.rect.y1 - g.rect.y0 + 1);
+}
+
+// Real orthonormal spherical harmonics of degree <= 3 (Condon-Shortley phase)
+// as polynomials in the unit direction; coefficients from
+// K_lm = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) and the Legendre derivatives.
+template <typename T> struct ShK {
+    static constexpr double PI = 3.14159265358979323846;
+};
+#define GS_SQRT(v) ((T)__builtin_sqrt(v))
+
+template <typename T> __device__ __forceinline__ void sh_basis(T x, T y, T z, T Y[16])
+{
+    constexpr double PI = 3.14159265358979323846;
+    const T c0 = GS_SQRT(1.0 / (4.0 * PI)), c1 = GS_SQRT(3.0 / (4.0 * PI));
+    const T c2a = GS_SQRT(15.0 / (4.0 * PI)), c2b = GS_SQRT(5.0 / (16.0 * PI)), c2c = GS_SQRT(15.0 / (16.0 * PI));
+    const T c3a = GS_SQRT(35.0 / (32.0 * PI)), c3b = GS_SQRT(105.0 / (4.0 * PI)), c3c = GS_SQRT(21.0 / (32.0 * PI));
+    const T c3d = GS_SQRT(7.0 / (16.0 * PI)), c3e = GS_SQRT(105.0 / (16.0 * PI));
+    T xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = c0;
+    Y[1] = -c1 * y; Y[2] = c1 * z; Y[3] = -c1 * x;
+    Y[4] = c2a * x * y; Y[5] = -c2a * y * z; Y[6] = c2b * (T(3) * zz - T(1)); Y[7] = -c2a * x * z;
+    Y[8] = c2c * (xx - yy);
+    Y[9] = -c3a * y * (T(3) * xx - yy); Y[10] = c3b * x * y * z; Y[11] = -c3c * y * (T(5) * zz - T(1));
+    Y[12] = c3d * z * (T(5) * zz - T(3)); Y[13] = -c3c * x * (T(5) * zz - T(1)); Y[14] = c3e * z * (xx - yy);
+    Y[15] = -c3a * x * (xx - T(3) * yy);
+}
+
+// sum_k w_k grad Y_k of the polynomial forms above (before projection onto
+// the sphere's tangent plane).
+template <typename T> __device__ __forceinline__ void sh_grad(T x, T y, T z, const T w[16], T g[3])
+{
+    constexpr double PI = 3.14159265358979323846;
+    const T c1 = GS_SQRT(3.0 / (4.0 * PI));
+    const T c2a = GS_SQRT(15.0 / (4.0 * PI)), c2b = GS_SQRT(5.0 / (16.0 * PI)), c2c = GS_SQRT(15.0 / (16.0 * PI));
+    const T c3a = GS_SQRT(35.0 / (32.0 * PI)), c3b = GS_SQRT(105.0 / (4.0 * PI)), c3c = GS_SQRT(21.0 / (32.0 * PI));
+    const T c3d = GS_SQRT(7.0 / (16.0 * PI)), c3e = GS_SQRT(105.0 / (16.0 * PI));
+    T xx = x * x, yy = y * y, zz = z * z;
+    T gx = T(0), gy = T(0), gz = T(0);
+    gy += -c1 * w[1];
+    gz += c1 * w[2];
+    gx += -c1 * w[3];
+    gx += c2a * y * w[4]; gy += c2a * x * w[4];
+    gy += -c2a * z * w[5]; gz += -c2a * y * w[5];
+    gz += c2b * T(6) * z * w[6];
+    gx += -c2a * z * w[7]; gz += -c2a * x * w[7];
+    gx += c2c * T(2) * x * w[8]; gy += -c2c * T(2) * y * w[8];
+    gx += -c3a * T(6) * x * y * w[9]; gy += -c3a * (T(3) * xx - T(3) * yy) * w[9];
+    gx += c3b * y * z * w[10]; gy += c3b * x * z * w[10]; gz += c3b * x * y * w[10];
+    gy += -c3c * (T(5) * zz - T(1)) * w[11]; gz += -c3c * T(10) * y * z * w[11];
+    gz += c3d * (T(15) * zz - T(3)) * w[12];
+    gx += -c3c * (T(5) * zz - T(1)) * w[13]; gz += -c3c * T(10) * x * z * w[13];
+    gx += c3e * T(2) * x * z * w[14]; gy += -c3e * T(2) * y * z * w[14]; gz += c3e * (xx - yy) * w[14];
+    gx += -c3a * (T(3) * xx - T(3) * yy) * w[15]; gy += c3a * T(6) * x * y * w[15];
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+#undef GS_SQRT
+
+template <typename T> using V4 = typename Vec4<T>::type;
+
+template <typename T>
+__global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ P, int64_t n,
+                                                          const gs_camera *__restrict__ cams, int32_t views,
+                                                          T *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    bool xok = finite(x[0]) && finite(x[1]) && finite(x[2]);
+    // Cheap pre-test on the mean alone: in front of some camera's near plane?
+    bool any_front = false;
+    for (int v = 0; v < views && xok; v++) {
+        const gs_camera *c = cams + v;
+        T z = (T)c->R[6] * x[0] + (T)c->R[7] * x[1] + (T)c->R[8] * x[2] + (T)c->t[2];
+        any_front |= z > (T)c->znear;
+    }
+    Shape<T> S;
+    if (any_front) make_shape(P, n, i, S);
+    else S.ok = false;
+    S.ok = S.ok && xok;
+    uint64_t need_colour = 0;
+    for (int v = 0; v < views; v++) {
+        V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
+        Camera<T> k = load_camera<T>(cams + v);
+        Geo<T> g;
+        make_geo(x, S, k, g);
+        if (!g.visible) {
+            rec[2] = V4<T>{T(0), T(0), T(0), T(0)};
+            continue;
+        }
+        if (g.tiles > 0) {
+            need_colour |= 1ull << v;
+            continue;
+        }
+        rec[0] = V4<T>{g.u, g.v, g.conic[0], g.conic[1]};
+        rec[1] = V4<T>{g.conic[2], S.opac, T(0), T(0)};
+        rec[2] = V4<T>{T(0), g.radius, g.y[2], T(0)};
+    }
+    if (!need_colour) return;
+    T sh[48];
+    for (int j = 0; j < 48; j++) sh[j] = P[(11 + j) * n + i];
+    for (int v = 0; v < views; v++) {
+        if (!((need_colour >> v) & 1ull)) continue;
+        V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
+        Camera<T> k = load_camera<T>(cams + v);
+        Geo<T> g;
+        make_geo(x, S, k, g);
+        T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
+        T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        T Y[16];
+        sh_basis(d[0] * idn, d[1] * idn, d[2] * idn, Y);
+        T rgb[3];
+        for (int ch = 0; ch < 3; ch++) {
+            T acc = T(0);
+            for (int k2 = 0; k2 < 16; k2++) acc += sh[3 * k2 + ch] * Y[k2];
+            acc += T(0.5);
+            rgb[ch] = acc > T(0) ? acc : T(0);
+        }
+        rec[0] = V4<T>{g.u, g.v, g.conic[0], g.conic[1]};
+        rec[1] = V4<T>{g.conic[2], S.opac, rgb[0], rgb[1]};
+        rec[2] = V4<T>{rgb[2], g.radius, g.y[2], (T)g.tiles};
+    }
+}
+
+// Transformation backward: chain rule from the per-view record gradients
+// d(u, v, a, b, c, opacity, rgb) to the 59 parameters; sums over views in
+// registers and adds each parameter gradient once (no atomics).
+template <typename T>
+__global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ P, int64_t n,
+                                                          const gs_camera *__restrict__ cams, int32_t views,
+                                                          const T *__restrict__ proj, const T *__restrict__ dproj,
+                                                          T *__restrict__ grad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t vis = 0;
+    for (int v = 0; v < views; v++)
+        if (proj[((int64_t)v * n + i) * REC + R_TILES] > T(0)) vis |= 1ull << v;
+    if (!vis) return;
+    T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    Shape<T> S;
+    make_shape(P, n, i, S);
+    T gmean[3] = {0, 0, 0}, gS[6] = {0, 0, 0, 0, 0, 0}, gop = T(0);
+    T gsh[48];
+    for (int j = 0; j < 48; j++) gsh[j] = T(0);
+    for (int v = 0; v < views; v++) {
+        if (!((vis >> v) & 1ull)) continue;
+        const V4<T> *dr = reinterpret_cast<const V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
+        V4<T> d0 = dr[0], d1 = dr[1], d2 = dr[2];
+        T du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x, dop = d1.y;
+        T drgb[3] = {d1.z, d1.w, d2.x};
+        Camera<T> k = load_camera<T>(cams + v);
+        Geo<T> g;
+        make_geo(x, S, k, g);
+        T z = g.y[2], iz = g.iz, iz2 = iz * iz;
+        T dy[3];
+        dy[0] = du * k.fx * iz;
+        dy[1] = dv * k.fy * iz;
+        dy[2] = -(du * k.fx * g.y[0] + dv * k.fy * g.y[1]) * iz2;
+        // conic = (C, -B, A) / det
+        T id = T(1) / g.det, id2 = id * id;
+        T dA = -da * g.C * g.C * id2 + db * g.B * g.C * id2 - dc * g.B * g.B * id2;
+        T dB = T(2) * da * g.B * g.C * id2 + db * (-id - T(2) * g.B * g.B * id2) + T(2) * dc * g.A * g.B * id2;
+        T dC = -da * g.B * g.B * id2 + db * g.A * g.B * id2 - dc * g.A * g.A * id2;
+        // S'00 = t0 Sig t0^T, S'01 = t0 Sig t1^T, S'11 = t1 Sig t1^T (t0, t1 rows of Tm)
+        T SigT0[3], SigT1[3];
+        for (int m = 0; m < 3; m++) {
+            SigT0[m] = sig_at(S.Sig, m, 0) * g.Tm[0] + sig_at(S.Sig, m, 1) * g.Tm[1] + sig_at(S.Sig, m, 2) * g.Tm[2];
+            SigT1[m] = sig_at(S.Sig, m, 0) * g.Tm[3] + sig_at(S.Sig, m, 1) * g.Tm[4] + sig_at(S.Sig, m, 2) * g.Tm[5];
+        }
+        T dT0[3], dT1[3];
+        for (int m = 0; m < 3; m++) {
+            dT0[m] = T(2) * dA * SigT0[m] + dB * SigT1[m];
+            dT1[m] = T(2) * dC * SigT1[m] + dB * SigT0[m];
+        }
+        // dSig (symmetric, stored as the 6 unique entries with off-diagonals summed)
+        {
+            const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+            for (int e = 0; e < 6; e++) {
+                int m = rr[e], q = cc[e];
+                T val = dA * g.Tm[m] * g.Tm[q] + dC * g.Tm[3 + m] * g.Tm[3 + q] +
+                        T(0.5) * dB * (g.Tm[m] * g.Tm[3 + q] + g.Tm[q] * g.Tm[3 + m]);
+                gS[e] += (m == q) ? val : T(2) * val;
+            }
+        }
+        // Tm = J R
+        T dJ00 = dT0[0] * k.R[0] + dT0[1] * k.R[1] + dT0[2] * k.R[2];
+        T dJ02 = dT0[0] * k.R[6] + dT0[1] * k.R[7] + dT0[2] * k.R[8];
+        T dJ11 = dT1[0] * k.R[3] + dT1[1] * k.R[4] + dT1[2] * k.R[5];
+        T dJ12 = dT1[0] * k.R[6] + dT1[1] * k.R[7] + dT1[2] * k.R[8];
+        dy[2] += -(dJ00 * k.fx + dJ11 * k.fy) * iz2 + (dJ02 * k.fx * g.xi + dJ12 * k.fy * g.eta) * iz2;
+        T dxi = -dJ02 * k.fx * iz, deta = -dJ12 * k.fy * iz;
+        if (!g.xi_cl) { dy[0] += dxi * iz; dy[2] -= dxi * g.y[0] * iz2; }
+        if (!g.eta_cl) { dy[1] += deta * iz; dy[2] -= deta * g.y[1] * iz2; }
+        (void)z;
+        for (int c = 0; c < 3; c++) gmean[c] += k.R[c] * dy[0] + k.R[3 + c] * dy[1] + k.R[6 + c] * dy[2];
+        gop += dop;
+        // colour
+        T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
+        T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
+        T Y[16];
+        sh_basis(dir[0], dir[1], dir[2], Y);
+        T w[16];
+        for (int k2 = 0; k2 < 16; k2++) w[k2] = T(0);
+        bool any = false;
+        for (int ch = 0; ch < 3; ch++) {
+            T raw = T(0.5);
+            for (int k2 = 0; k2 < 16; k2++) raw += P[(11 + 3 * k2 + ch) * n + i] * Y[k2];
+            if (!(raw > T(0))) continue;
+            any = true;
+            for (int k2 = 0; k2 < 16; k2++) {
+                T coef = P[(11 + 3 * k2 + ch) * n + i];
+                gsh[3 * k2 + ch] += drgb[ch] * Y[k2];
+                w[k2] += drgb[ch] * coef;
+            }
+        }
+        if (any) {
+            T gd[3];
+            sh_grad(dir[0], dir[1], dir[2], w, gd);
+            T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+            for (int c = 0; c < 3; c++) gmean[c] += (gd[c] - dir[c] * dd) * idn;
+        }
+    }
+    // Sig = Rq diag(s^2) Rq^T -> scale and rotation
+    T dM[9];
+    {
+        // dL/dM = (dSig + dSig^T) M with dSig the full symmetric gradient
+        T M[9];
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++) M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
+        T Gs[9];
+        const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+        for (int e = 0; e < 9; e++) {
+            int r = e / 3, c = e % 3;
+            Gs[e] = (r == c) ? gS[idx[e]] : T(0.5) * gS[idx[e]];
+        }
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++)
+                dM[3 * r + c] = T(2) * (Gs[3 * r] * M[c] + Gs[3 * r + 1] * M[3 + c] + Gs[3 * r + 2] * M[6 + c]);
+    }
+    T gls[3], dRq[9];
+    for (int c = 0; c < 3; c++) {
+        T acc = T(0);
+        for (int r = 0; r < 3; r++) {
+            dRq[3 * r + c] = dM[3 * r + c] * S.s[c];
+            acc += dM[3 * r + c] * S.Rq[3 * r + c];
+        }
+        gls[c] = acc * S.s[c];
+    }
+    T w = S.q[0], qx = S.q[1], qy = S.q[2], qz = S.q[3];
+    T dq[4];
+    dq[0] = T(2) * (-qz * dRq[1] + qy * dRq[2] + qz * dRq[3] - qx * dRq[5] - qy * dRq[6] + qx * dRq[7]);
+    dq[1] = T(2) * (qy * dRq[1] + qz * dRq[2] + qy * dRq[3] - T(2) * qx * dRq[4] - w * dRq[5] + qz * dRq[6] +
+                    w * dRq[7] - T(2) * qx * dRq[8]);
+    dq[2] = T(2) * (-T(2) * qy * dRq[0] + qx * dRq[1] + w * dRq[2] + qx * dRq[3] + qz * dRq[5] - w * dRq[6] +
+                    qz * dRq[7] - T(2) * qy * dRq[8]);
+    dq[3] = T(2) * (-T(2) * qz * dRq[0] - w * dRq[1] + qx * dRq[2] + w * dRq[3] - T(2) * qz * dRq[4] +
+                    qy * dRq[5] + qx * dRq[6] + qy * dRq[7]);
+    T dot = dq[0] * S.q[0] + dq[1] * S.q[1] + dq[2] * S.q[2] + dq[3] * S.q[3];
+    T iqn = T(1) / S.qn;
+    for (int c = 0; c < 3; c++) grad[c * n + i] += gmean[c];
+    for (int c = 0; c < 3; c++) grad[(3 + c) * n + i] += gls[c];
+    for (int j = 0; j < 4; j++) grad[(6 + j) * n + i] += (dq[j] - S.q[j] * dot) * iqn;
+    grad[10 * n + i] += gop * S.opac * (T(1) - S.opac);
+    for (int j = 0; j < 48; j++) grad[(11 + j) * n + i] += gsh[j];
+}
+
+template <typename T>
+hipError_t launch_project_fwd(const void *P, int64_t n, const gs_camera *cams, int32_t views, void *out,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(project_fwd_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams, views,
+                       (T *)out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, int32_t views, const void *proj,
+                              const void *dproj, void *grad, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(project_bwd_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams, views,
+                       (const T *)proj, (const T *)dproj, (T *)grad);
+    return hipGetLastError();
+}
+
+template hipError_t launch_project_fwd<float>(const void *, int64_t, const gs_camera *, int32_t, void *, hipStream_t);
+template hipError_t launch_project_fwd<double>(const void *, int64_t, const gs_camera *, int32_t, void *, hipStream_t);
+template hipError_t launch_project_bwd<float>(const void *, int64_t, const gs_camera *, int32_t, const void *,
+                                              const void *, void *, hipStream_t);
+template hipError_t launch_project_bwd<double>(const void *, int64_t, const gs_camera *, int32_t, const void *,
+                                               const void *, void *, hipStream_t);
+
+}  // namespace gs

@@ -1,0 +1,500 @@
+// Render forward and backward over 16x16 pixel tiles (paper section 2.1 step
+// 2; appendix A.3: render and its backward are pixel-wise), and the
+// scheduler that spreads the tiles of a whole batch over the GPU.
+//
+// A tile is worked by one workgroup of 256/PX threads, each owning PX pixels.
+// The tile's depth-ordered list is staged CHUNK records at a time into LDS
+// (one gathered 48-byte record per entry), and every thread walks the staged
+// records for its pixels. In the backward pass the list is walked in reverse
+// from the tile's largest `last`, the blend is undone with T_k = T_{k+1} /
+// (1 - alpha_k), and the per-Gaussian gradients of a wavefront are summed
+// with DPP before one global atomic per component.
+//
+// Work distribution:
+//  - per-tile mode: one workgroup per tile; workgroup b runs tile
+//    (b mod 8) * ceil(T/8) + b div 8, so each XCD (workgroups are dealt
+//    round-robin to the 8 XCDs) sees a contiguous eighth of the serialised
+//    tiles and neighbouring tiles share that XCD's L2;
+//  - persistent mode: a fixed grid of workgroups takes tiles from Q queues.
+//    The queues are the contiguous, cost-balanced chunks of Algorithm 1
+//    (division points) computed from per-tile costs; queue q belongs to XCD
+//    q div (Q/8). A workgroup drains its home queue, then steals from the
+//    other queues of its XCD, then from the other XCDs.
+#include "common.hpp"
+
+namespace gs {
+
+template <typename T> using V4 = typename Vec4<T>::type;
+
+template <typename T> struct FwdArgs {
+    const T *proj;
+    int64_t n;
+    const uint32_t *ids;
+    const uint32_t *ranges;
+    T bg[3];
+    T *rgb;
+    T *finalT;
+    uint32_t *last;
+    uint32_t *work_fwd;
+    uint32_t *work_bwd;
+};
+
+template <typename T> struct BwdArgs {
+    const T *proj;
+    int64_t n;
+    const uint32_t *ids;
+    const uint32_t *ranges;
+    T bg[3];
+    const T *finalT;
+    const uint32_t *last;
+    const T *dL;
+    T *dproj;
+};
+
+template <typename T, int CHUNK> struct Stage {
+    V4<T> a[CHUNK];    // u, v, r^2, opacity
+    V4<T> b[CHUNK];    // conic a, b, c, -
+    V4<T> c[CHUNK];    // r, g, b, -
+    uint32_t id[CHUNK];
+};
+
+template <typename T, int CHUNK, int NT>
+__device__ __forceinline__ void stage_records(Stage<T, CHUNK> &st, const T *__restrict__ proj, int64_t vbase,
+                                              const uint32_t *__restrict__ ids, int64_t first, int cnt)
+{
+    for (int q = threadIdx.x; q < cnt; q += NT) {
+        uint32_t id = ids[first + q];
+        const V4<T> *rec = reinterpret_cast<const V4<T> *>(proj + (vbase + id) * REC);
+        V4<T> r0 = rec[0], r1 = rec[1], r2 = rec[2];
+        T rad = r2.y;
+        st.a[q] = V4<T>{r0.x, r0.y, rad * rad, r1.y};
+        st.b[q] = V4<T>{r0.z, r0.w, r1.x, T(0)};
+        st.c[q] = V4<T>{r1.z, r1.w, r2.x, T(0)};
+        st.id[q] = id;
+    }
+}
+
+// ------------------------------------------------------------------ forward tile
+template <typename T, int PX, int CHUNK>
+__device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
+{
+    constexpr int NT = 256 / PX;
+    int v = view_of_tile(vt, g);
+    int local = g - vt.tile_base[v];
+    int TX = vt.tiles_x[v];
+    int tx = local % TX, ty = local / TX;
+    int W = vt.width[v], H = vt.height[v];
+    T pxc[PX], pyc[PX], Tr[PX], C[PX][3];
+    uint32_t lastp[PX];
+    bool done[PX];
+    bool inside[PX];
+    for (int j = 0; j < PX; j++) {
+        int p = threadIdx.x + j * NT;
+        int px = tx * TILE + (p & 15), py = ty * TILE + (p >> 4);
+        inside[j] = px < W && py < H;
+        pxc[j] = (T)px + T(0.5);
+        pyc[j] = (T)py + T(0.5);
+        Tr[j] = T(1);
+        C[j][0] = C[j][1] = C[j][2] = T(0);
+        lastp[j] = 0;
+        done[j] = !inside[j];
+    }
+    uint32_t s = A.ranges[2 * (int64_t)g], e = A.ranges[2 * (int64_t)g + 1];
+    int64_t vbase = (int64_t)v * A.n;
+    uint32_t walked = 0;
+    if (threadIdx.x == 0) *s_red = 0;
+    for (uint32_t base = s; base < e; base += CHUNK) {
+        int cnt = (int)min((uint32_t)CHUNK, e - base);
+        __syncthreads();
+        stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, base, cnt);
+        __syncthreads();
+        bool alldone = true;
+        for (int j = 0; j < PX; j++) alldone &= done[j];
+        for (int q = 0; q < cnt && !alldone; q++) {
+            V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q];
+            alldone = true;
+            for (int j = 0; j < PX; j++) {
+                if (done[j]) continue;
+                T dx, dy, G, og, alpha;
+                if (eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rb.x, rb.y, rb.z, ra.w, dx, dy, G, og, alpha)) {
+                    T Tn = Tr[j] * (T(1) - alpha);
+                    if (Tn < K<T>::t_min) {
+                        done[j] = true;
+                    } else {
+                        T w = alpha * Tr[j];
+                        C[j][0] += rc.x * w;
+                        C[j][1] += rc.y * w;
+                        C[j][2] += rc.z * w;
+                        Tr[j] = Tn;
+                        lastp[j] = base - s + q + 1;
+                    }
+                }
+                alldone &= done[j];
+            }
+        }
+        walked += cnt;
+        if (!__syncthreads_or(!alldone)) break;
+    }
+    uint32_t mylast = 0;
+    for (int j = 0; j < PX; j++) {
+        if (!inside[j]) continue;
+        int p = threadIdx.x + j * NT;
+        int px = tx * TILE + (p & 15), py = ty * TILE + (p >> 4);
+        int64_t pix = vt.pix_base[v] + (int64_t)py * W + px;
+        int64_t plane = (int64_t)W * H;
+        T *rgb = A.rgb + 3 * vt.pix_base[v] + (int64_t)py * W + px;
+        rgb[0] = C[j][0] + Tr[j] * A.bg[0];
+        rgb[plane] = C[j][1] + Tr[j] * A.bg[1];
+        rgb[2 * plane] = C[j][2] + Tr[j] * A.bg[2];
+        A.finalT[pix] = Tr[j];
+        A.last[pix] = lastp[j];
+        mylast = max(mylast, lastp[j]);
+    }
+    if (A.work_bwd) atomicMax(s_red, mylast);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (A.work_fwd) A.work_fwd[g] = walked;
+        if (A.work_bwd) A.work_bwd[g] = *s_red;
+    }
+}
+
+// ------------------------------------------------------------------ backward tile
+template <typename T>
+__device__ __forceinline__ T lane_pick(const T (&acc)[9], int lane)
+{
+    T r = acc[0];
+    for (int c = 1; c < 9; c++) r = lane == c ? acc[c] : r;
+    return r;
+}
+
+template <typename T, int PX, int CHUNK>
+__device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
+{
+    constexpr int NT = 256 / PX;
+    int v = view_of_tile(vt, g);
+    int local = g - vt.tile_base[v];
+    int TX = vt.tiles_x[v];
+    int tx = local % TX, ty = local / TX;
+    int W = vt.width[v], H = vt.height[v];
+    int lane = threadIdx.x & 63;
+    T pxc[PX], pyc[PX], Tr[PX], gr[PX][3], Bc[PX][3];
+    uint32_t L[PX];
+    uint32_t mymax = 0;
+    int64_t plane = (int64_t)W * H;
+    for (int j = 0; j < PX; j++) {
+        int p = threadIdx.x + j * NT;
+        int px = tx * TILE + (p & 15), py = ty * TILE + (p >> 4);
+        bool in = px < W && py < H;
+        pxc[j] = (T)px + T(0.5);
+        pyc[j] = (T)py + T(0.5);
+        int64_t pix = vt.pix_base[v] + (int64_t)py * W + px;
+        const T *dl = A.dL + 3 * vt.pix_base[v] + (int64_t)py * W + px;
+        Tr[j] = in ? A.finalT[pix] : T(1);
+        L[j] = in ? A.last[pix] : 0u;
+        for (int ch = 0; ch < 3; ch++) {
+            gr[j][ch] = in ? dl[ch * plane] : T(0);
+            Bc[j][ch] = A.bg[ch];
+        }
+        mymax = max(mymax, L[j]);
+    }
+    if (threadIdx.x == 0) *s_red = 0;
+    __syncthreads();
+    atomicMax(s_red, mymax);
+    __syncthreads();
+    uint32_t Lmax = *s_red;
+    uint32_t s = A.ranges[2 * (int64_t)g];
+    int64_t vbase = (int64_t)v * A.n;
+    for (int64_t hi = Lmax; hi > 0; hi -= CHUNK) {
+        int64_t lo = hi - CHUNK > 0 ? hi - CHUNK : 0;
+        int cnt = (int)(hi - lo);
+        __syncthreads();
+        stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, (int64_t)s + lo, cnt);
+        __syncthreads();
+        for (int q = cnt - 1; q >= 0; q--) {
+            uint32_t k = (uint32_t)(lo + q);
+            V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q];
+            T acc[9];
+            for (int c = 0; c < 9; c++) acc[c] = T(0);
+            bool any = false;
+            for (int j = 0; j < PX; j++) {
+                if (k >= L[j]) continue;
+                T dx, dy, G, og, alpha;
+                if (!eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rb.x, rb.y, rb.z, ra.w, dx, dy, G, og, alpha))
+                    continue;
+                any = true;
+                T Tk = Tr[j] / (T(1) - alpha);
+                T w = alpha * Tk;
+                acc[6] += w * gr[j][0];
+                acc[7] += w * gr[j][1];
+                acc[8] += w * gr[j][2];
+                T dalpha = ((rc.x - Bc[j][0]) * gr[j][0] + (rc.y - Bc[j][1]) * gr[j][1] + (rc.z - Bc[j][2]) * gr[j][2]) * Tk;
+                T om = T(1) - alpha;
+                Bc[j][0] = alpha * rc.x + om * Bc[j][0];
+                Bc[j][1] = alpha * rc.y + om * Bc[j][1];
+                Bc[j][2] = alpha * rc.z + om * Bc[j][2];
+                Tr[j] = Tk;
+                if (og <= K<T>::alpha_max) {
+                    T dpow = dalpha * og;
+                    acc[5] += dalpha * G;
+                    acc[0] += dpow * (rb.x * dx + rb.y * dy);
+                    acc[1] += dpow * (rb.y * dx + rb.z * dy);
+                    acc[2] += T(-0.5) * dpow * dx * dx;
+                    acc[3] += -dpow * dx * dy;
+                    acc[4] += T(-0.5) * dpow * dy * dy;
+                }
+            }
+            if (__ballot(any) == 0) continue;
+            for (int c = 0; c < 9; c++) acc[c] = wave_sum(acc[c]);
+            if (lane < 9) {
+                T *dst = A.dproj + (vbase + st.id[q]) * REC;
+                atomic_add(dst + lane, lane_pick(acc, lane));
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+__device__ __forceinline__ int32_t per_tile_index(int32_t b, int32_t T_all)
+{
+    int32_t per = (T_all + 7) / 8;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Claims the next tile for this workgroup in persistent mode; -1 when every
+// queue is drained. Home queue first, then the rest of the XCD, then others.
+__device__ __forceinline__ int32_t claim(const SchedState &S, int &qi, int32_t *s_item)
+{
+    if (threadIdx.x == 0) {
+        int Q = S.queues, per = Q / 8;
+        int x = blockIdx.x & 7;
+        int home = x * per + (int)((blockIdx.x >> 3) % per);
+        int32_t item = -1;
+        while (qi < Q) {
+            int q;
+            if (qi < per) q = x * per + (home - x * per + qi) % per;
+            else {
+                int o = qi - per;                 // other XCDs, nearest first
+                int xo = (x + 1 + o / per) & 7;
+                q = xo * per + o % per;
+            }
+            int32_t end = S.dp[q + 1];
+            if (__hip_atomic_load(S.cursor + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < end) {
+                int32_t got = atomicAdd(S.cursor + q, 1);
+                if (got < end) { item = got; break; }
+            }
+            qi++;
+        }
+        *s_item = item;
+    }
+    __syncthreads();
+    int32_t item = *s_item;
+    __syncthreads();
+    return item;
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) render_fwd_kernel(ViewTable vt, FwdArgs<T> A)
+{
+    __shared__ Stage<T, CHUNK> st;
+    __shared__ uint32_t s_red;
+    int32_t g = per_tile_index(blockIdx.x, vt.total_tiles);
+    if (g >= vt.total_tiles) return;
+    fwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) render_fwd_persistent(ViewTable vt, FwdArgs<T> A, SchedState S)
+{
+    __shared__ Stage<T, CHUNK> st;
+    __shared__ uint32_t s_red;
+    __shared__ int32_t s_item;
+    int qi = 0;
+    for (;;) {
+        int32_t g = claim(S, qi, &s_item);
+        if (g < 0) break;
+        fwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+    }
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) render_bwd_kernel(ViewTable vt, BwdArgs<T> A)
+{
+    __shared__ Stage<T, CHUNK> st;
+    __shared__ uint32_t s_red;
+    int32_t g = per_tile_index(blockIdx.x, vt.total_tiles);
+    if (g >= vt.total_tiles) return;
+    bwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, BwdArgs<T> A, SchedState S)
+{
+    __shared__ Stage<T, CHUNK> st;
+    __shared__ uint32_t s_red;
+    __shared__ int32_t s_item;
+    int qi = 0;
+    for (;;) {
+        int32_t g = claim(S, qi, &s_item);
+        if (g < 0) break;
+        bwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+    }
+}
+
+template <typename T>
+__global__ void fill_kernel(T *p, int64_t n)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) p[j] = T(0);
+}
+
+// ------------------------------------------------------------------ Algorithm 1 on the device
+// CT = cumsum(ET) with ET_j = cost_j + 1; DP[q] = first j with CT[j] >= q * CT[last] / Q;
+// DP[Q] = T. Resets cursor[q] = DP[q].
+__global__ void __launch_bounds__(1024) plan_kernel(const uint32_t *__restrict__ cost, int32_t T_all, int32_t Q,
+                                                    uint64_t *__restrict__ ct, int32_t *__restrict__ dp,
+                                                    int32_t *__restrict__ cursor, int32_t *__restrict__ dp_out)
+{
+    __shared__ uint64_t s_w[16];
+    __shared__ uint64_t s_carry;
+    int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < T_all; base += 1024) {
+        int32_t j = base + tid;
+        uint64_t x = j < T_all ? (uint64_t)(cost ? cost[j] : 0u) + 1ull : 0ull;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint64_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint64_t pre = s_carry;
+        for (int q = 0; q < w; q++) pre += s_w[q];
+        if (j < T_all) ct[j] = pre + x;
+        __syncthreads();
+        if (tid == 1023) s_carry = pre + x;
+        __syncthreads();
+    }
+    double total = (double)s_carry;
+    for (int q = tid; q <= Q; q += 1024) {
+        int32_t r;
+        if (q == Q) r = T_all;
+        else {
+            double th = (double)q * (total / (double)Q);
+            int32_t lo = 0, hi = T_all;
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if ((double)ct[mid] < th) lo = mid + 1;
+                else hi = mid;
+            }
+            r = lo;
+        }
+        dp[q] = r;
+        if (q < Q) cursor[q] = r;
+        if (dp_out) dp_out[q] = r;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+#define GS_DISPATCH_SHAPE(T, PX, CH, CALL)                                                                   \
+    do {                                                                                                     \
+        if (PX == 1 && CH == 32) { CALL(T, 1, 32); }                                                         \
+        else if (PX == 1 && CH == 64) { CALL(T, 1, 64); }                                                    \
+        else if (PX == 1 && CH == 128) { CALL(T, 1, 128); }                                                  \
+        else if (PX == 1 && CH == 256) { CALL(T, 1, 256); }                                                  \
+        else if (PX == 2 && CH == 32) { CALL(T, 2, 32); }                                                    \
+        else if (PX == 2 && CH == 64) { CALL(T, 2, 64); }                                                    \
+        else if (PX == 2 && CH == 128) { CALL(T, 2, 128); }                                                  \
+        else if (PX == 2 && CH == 256) { CALL(T, 2, 256); }                                                  \
+        else if (PX == 4 && CH == 32) { CALL(T, 4, 32); }                                                    \
+        else if (PX == 4 && CH == 64) { CALL(T, 4, 64); }                                                    \
+        else if (PX == 4 && CH == 128) { CALL(T, 4, 128); }                                                  \
+        else { CALL(T, 4, 256); }                                                                            \
+    } while (0)
+
+template <typename T>
+hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, const gs_bins *b, const float *bg,
+                             const LaunchShape &sh, void *rgb, void *finalT, uint32_t *last, uint32_t *wf,
+                             uint32_t *wb, hipStream_t s)
+{
+    FwdArgs<T> A;
+    A.proj = (const T *)proj;
+    A.n = n;
+    A.ids = b->ids;
+    A.ranges = b->ranges;
+    for (int c = 0; c < 3; c++) A.bg[c] = (T)bg[c];
+    A.rgb = (T *)rgb;
+    A.finalT = (T *)finalT;
+    A.last = last;
+    A.work_fwd = wf;
+    A.work_bwd = wb;
+    if (vt.total_tiles == 0) return hipSuccess;
+    unsigned grid_tiles = (unsigned)(8 * ((vt.total_tiles + 7) / 8));
+#define GS_FWD(TT, P, C)                                                                                     \
+    if (sh.mode == GS_SCHED_PERSISTENT)                                                                      \
+        hipLaunchKernelGGL((render_fwd_persistent<TT, P, C>), dim3(sh.workers), dim3(256 / P), 0, s, vt, A, sh.S); \
+    else                                                                                                     \
+        hipLaunchKernelGGL((render_fwd_kernel<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
+    if (sizeof(T) == 8) {
+        GS_FWD(T, 1, 64);
+    } else {
+        GS_DISPATCH_SHAPE(T, sh.px, sh.chunk, GS_FWD);
+    }
+#undef GS_FWD
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, const gs_bins *b, const float *bg,
+                             const LaunchShape &sh, const void *finalT, const uint32_t *last, const void *dL,
+                             void *dproj, hipStream_t s)
+{
+    BwdArgs<T> A;
+    A.proj = (const T *)proj;
+    A.n = n;
+    A.ids = b->ids;
+    A.ranges = b->ranges;
+    for (int c = 0; c < 3; c++) A.bg[c] = (T)bg[c];
+    A.finalT = (const T *)finalT;
+    A.last = last;
+    A.dL = (const T *)dL;
+    A.dproj = (T *)dproj;
+    int64_t nd = (int64_t)vt.nviews * n * REC;
+    if (nd > 0) hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, s, (T *)dproj, nd);
+    if (vt.total_tiles == 0) return hipGetLastError();
+    unsigned grid_tiles = (unsigned)(8 * ((vt.total_tiles + 7) / 8));
+#define GS_BWD(TT, P, C)                                                                                     \
+    if (sh.mode == GS_SCHED_PERSISTENT)                                                                      \
+        hipLaunchKernelGGL((render_bwd_persistent<TT, P, C>), dim3(sh.workers), dim3(256 / P), 0, s, vt, A, sh.S); \
+    else                                                                                                     \
+        hipLaunchKernelGGL((render_bwd_kernel<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
+    if (sizeof(T) == 8) {
+        GS_BWD(T, 1, 64);
+    } else {
+        GS_DISPATCH_SHAPE(T, sh.px, sh.chunk, GS_BWD);
+    }
+#undef GS_BWD
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const uint32_t *cost, int32_t T_all, int32_t Q, uint64_t *ct, int32_t *dp, int32_t *cursor,
+                       int32_t *dp_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, cost, T_all, Q, ct, dp, cursor, dp_out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_render_fwd<float>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
+                                             const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *,
+                                             hipStream_t);
+template hipError_t launch_render_fwd<double>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
+                                              const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *,
+                                              hipStream_t);
+template hipError_t launch_render_bwd<float>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
+                                             const LaunchShape &, const void *, const uint32_t *, const void *, void *,
+                                             hipStream_t);
+template hipError_t launch_render_bwd<double>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
+                                              const LaunchShape &, const void *, const uint32_t *, const void *, void *,
+                                              hipStream_t);
+
+}  // namespace gs

@@ -1,0 +1,368 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (FP32 kernels against the FP64 oracle):
+  - binning: keys (tile << 32 | FP32 depth bits), ids and ranges bit-exact,
+    the oracle binning the GPU's own FP32 (u, v, radius, depth);
+  - images: max |difference| <= 1e-5 over pixels the oracle does not flag as
+    ambiguous (a threshold decision within rounding distance), flagged pixels
+    < 1e-4 of all;
+  - gradients: ||g - g_oracle|| / ||g_oracle|| <= 1e-3 per parameter group.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import scenes
+
+pytestmark = pytest.mark.gpu
+
+BG = (0.1, 0.2, 0.3)
+GROUPS = {"mean": slice(0, 3), "log_scale": slice(3, 6), "quat": slice(6, 10), "opacity": slice(10, 11),
+          "sh_dc": slice(11, 14), "sh_rest": slice(14, 59)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_18533_amd import raster
+    raster.init(0)
+
+
+def _gp():
+    from tests import gpu_pipeline as gp
+    return gp
+
+
+def oracle_proj_from_gpu(pf: dict, v: int) -> np.ndarray:
+    """GPU FP32 record fields of view v promoted to the oracle's FP64 layout."""
+    N = pf["u"].shape[1]
+    pr = np.zeros((oracle.ONF, N))
+    vis = pf["radius"][v] > 0
+    for dst, src in [(oracle.F_U, "u"), (oracle.F_V, "v"), (oracle.F_DEPTH, "depth"), (oracle.F_A, "a"),
+                     (oracle.F_B, "b"), (oracle.F_C, "c"), (oracle.F_OPAC, "opac"), (oracle.F_R, "r"),
+                     (oracle.F_G, "g"), (oracle.F_BL, "bl"), (oracle.F_RADIUS, "radius"), (oracle.F_REXACT, "radius")]:
+        pr[dst] = np.where(vis, pf[src][v].astype(np.float64), 0.0)
+    return pr
+
+
+def small_multiview():
+    P = scenes.uniform_cube_gaussians(20_000, 7)
+    cams = [scenes.orbit_camera(70, 45, 3.0, 0.3, 0.2), scenes.orbit_camera(200, 120, 4.0, 2.0, 0.5),
+            scenes.orbit_camera(33, 50, 3.5, 4.0, -0.3)]
+    return P, cams
+
+
+WORKLOADS = {
+    "single_view_256": lambda: (scenes.plain_single_view().params, scenes.plain_single_view().cameras),
+    "ragged_3_views": small_multiview,
+}
+
+
+# ----------------------------------------------------------------------------- projection
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_project_matches_oracle(name):
+    gp = _gp()
+    P, cams = WORKLOADS[name]()
+    f = gp.forward(gp.to_dev(P), cams, BG)
+    pf = gp.proj_fields(f["proj"])
+    P64 = P.double()
+    n_checked = 0
+    for v, cam in enumerate(cams):
+        o = oracle.project(P64, cam)
+        both = (o[oracle.F_RADIUS] > 0) & (pf["radius"][v] > 0)
+        assert ((o[oracle.F_RADIUS] > 0) == (pf["radius"][v] > 0)).mean() > 0.9999
+        re = o[oracle.F_REXACT]
+        stable = both & (np.abs(re - np.round(re)) > 1e-5 * np.maximum(re, 1))
+        assert (pf["radius"][v][stable] == o[oracle.F_RADIUS][stable]).all()
+        # positions to 1e-6 of the image size, depth and opacity to 1e-6 relative
+        size = max(cam["width"], cam["height"])
+        for fo, fg, scale in [(oracle.F_U, "u", size), (oracle.F_V, "v", size), (oracle.F_DEPTH, "depth", 0),
+                              (oracle.F_OPAC, "opac", 0)]:
+            a, b = pf[fg][v][both].astype(np.float64), o[fo][both]
+            assert np.max(np.abs(a - b) / np.maximum(np.abs(b), max(scale, 1e-30))) <= 1e-6, fg
+        # conic relative to its own scale
+        ca = np.stack([pf[k][v][both] for k in ("a", "b", "c")]).astype(np.float64)
+        co = o[[oracle.F_A, oracle.F_B, oracle.F_C]][:, both]
+        scale = np.abs(co[0]) + np.abs(co[2])
+        assert np.max(np.abs(ca - co) / scale) <= 1e-5
+        # colour where the GPU computed it (tiles touched > 0)
+        col = both & (pf["tiles"][v] > 0)
+        cg = np.stack([pf[k][v][col] for k in ("r", "g", "bl")]).astype(np.float64)
+        assert np.max(np.abs(cg - o[[oracle.F_R, oracle.F_G, oracle.F_BL]][:, col])) <= 1e-5
+        n_checked += both.sum()
+    # tiles touched: bit-exact against the oracle's FP32 rectangle on the GPU's values
+    tt = oracle.tiles_touched(pf["u"], pf["v"], np.where(pf["radius"] > 0, pf["radius"], 0), cams)
+    assert (tt == pf["tiles"].astype(np.int64)).all()
+    assert n_checked > 1000
+
+
+# ----------------------------------------------------------------------------- binning
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_bin_sort_bit_exact(name):
+    gp = _gp()
+    P, cams = WORKLOADS[name]()
+    f = gp.forward(gp.to_dev(P), cams, BG)
+    pf = gp.proj_fields(f["proj"])
+    r = np.where(pf["radius"] > 0, pf["radius"], 0).astype(np.float32)
+    keys_o, ids_o, ranges_o = oracle.bin_sort(pf["u"], pf["v"], r, pf["depth"], cams)
+    keys_g, ids_g, ranges_g = gp.bins_numpy(f)
+    assert keys_g.shape == keys_o.shape and keys_o.size > 1000
+    assert (keys_g == keys_o).all()
+    assert (ids_g == ids_o).all()
+    assert (ranges_g == ranges_o).all()
+
+
+# ----------------------------------------------------------------------------- render forward
+def _render_parity(f, P, cams, gp):
+    pf = gp.proj_fields(f["proj"])
+    keys_o, ids_o, ranges_o = gp.bins_numpy(f)
+    base = oracle.tile_base(cams)
+    rgb_g = gp.split_views(f["rgb"], cams, 3)
+    T_g = gp.split_views(f["T"], cams, 1)
+    last_g = gp.split_views(f["last"], cams, 1)
+    amb_total = pix_total = 0
+    for v, cam in enumerate(cams):
+        pr = oracle_proj_from_gpu(pf, v)
+        o = oracle.render(pr, cam, ids_o, ranges_o[base[v]:base[v + 1]], BG)
+        ok = o["amb"] == 0
+        amb_total += (~ok).sum()
+        pix_total += ok.size
+        assert np.max(np.abs(rgb_g[v] - o["rgb"])[:, ok]) <= 1e-5
+        assert np.max(np.abs(T_g[v] - o["T"])[ok]) <= 1e-5
+        assert (last_g[v].view(np.uint32)[ok] == o["last"][ok]).all()
+    assert amb_total <= max(4, 1e-3 * pix_total), (amb_total, pix_total)
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_render_fwd_matches_oracle(name):
+    gp = _gp()
+    P, cams = WORKLOADS[name]()
+    f = gp.forward(gp.to_dev(P), cams, BG)
+    _render_parity(f, P, cams, gp)
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_end_to_end_images_match_oracle(name):
+    """The oracle's own FP64 projection, binning and composition."""
+    gp = _gp()
+    P, cams = WORKLOADS[name]()
+    f = gp.forward(gp.to_dev(P), cams, BG)
+    o = oracle.forward(P.double(), cams, BG, fragile_tol=1e-5)
+    rgb_g = gp.split_views(f["rgb"], cams, 3)
+    amb = 0
+    for v in range(len(cams)):
+        ok = o["views"][v]["amb"] == 0
+        amb += (~ok).sum()
+        err = np.abs(rgb_g[v] - o["views"][v]["rgb"])
+        assert np.max(err[:, ok]) <= 1e-5
+        # flagged pixels: one Gaussian may switch on or off at its alpha or
+        # radius threshold, so they still agree to within a small blend
+        assert np.max(err, initial=0.0) <= 0.05
+    # flagged: pixels on the rim of a Gaussian whose FP64 radius is within 1e-5
+    # of an integer, or with two consecutive contributors <= 2 FP32 ulps apart
+    # in depth; about 1% of the pixels of these small, dense views
+    assert amb <= max(8, 0.02 * sum(c["width"] * c["height"] for c in cams)), amb
+
+
+# ----------------------------------------------------------------------------- backward
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_render_bwd_matches_oracle(name):
+    gp = _gp()
+    P, cams = WORKLOADS[name]()
+    Pd = gp.to_dev(P)
+    f = gp.forward(Pd, cams, BG)
+    total = sum(3 * c["width"] * c["height"] for c in cams)
+    dL = torch.from_numpy(np.random.default_rng(5).normal(size=total).astype(np.float32) * 1e-3)
+    grad, dproj = gp.backward(Pd, f, dL.cuda(), BG)
+    pf = gp.proj_fields(f["proj"])
+    keys_o, ids_o, ranges_o = gp.bins_numpy(f)
+    base = oracle.tile_base(cams)
+    dLv = gp.split_views(dL, cams, 3)
+    dpg = dproj.cpu().numpy()
+    for v, cam in enumerate(cams):
+        pr = oracle_proj_from_gpu(pf, v)
+        do = oracle.render_bwd(pr, cam, ids_o, ranges_o[base[v]:base[v + 1]], dLv[v], BG)
+        for comp in [slice(0, 2), slice(2, 5), slice(5, 6), slice(6, 9)]:
+            a = dpg[v][:, comp].T.astype(np.float64)
+            b = do[comp]
+            err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            assert err <= 1e-3, (v, comp, err)
+    # parameter gradients: the oracle's whole FP64 backward from its own projection
+    fo = oracle.forward(P.double(), cams, BG)
+    go, _ = oracle.backward(P.double(), cams, fo, dLv, BG)
+    gg = grad.double().cpu().numpy()
+    for k, sl in GROUPS.items():
+        err = np.linalg.norm(gg[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        assert err <= 1e-3, (k, err)
+
+
+def test_fp64_path_matches_central_differences():
+    """The FP64 instantiation of the kernels against central finite
+    differences of its own forward (h = 1e-6), on 64x64 with 200 Gaussians."""
+    gp = _gp()
+    w = scenes.diff_check_small(dtype=torch.float64)
+    cam = w.cameras[0]
+    Pd = w.params.cuda()
+    G = torch.from_numpy(np.random.default_rng(3).normal(size=3 * 64 * 64)).cuda()
+    f = gp.forward(Pd, [cam], BG)
+    grad, _ = gp.backward(Pd, f, G, BG)
+
+    def loss_and_sig(P):
+        ff = gp.forward(P, [cam], BG)
+        return float((ff["rgb"] * G).sum()), (ff["bins"].ids[:int(ff["bins"].n_instances.item())].cpu().numpy().tobytes(),
+                                              ff["last"].cpu().numpy().tobytes())
+    rng = np.random.default_rng(4)
+    vis = np.nonzero(gp.proj_fields(f["proj"])["tiles"][0] > 0)[0]
+    checked = 0
+    for _ in range(60):
+        i, row = int(rng.choice(vis)), int(rng.integers(0, 59))
+        Pp, Pm = Pd.clone(), Pd.clone()
+        Pp[row, i] += 1e-6
+        Pm[row, i] -= 1e-6
+        lp, sp = loss_and_sig(Pp)
+        lm, sm = loss_and_sig(Pm)
+        if sp != sm:
+            continue
+        fd = (lp - lm) / 2e-6
+        assert abs(fd - grad[row, i].item()) <= 1e-5 * max(1.0, abs(fd)), (row, i, fd, grad[row, i].item())
+        checked += 1
+    assert checked >= 45
+
+
+# ----------------------------------------------------------------------------- loss and Adam
+def test_loss_l1_matches_oracle():
+    from paper_2406_18533_amd import raster as R
+    gp = _gp()
+    P, cams = small_multiview()
+    f = gp.forward(gp.to_dev(P), cams, BG)
+    tgt = scenes.random_images(cams, 9).cuda()
+    buf = R.LossBuffers(f["cams"])
+    loss, dL = R.gs_loss_l1(f["rgb"], tgt, f["cams"], buf)
+    torch.cuda.synchronize()
+    lo, go = oracle.l1_loss(gp.split_views(f["rgb"], cams, 3), gp.split_views(tgt, cams, 3))
+    assert abs(loss.item() - lo) <= 1e-6 * lo
+    gv = gp.split_views(dL, cams, 3)
+    for a, b in zip(gv, go):
+        np.testing.assert_allclose(a, b, rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("n", [1, 37, 10_000])
+def test_adam_matches_oracle(n):
+    from paper_2406_18533_amd import raster as R
+    rng = np.random.default_rng(n)
+    lr6 = [1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4]
+    p = rng.normal(size=(59, n)).astype(np.float32).astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    pd = torch.from_numpy(p).float().cuda()
+    md, vd = torch.zeros_like(pd), torch.zeros_like(pd)
+    step = torch.zeros(1, dtype=torch.int64, device="cuda")
+    scratch = torch.zeros(2, dtype=torch.float64, device="cuda")
+    h = R.adam_hparams(lr6, 0.9, 0.999, 1e-15, batch_size=16, zero_grad=True)
+    for t in range(1, 4):
+        g = rng.normal(size=(59, n)).astype(np.float32).astype(np.float64)
+        gd = torch.from_numpy(g).float().cuda()
+        R.gs_adam_step(pd, gd, md, vd, h, step, scratch)
+        oracle.adam(p, g, m, v, lr6, 0.9, 0.999, 1e-15, 16, t)
+        torch.cuda.synchronize()
+        assert (gd == 0).all()
+    assert step.item() == 3
+    # FP32 storage: each step rounds p to FP32 (half an ulp is 2.4e-7 below |p| = 4)
+    np.testing.assert_allclose(pd.double().cpu().numpy(), p, rtol=1e-6, atol=2e-6)
+    np.testing.assert_allclose(md.double().cpu().numpy(), m, rtol=1e-5, atol=1e-7)
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_nothing_visible_renders_background():
+    gp = _gp()
+    P = scenes.uniform_cube_gaussians(500, 3)
+    P[0] += 100.0                                   # all far behind the camera at (4,0,0)
+    cam = scenes.orbit_camera(48, 40, 4.0, 0.0, 0.0)
+    f = gp.forward(gp.to_dev(P), [cam], BG)
+    assert int(f["bins"].n_instances.item()) == 0
+    rgb = gp.split_views(f["rgb"], [cam], 3)[0]
+    for ch in range(3):
+        assert (rgb[ch] == np.float32(BG[ch])).all()
+    assert (f["T"].cpu().numpy() == 1).all() and (f["last"].cpu().numpy() == 0).all()
+    grad, _ = gp.backward(gp.to_dev(P), f, torch.ones(3 * 48 * 40, device="cuda"), BG)
+    assert (grad == 0).all()
+
+
+def test_single_gaussian_closed_form_on_gpu():
+    gp = _gp()
+    P = torch.zeros(59, 1)
+    P[3:6] = math.log(0.05)
+    P[6] = 1.0
+    P[10] = 2.0
+    P[11:14] = 0.7
+    cam = scenes.orbit_camera(64, 64, 4.0, 0.0, 0.0)
+    f = gp.forward(gp.to_dev(P), [cam], (0.0, 0.0, 0.0))
+    var = (cam["fx"] * 0.05 / 4.0) ** 2 + 0.3
+    r = math.ceil(3 * math.sqrt(var))
+    o = 1 / (1 + math.exp(-2.0))
+    col = 0.7 / (2 * math.sqrt(math.pi)) + 0.5
+    ys, xs = np.mgrid[0:64, 0:64]
+    d2 = (xs + 0.5 - 32) ** 2 + (ys + 0.5 - 32) ** 2
+    alpha = np.minimum(0.99, o * np.exp(-d2 / (2 * var)))
+    alpha = np.where((d2 <= r * r) & (alpha >= 1 / 255), alpha, 0)
+    rgb = gp.split_views(f["rgb"], [cam], 3)[0]
+    np.testing.assert_allclose(rgb[0], alpha * col, atol=2e-6)
+
+
+def test_capacity_overflow_is_reported():
+    from paper_2406_18533_amd import raster as R
+    from paper_2406_18533_amd._lib import GsError, GS_ERR_CAPACITY
+    P, cams = small_multiview()
+    C = R.Cameras(cams)
+    proj = R.gs_project(P.cuda(), C)
+    bins = R.Bins(P.shape[1], C, 100)
+    with pytest.raises(GsError) as ei:
+        R.gs_bin_sort(proj, P.shape[1], C, bins, check_capacity=True)
+    assert ei.value.status == GS_ERR_CAPACITY
+    assert int(bins.overflow.item()) == 1 and int(bins.n_instances.item()) > 100
+    # graph-safe mode: no error and no wait, the device flag reports it
+    bins2 = R.Bins(P.shape[1], C, 100)
+    R.gs_bin_sort(proj, P.shape[1], C, bins2, check_capacity=False)
+    torch.cuda.synchronize()
+    assert int(bins2.overflow.item()) == 1
+
+
+def test_invalid_arguments_rejected():
+    from paper_2406_18533_amd import _lib
+    from paper_2406_18533_amd import raster as R
+    L = _lib.load()
+    C = R.Cameras([scenes.orbit_camera(32, 32, 4.0, 0.0, 0.0)])
+    assert L.gs_project(_lib.GS_F32, None, 10, C.dev_ptr, C.host_ptr, 0, None, None) == _lib.GS_ERR_ARG
+    assert L.gs_project(7, None, 10, C.dev_ptr, C.host_ptr, 1, None, None) == _lib.GS_ERR_ARG
+    assert L.gs_project(_lib.GS_F32, None, 10, C.dev_ptr, C.host_ptr, 1, None, None) == _lib.GS_ERR_ARG
+
+
+# ----------------------------------------------------------------------------- invariance
+def test_image_identical_across_launch_shapes_and_schedulers():
+    gp = _gp()
+    from paper_2406_18533_amd import _lib
+    P, cams = small_multiview()
+    Pd = gp.to_dev(P)
+    ref = gp.forward(Pd, cams, BG)
+    for kw in [dict(px_per_thread=2, chunk=32), dict(px_per_thread=4, chunk=256), dict(px_per_thread=1, chunk=128),
+               dict(mode=_lib.GS_SCHED_PERSISTENT, px_per_thread=1, chunk=64, queues=16),
+               dict(mode=_lib.GS_SCHED_PERSISTENT, px_per_thread=4, chunk=128, queues=64, workers=64)]:
+        f = gp.forward(Pd, cams, BG, sched_kw=kw)
+        assert torch.equal(f["rgb"], ref["rgb"]) and torch.equal(f["T"], ref["T"]), kw
+        assert torch.equal(f["last"], ref["last"]), kw
+        assert torch.equal(f["work_bwd"], ref["work_bwd"]), kw
+
+
+def test_view_alone_equals_view_in_batch():
+    gp = _gp()
+    P, cams = small_multiview()
+    Pd = gp.to_dev(P)
+    batch = gp.forward(Pd, cams, BG)
+    rgb_b = gp.split_views(batch["rgb"], cams, 3)
+    for v, c in enumerate(cams):
+        alone = gp.forward(Pd, [c], BG)
+        assert (gp.split_views(alone["rgb"], [c], 3)[0] == rgb_b[v]).all()

@@ -1,0 +1,296 @@
+"""Benchmark of the batched 3DGS training step on one MI355X.
+
+Default workload: 1,000,000 clustered Gaussians, a batch of 16 views at
+1920x1080 (synthetic, seeded), L1 loss against a jittered-scene target, Adam
+with lr * sqrt(16) and beta^16. One step = transformation of every view,
+binning + sort, render forward, loss, render backward, transformation
+backward, Adam - the whole hot path, replayed as one captured HIP graph.
+
+Prints one JSON line: train views/s (value), the plain per-view path's
+views/s beside it, per-entry-point timings, the roofline of the dominant
+kernel and the FP64 CPU oracle timed on a sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from synthetic import scenes
+    if name == "batched_1080p":
+        return scenes.batched_1080p()
+    if name == "aerial_4k":
+        return scenes.aerial_4k()
+    if name == "small":
+        return scenes.Workload("small_4x256", scenes.clustered_gaussians(100_000, 1),
+                               scenes.sphere_cameras(4, 12, 256, 256), None)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def render_targets(P_target, cams_list):
+    """Target images: the jittered scene rendered by the same rasterizer (setup, untimed)."""
+    import torch
+    from paper_2406_18533_amd import raster as R
+    cams = R.Cameras(cams_list)
+    proj = R.gs_project(P_target, cams)
+    K = int(proj[..., 11].double().sum().item())
+    bins = R.Bins(P_target.shape[1], cams, K + 1024)
+    R.gs_bin_sort(proj, P_target.shape[1], cams, bins)
+    rgb, _, _ = R.gs_render_fwd(proj, P_target.shape[1], bins, cams)
+    torch.cuda.synchronize()
+    del bins, proj
+    return rgb
+
+
+def entry_timings(tr, reps: int):
+    """Average duration of every entry point of the step, from HIP events on
+    the stream the kernels run on (eager steps, same kernels as the graph)."""
+    import torch
+    from paper_2406_18533_amd import raster as R
+    names = ["gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss_l1", "gs_render_bwd_pixels", "gs_project_bwd",
+             "gs_adam_step"]
+    acc = {k: 0.0 for k in names}
+    c = tr.cfg
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ev[0].record()
+        R.gs_project(tr.P, tr.cams, tr.proj)
+        ev[1].record()
+        R.gs_bin_sort(tr.proj, tr.n, tr.cams, tr.bins, check_capacity=False)
+        ev[2].record()
+        R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, c.bg, tr.sched_fwd, tr.rgb, tr.T, tr.last, tr.work_fwd,
+                        tr.work_bwd)
+        ev[3].record()
+        R.gs_loss_l1(tr.rgb, tr.targets, tr.cams, tr.loss_buf)
+        ev[4].record()
+        R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, tr.dproj, c.bg,
+                               tr.sched_bwd)
+        ev[5].record()
+        R.gs_project_bwd(tr.P, tr.cams, tr.proj, tr.dproj, tr.grad, clear=True)
+        ev[6].record()
+        R.gs_adam_step(tr.P, tr.grad, tr.m, tr.v, tr.hp, tr.step_dev, tr.scratch, skip_flag=tr.bins.overflow)
+        ev[7].record()
+        torch.cuda.synchronize()
+        for j, k in enumerate(names):
+            acc[k] += ev[j].elapsed_time(ev[j + 1])
+    return {k: v / reps for k, v in acc.items()}
+
+
+def workload_counts(tr):
+    """Exact counts of the step's work units, for the algorithmic bytes/flops."""
+    import torch
+    from paper_2406_18533_amd import raster as R
+    stats = torch.zeros(2, dtype=torch.int64, device="cuda")
+    R.gs_project(tr.P, tr.cams, tr.proj)
+    R.gs_bin_sort(tr.proj, tr.n, tr.cams, tr.bins, check_capacity=True)
+    R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, tr.cfg.bg, tr.sched_fwd, tr.rgb, tr.T, tr.last,
+                    tr.work_fwd, tr.work_bwd, pair_stats=stats)
+    torch.cuda.synchronize()
+    tiles = tr.proj[..., 11]
+    radius = tr.proj[..., 9]
+    return {
+        "N": tr.n, "V": tr.V, "pixels": tr.cams.total_pixels(), "tiles": tr.cams.total_tiles(),
+        "K": int(tr.bins.n_instances.item()),
+        "records_on_screen": int((tiles > 0).sum().item()),
+        "records_in_front": int((radius > 0).sum().item()),
+        "gaussians_on_screen": int((tiles > 0).any(dim=0).sum().item()),
+        "pairs_evaluated_fwd": int(stats[0].item()),
+        "pairs_blended": int(stats[1].item()),
+        "pairs_evaluated_bwd": int(tr.last.double().sum().item()),
+    }
+
+
+def algorithmic(c: dict) -> dict:
+    """Algorithmic work of each entry point (bytes the method must move, or
+    FP32 flops it must execute), per launch, from the exact counts."""
+    VN, M, K, T, Pn = c["V"] * c["N"], c["records_on_screen"], c["K"], c["tiles"], c["pixels"]
+    N, Ns = c["N"], c["gaussians_on_screen"]
+    radix_passes_depth, radix_passes_tile = 4, 2
+    return {
+        # read means of all, the other 224 B of Gaussians on screen; write a 48-B record per on-screen
+        # (view, Gaussian) and a 4-B "no tiles" marker for the rest
+        "gs_project": ("hbm", 12 * N + 224 * Ns + 48 * M + 4 * (VN - M)),
+        # compaction (4 B flag + 4 B depth in, 8 B out per pair), 4 depth passes over pairs (20 B each),
+        # offsets (16 B per pair), emission (20 B per pair + 8 B per instance), 2 tile passes over
+        # instances (20 B each), ranges (4 B per instance + 8 B per tile)
+        "gs_bin_sort": ("hbm", 4 * VN + 12 * M + radix_passes_depth * 20 * M + 16 * M + 20 * M + 8 * K
+                        + radix_passes_tile * 20 * K + 4 * K + 8 * T),
+        # 17 flops to evaluate a pair (offset, circle, quadratic form, exp, opacity), 9 more to blend it
+        "gs_render_fwd": ("alu", 17 * c["pairs_evaluated_fwd"] + 9 * c["pairs_blended"]),
+        "gs_loss_l1": ("hbm", 36 * Pn),
+        # re-evaluate every pair up to `last` (17 flops), 53 more for each blended pair's gradients
+        "gs_render_bwd_pixels": ("alu", 17 * c["pairs_evaluated_bwd"] + 53 * c["pairs_blended"]),
+        # params of on-screen Gaussians (236 B), their gradient read + write (472 B), tiles field of every
+        # record (4 B), the 36-B record gradient read and cleared per on-screen record
+        "gs_project_bwd": ("hbm", 708 * Ns + 4 * VN + 72 * M),
+        # read p, g, m, v and write p, m, v (+ g cleared): 32 B per parameter float, 59 per Gaussian
+        "gs_adam_step": ("hbm", 32 * 59 * N),
+    }
+
+
+def roofline(timings: dict, counts: dict):
+    work = algorithmic(counts)
+    dom = max(timings, key=lambda k: timings[k])
+    bound, amount = work[dom]
+    sec = timings[dom] / 1e3
+    if bound == "hbm":
+        achieved = amount / sec / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        achieved = amount / sec / 1e12
+        out = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    out["frac"] = round(achieved / out["peak"], 4)
+    out["traffic"] = None
+    out["kernel"] = dom
+    out["ms"] = round(timings[dom], 4)
+    per = {}
+    for k, (b, a) in work.items():
+        t = timings[k] / 1e3
+        per[k] = {"bound": b, "ms": round(timings[k], 4),
+                  "achieved": round(a / t / (1e9 if b == "hbm" else 1e12), 2 if b == "alu" else 1),
+                  "unit": "GB/s" if b == "hbm" else "TFLOP/s"}
+    return out, per
+
+
+def cpu_baseline(workload, sample_views: int = 1):
+    """The FP64 oracle on a bounded sample: the whole per-view pipeline of one
+    view of the batch (transformation, binning, render, loss, render and
+    transformation backward) plus one Adam step, extrapolated to the batch."""
+    import numpy as np
+    import oracle
+    P = workload.params.double().numpy()
+    cams = workload.cameras[:sample_views]
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    f = oracle.forward(P, cams)
+    targets = [rng.uniform(size=v["rgb"].shape) for v in f["views"]]
+    loss, g = oracle.l1_loss([v["rgb"] for v in f["views"]], targets)
+    grad, _ = oracle.backward(P, cams, f, g)
+    t1 = time.perf_counter()
+    m = np.zeros_like(P)
+    v = np.zeros_like(P)
+    oracle.adam(P, grad, m, v, [1e-4] * 6, 0.9, 0.999, 1e-15, len(workload.cameras), 1)
+    t2 = time.perf_counter()
+    per_view = (t1 - t0) / sample_views
+    step = per_view * len(workload.cameras) + (t2 - t1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(len(workload.cameras) / step, 5), "unit": "views/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_views} of {len(workload.cameras)} views ({cams[0]['width']}x{cams[0]['height']}, "
+                      f"N={P.shape[1]}), full per-view pipeline in {per_view:.1f} s + Adam in {t2 - t1:.1f} s, "
+                      f"extrapolated linearly to the batch"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched_1080p")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (a multi-GPU run would "
+                                   "shard Gaussians and tiles across GPUs, which is not built)"}))
+        sys.exit(2)
+    import torch
+    from paper_2406_18533_amd import _lib, autotune, train
+    from paper_2406_18533_amd import raster as R
+
+    _lib.load()
+    R.init(0)
+    log(f"workload {args.workload}: generating")
+    w = make_workload(args.workload)
+    P = w.params.cuda()
+    log(f"N={P.shape[1]} views={len(w.cameras)}; rendering targets")
+    targets = render_targets(w.target_params.cuda() if w.target_params is not None else P.clone(), w.cameras)
+    cfg = train.TrainConfig(graph=not args.no_graph)
+    if args.mode is not None:
+        cfg.mode = args.mode
+    tr = train.BatchedTrainer(P.clone(), w.cameras, targets, cfg)
+    tuned = None
+    if not args.no_autotune:
+        log("autotuning render launch shapes")
+        tuned = autotune.tune(tr, verbose=False)
+        log(f"autotune: fwd {tuned['fwd']} bwd {tuned['bwd']}")
+    if args.mode is not None:
+        tr.set_shapes(mode=args.mode)
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        tr.step()
+        tr.check_overflow()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tr.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    redo = tr.check_overflow()
+    ms = (t1 - t0) * 1e3 / args.steps
+    views_s = tr.V * args.steps / (t1 - t0)
+    log(f"{ms:.3f} ms/step, {views_s:.1f} views/s, loss {tr.loss():.5f}, overflow redo {redo}")
+    log("per-entry timings (eager, HIP events)")
+    timings = entry_timings(tr, reps=min(5, max(args.steps, 1)))
+    counts = workload_counts(tr)
+    roof, per = roofline(timings, counts)
+    log(f"timings {json.dumps(timings)}")
+    plain = None
+    if not args.no_plain:
+        log("plain per-view path")
+        pt = train.PlainTrainer(P.clone(), w.cameras, targets, cfg)
+        pt.step()
+        torch.cuda.synchronize()
+        k = max(2, min(args.steps, 5))
+        t0 = time.perf_counter()
+        for _ in range(k):
+            pt.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain = {"views_per_s": round(pt.V * k / (t1 - t0), 2), "ms_per_step": round((t1 - t0) * 1e3 / k, 3)}
+        del pt
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (sample)")
+        cpu = cpu_baseline(w)
+    cams = w.cameras
+    out = {
+        "metric": "train views/s fwd+bwd (1080p, 4K) vs plain path; render p50/p99 ms at fixed QPS",
+        "value": round(views_s, 2), "unit": "views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "gaussians": P.shape[1], "views": len(cams),
+                   "resolution": sorted({f"{c['width']}x{c['height']}" for c in cams}),
+                   "global_batch": len(cams), "parallelism": "single-gpu",
+                   "graph": not args.no_graph, "scheduler": {"fwd": list(tr.cfg.fwd_shape), "bwd": list(tr.cfg.bwd_shape),
+                                                            "modes": tr.cfg.extra}},
+        "plain_path": plain,
+        "speedup_vs_plain": round(views_s / plain["views_per_s"], 3) if plain else None,
+        "roofline": roof,
+        "per_kernel": per,
+        "counts": counts,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

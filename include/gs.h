@@ -187,35 +187,58 @@ gs_status gs_bins_keys64(gs_dtype dtype, const void *projected, int64_t n, const
  * Writes rgb = C + T bg, final_T and last (list position after the last
  * blended Gaussian) for every pixel. Optional (nullable) per global tile:
  * tile_work_fwd = list entries walked, tile_work_bwd = max of last; the
- * scheduler uses them as the next cost estimates. bg: [host] 3 floats.
- * sched: launch shape; NULL = per-tile, 256 threads, chunk 64. */
+ * scheduler uses them as the next cost estimates. pair_stats: nullable [2]
+ * device counters, incremented by (pixel, Gaussian) pairs evaluated and
+ * blended (a separate kernel variant; for measurement). bg: [host] 3
+ * floats. sched: launch shape; NULL = per-tile, 256 threads, chunk 64. */
 gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
                         const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
                         void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd,
-                        uint32_t *tile_work_bwd, void *stream);
+                        uint32_t *tile_work_bwd, uint64_t *pair_stats, void *stream);
 
 /* Back-propagation through rendering and transformation (section 2.1,
  * "standard approaches to backpropagation"; appendix A.3: render backward is
- * pixel-wise, transformation backward Gaussian-wise). Given dL/drgb it
- * recomputes the blend in reverse from final_T and last, accumulates the
- * per-(view, Gaussian) gradients of (u, v, a, b, c, opacity, r, g, b) into
- * dprojected [views][n][GS_REC] (zeroed by this call first), then adds
- * (+=) the parameter gradients into grad [59][n]. Depth, radius and the tile
- * rectangle carry no gradient. bins, final_T and last must come from the
- * gs_bin_sort / gs_render_fwd of the same projected buffer. */
+ * pixel-wise, transformation backward Gaussian-wise): gs_render_bwd_pixels
+ * followed by gs_project_bwd with clear = 1. dprojected [views][n][GS_REC]
+ * must be all zero on entry (allocate it zeroed once) and is all zero again
+ * on return. Adds (+=) the parameter gradients into grad [59][n]. */
 gs_status gs_render_bwd(gs_dtype dtype, const void *params, int64_t n, const void *projected,
                         const gs_bins *bins, const gs_camera *cams_dev, const gs_camera *cams_host,
                         int32_t views, const float *bg, const gs_sched *sched, const void *final_T,
                         const uint32_t *last, const void *dL_drgb, void *dprojected, void *grad,
                         void *stream);
 
-/* Loss (section 2.1 step 3, L1 part): loss = (1/views) sum_v mean over the
- * 3 H W values of |rgb - target|, the batch loss being the mean of per-view
- * losses (section 4, g = sum_k g_k / b). Writes dL_drgb = sign(rgb -
- * target) / (3 H W views) (sign(0) = 0) and *loss_dev (one double, device).
- * workspace: gs_loss_workspace_bytes. Deterministic. */
+/* Render backward (pixel-wise half). Given dL/drgb, recomputes the blend of
+ * every pixel in reverse from final_T and last (T_k = T_{k+1} / (1 - alpha_k),
+ * colour behind k composed from the background forward), and adds (+=) the
+ * per-(view, Gaussian) gradients of (u, v, a, b, c, opacity, r, g, b) into
+ * slots 0-8 of dprojected [views][n][GS_REC]. bins, final_T and last must
+ * come from the gs_bin_sort / gs_render_fwd of the same projected buffer. */
+gs_status gs_render_bwd_pixels(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                               const gs_camera *cams_host, int32_t views, const float *bg,
+                               const gs_sched *sched, const void *final_T, const uint32_t *last,
+                               const void *dL_drgb, void *dprojected, void *stream);
+
+/* Transformation backward (Gaussian-wise half): chain rule from dprojected
+ * through colour (SH, clamp mask, view direction), conic, EWA covariance,
+ * perspective Jacobian (zero through a clamped coordinate), camera
+ * transform, rotation (with the normalisation), scale and sigmoid, summed
+ * over the views and added (+=) into grad [59][n]. Depth, radius and the
+ * tile rectangle carry no gradient. clear = 1 zeroes the dprojected records
+ * it read (those with tiles touched > 0), leaving dprojected all zero. */
+gs_status gs_project_bwd(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
+                         const gs_camera *cams_host, int32_t views, const void *projected,
+                         void *dprojected, int32_t clear, void *grad, void *stream);
+
+/* Loss (section 2.1 step 3, L1 part): loss = (scale/views) sum_v mean over
+ * the 3 H W values of |rgb - target|, the batch loss being the mean of
+ * per-view losses (section 4, g = sum_k g_k / b). Writes dL_drgb =
+ * scale sign(rgb - target) / (3 H W views) (sign(0) = 0) and *loss_dev (one
+ * double, device). scale = 1 for a batch; a caller that walks a batch of b
+ * views one view at a time passes 1/b. workspace: gs_loss_workspace_bytes.
+ * Deterministic. */
 gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host,
-                     int32_t views, void *dL_drgb, double *loss_dev, void *workspace,
+                     int32_t views, double scale, void *dL_drgb, double *loss_dev, void *workspace,
                      size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------ optimizer */
@@ -226,9 +249,13 @@ gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const 
  *   p -= (lr' / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps).
  * step_dev: [1] device step counter, incremented on the device so graph
  * replays advance it. scratch: [2] device doubles for the bias corrections.
+ * skip_flag: nullable device int32; when it holds a non-zero value (e.g. the
+ * bins overflow flag of this step) the update is skipped: params, moments
+ * and the step counter stay unchanged (grad is still zeroed if asked).
  * h: [host]. */
 gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *v, int64_t n,
-                       const gs_adam_hparams *h, int64_t *step_dev, double *scratch, void *stream);
+                       const gs_adam_hparams *h, int64_t *step_dev, double *scratch,
+                       const int32_t *skip_flag, void *stream);
 
 /* ------------------------------------------------------------------ scheduler */
 /* Algorithm 1 ("Calculation of Division Points") on the device with G =

@@ -11,7 +11,7 @@ namespace gs {
 
 template <typename T> hipError_t launch_project_fwd(const void *, int64_t, const gs_camera *, int32_t, void *, hipStream_t);
 template <typename T>
-hipError_t launch_project_bwd(const void *, int64_t, const gs_camera *, int32_t, const void *, const void *, void *,
+hipError_t launch_project_bwd(const void *, int64_t, const gs_camera *, int32_t, const void *, void *, int, void *,
                               hipStream_t);
 template <typename T>
 hipError_t launch_bin_sort(const void *, int64_t, const ViewTable &, gs_bins *, bool, int *, hipStream_t);
@@ -20,16 +20,17 @@ hipError_t launch_keys64(const void *, int64_t, const ViewTable &, const gs_bins
 size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws);
 template <typename T>
 hipError_t launch_render_fwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
-                             const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *, hipStream_t);
+                             const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *, uint64_t *,
+                             hipStream_t);
 template <typename T>
 hipError_t launch_render_bwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                              const LaunchShape &, const void *, const uint32_t *, const void *, void *, hipStream_t);
 hipError_t launch_plan(const uint32_t *, int32_t, int32_t, uint64_t *, int32_t *, int32_t *, int32_t *, hipStream_t);
 template <typename T>
 hipError_t launch_adam(void *, void *, void *, void *, int64_t, const gs_adam_hparams *, int64_t *, double *,
-                       hipStream_t);
+                       const int32_t *, hipStream_t);
 template <typename T>
-hipError_t launch_l1(const void *, const void *, const ViewTable &, void *, double *, void *, hipStream_t);
+hipError_t launch_l1(const void *, const void *, const ViewTable &, double, void *, double *, void *, hipStream_t);
 size_t loss_ws_bytes(int32_t views);
 
 ViewTable make_view_table(const gs_camera *cams, int32_t views)
@@ -289,7 +290,8 @@ gs_status gs_sched_plan(const gs_sched *sched, const gs_camera *cams_host, int32
 
 gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
                         const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched, void *rgb,
-                        void *final_T, uint32_t *last, uint32_t *tile_work_fwd, uint32_t *tile_work_bwd, void *stream)
+                        void *final_T, uint32_t *last, uint32_t *tile_work_fwd, uint32_t *tile_work_bwd,
+                        uint64_t *pair_stats, void *stream)
 {
     std::string why;
     CHECK_ARG(dtype_ok(dtype), "bad dtype");
@@ -306,10 +308,51 @@ gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const 
     }
     hipError_t e = dtype == GS_F32
                        ? launch_render_fwd<float>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
-                                                  tile_work_bwd, s)
+                                                  tile_work_bwd, pair_stats, s)
                        : launch_render_fwd<double>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
-                                                   tile_work_bwd, s);
+                                                   tile_work_bwd, pair_stats, s);
     return hip_status(e, "gs_render_fwd");
+}
+
+gs_status gs_render_bwd_pixels(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                               const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
+                               const void *final_T, const uint32_t *last, const void *dL_drgb, void *dprojected,
+                               void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(bins_ok(bins, n, views, why), why);
+    CHECK_ARG(bg && final_T && last && dL_drgb && dprojected && projected, "null pointer");
+    ViewTable vt = make_view_table(cams_host, views);
+    LaunchShape sh;
+    CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
+    hipStream_t s = (hipStream_t)stream;
+    if (sh.mode == GS_SCHED_PERSISTENT) {
+        hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
+        if (e != hipSuccess) return hip_status(e, "gs_render_bwd_pixels plan");
+    }
+    hipError_t e = dtype == GS_F32
+                       ? launch_render_bwd<float>(vt, projected, n, bins, bg, sh, final_T, last, dL_drgb, dprojected, s)
+                       : launch_render_bwd<double>(vt, projected, n, bins, bg, sh, final_T, last, dL_drgb, dprojected,
+                                                   s);
+    return hip_status(e, "gs_render_bwd_pixels");
+}
+
+gs_status gs_project_bwd(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
+                         const gs_camera *cams_host, int32_t views, const void *projected, void *dprojected,
+                         int32_t clear, void *grad, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(n >= 0 && (uint64_t)n * (uint64_t)views < (uint64_t(1) << 32), "n * views must be < 2^32");
+    CHECK_ARG(n == 0 || (params && cams_dev && projected && dprojected && grad), "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32
+                       ? launch_project_bwd<float>(params, n, cams_dev, views, projected, dprojected, clear, grad, s)
+                       : launch_project_bwd<double>(params, n, cams_dev, views, projected, dprojected, clear, grad, s);
+    return hip_status(e, "gs_project_bwd");
 }
 
 gs_status gs_render_bwd(gs_dtype dtype, const void *params, int64_t n, const void *projected, const gs_bins *bins,
@@ -317,32 +360,16 @@ gs_status gs_render_bwd(gs_dtype dtype, const void *params, int64_t n, const voi
                         const gs_sched *sched, const void *final_T, const uint32_t *last, const void *dL_drgb,
                         void *dprojected, void *grad, void *stream)
 {
-    std::string why;
-    CHECK_ARG(dtype_ok(dtype), "bad dtype");
-    CHECK_ARG(cams_ok(cams_host, views, why), why);
-    CHECK_ARG(bins_ok(bins, n, views, why), why);
-    CHECK_ARG(bg && final_T && last && dL_drgb && dprojected && grad && params && projected && cams_dev,
-              "null pointer");
-    ViewTable vt = make_view_table(cams_host, views);
-    LaunchShape sh;
-    CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
-    hipStream_t s = (hipStream_t)stream;
-    if (sh.mode == GS_SCHED_PERSISTENT) {
-        hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
-        if (e != hipSuccess) return hip_status(e, "gs_render_bwd plan");
-    }
-    hipError_t e = dtype == GS_F32
-                       ? launch_render_bwd<float>(vt, projected, n, bins, bg, sh, final_T, last, dL_drgb, dprojected, s)
-                       : launch_render_bwd<double>(vt, projected, n, bins, bg, sh, final_T, last, dL_drgb, dprojected,
-                                                   s);
-    if (e != hipSuccess) return hip_status(e, "gs_render_bwd render");
-    e = dtype == GS_F32 ? launch_project_bwd<float>(params, n, cams_dev, views, projected, dprojected, grad, s)
-                        : launch_project_bwd<double>(params, n, cams_dev, views, projected, dprojected, grad, s);
-    return hip_status(e, "gs_render_bwd transform");
+    CHECK_ARG(params && grad && cams_dev, "null pointer");
+    gs_status st = gs_render_bwd_pixels(dtype, projected, n, bins, cams_host, views, bg, sched, final_T, last,
+                                        dL_drgb, dprojected, stream);
+    if (st != GS_OK) return st;
+    return gs_project_bwd(dtype, params, n, cams_dev, cams_host, views, projected, dprojected, 1, grad, stream);
 }
 
 gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host, int32_t views,
-                     void *dL_drgb, double *loss_dev, void *workspace, size_t workspace_bytes, void *stream)
+                     double scale, void *dL_drgb, double *loss_dev, void *workspace, size_t workspace_bytes,
+                     void *stream)
 {
     std::string why;
     CHECK_ARG(dtype_ok(dtype), "bad dtype");
@@ -351,13 +378,15 @@ gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const 
     CHECK_ARG(workspace_bytes >= loss_ws_bytes(views), "loss workspace too small");
     ViewTable vt = make_view_table(cams_host, views);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = dtype == GS_F32 ? launch_l1<float>(rgb, target, vt, dL_drgb, loss_dev, workspace, s)
-                                   : launch_l1<double>(rgb, target, vt, dL_drgb, loss_dev, workspace, s);
+    CHECK_ARG(isfinite(scale), "bad scale");
+    hipError_t e = dtype == GS_F32 ? launch_l1<float>(rgb, target, vt, scale, dL_drgb, loss_dev, workspace, s)
+                                   : launch_l1<double>(rgb, target, vt, scale, dL_drgb, loss_dev, workspace, s);
     return hip_status(e, "gs_loss_l1");
 }
 
 gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *v, int64_t n,
-                       const gs_adam_hparams *h, int64_t *step_dev, double *scratch, void *stream)
+                       const gs_adam_hparams *h, int64_t *step_dev, double *scratch, const int32_t *skip_flag,
+                       void *stream)
 {
     CHECK_ARG(dtype_ok(dtype), "bad dtype");
     CHECK_ARG(h && step_dev && scratch, "null pointer");
@@ -366,8 +395,8 @@ gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *
     CHECK_ARG(h->batch_size >= 1, "batch_size must be >= 1");
     CHECK_ARG(h->beta1 >= 0 && h->beta1 < 1 && h->beta2 >= 0 && h->beta2 < 1 && h->eps >= 0, "bad betas / eps");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = dtype == GS_F32 ? launch_adam<float>(params, grad, m, v, n, h, step_dev, scratch, s)
-                                   : launch_adam<double>(params, grad, m, v, n, h, step_dev, scratch, s);
+    hipError_t e = dtype == GS_F32 ? launch_adam<float>(params, grad, m, v, n, h, step_dev, scratch, skip_flag, s)
+                                   : launch_adam<double>(params, grad, m, v, n, h, step_dev, scratch, skip_flag, s);
     return hip_status(e, "gs_adam_step");
 }
 

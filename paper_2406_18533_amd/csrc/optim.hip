@@ -15,8 +15,13 @@ struct AdamConst {
     int32_t zero_grad;
 };
 
-__global__ void adam_prepare_kernel(int64_t *step, double b1, double b2, double *scratch)
+// scratch[0] = 1 - b1^t, scratch[1] = sqrt(1 - b2^t); 0 in scratch[0] marks a skipped step.
+__global__ void adam_prepare_kernel(int64_t *step, double b1, double b2, double *scratch, const int32_t *skip)
 {
+    if (skip && *skip != 0) {
+        scratch[0] = 0.0;
+        return;
+    }
     int64_t t = *step + 1;
     *step = t;
     scratch[0] = 1.0 - pow(b1, (double)t);
@@ -43,9 +48,16 @@ __global__ void __launch_bounds__(256) adam_kernel(T *__restrict__ P, T *__restr
                                                    const double *__restrict__ scratch)
 {
     int row = blockIdx.y;
+    double bc1 = scratch[0];
+    if (bc1 == 0.0) {  // skipped step: only clear the gradient
+        if (c.zero_grad)
+            for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+                Gr[(int64_t)row * n + j] = T(0);
+        return;
+    }
     T lr = (T)c.lr[row_group(row)];
     T b1 = (T)c.b1, b2 = (T)c.b2, eps = (T)c.eps;
-    T step = lr / (T)scratch[0];
+    T step = lr / (T)bc1;
     T bc2s = (T)scratch[1];
     int64_t off = (int64_t)row * n;
     if (VEC) {
@@ -79,7 +91,7 @@ __global__ void __launch_bounds__(256) adam_kernel(T *__restrict__ P, T *__restr
 
 template <typename T>
 hipError_t launch_adam(void *p, void *g, void *m, void *v, int64_t n, const gs_adam_hparams *h, int64_t *step,
-                       double *scratch, hipStream_t s)
+                       double *scratch, const int32_t *skip, hipStream_t s)
 {
     AdamConst c;
     double sb = sqrt((double)h->batch_size);
@@ -88,7 +100,7 @@ hipError_t launch_adam(void *p, void *g, void *m, void *v, int64_t n, const gs_a
     c.b2 = pow(h->beta2, (double)h->batch_size);
     c.eps = h->eps;
     c.zero_grad = h->zero_grad;
-    hipLaunchKernelGGL(adam_prepare_kernel, dim3(1), dim3(1), 0, s, step, c.b1, c.b2, scratch);
+    hipLaunchKernelGGL(adam_prepare_kernel, dim3(1), dim3(1), 0, s, step, c.b1, c.b2, scratch, skip);
     if (n == 0) return hipGetLastError();
     bool vec = (n % 4 == 0) && ((uintptr_t)p % 32 == 0) && ((uintptr_t)g % 32 == 0) && ((uintptr_t)m % 32 == 0) &&
                ((uintptr_t)v % 32 == 0);
@@ -110,13 +122,14 @@ constexpr int LOSS_BLOCKS = 64;
 
 template <typename T>
 __global__ void __launch_bounds__(256) l1_kernel(const T *__restrict__ rgb, const T *__restrict__ tgt,
-                                                 T *__restrict__ dL, ViewTable vt, double *__restrict__ partial)
+                                                 T *__restrict__ dL, ViewTable vt, double scale,
+                                                 double *__restrict__ partial)
 {
     __shared__ double s_w[4];
     int v = blockIdx.y;
     int64_t beg = 3 * vt.pix_base[v], end = 3 * vt.pix_base[v + 1];
     int64_t cnt = end - beg;
-    double wd = 1.0 / ((double)cnt * (double)vt.nviews);
+    double wd = scale / ((double)cnt * (double)vt.nviews);
     T w = (T)wd;
     double acc = 0.0;
     for (int64_t j = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < end;
@@ -143,23 +156,23 @@ __global__ void l1_finish_kernel(const double *partial, int64_t n, double *loss)
 size_t loss_ws_bytes(int32_t views) { return sizeof(double) * (size_t)LOSS_BLOCKS * (size_t)views; }
 
 template <typename T>
-hipError_t launch_l1(const void *rgb, const void *tgt, const ViewTable &vt, void *dL, double *loss, void *ws,
-                     hipStream_t s)
+hipError_t launch_l1(const void *rgb, const void *tgt, const ViewTable &vt, double scale, void *dL, double *loss,
+                     void *ws, hipStream_t s)
 {
     hipLaunchKernelGGL(l1_kernel<T>, dim3(LOSS_BLOCKS, vt.nviews), dim3(256), 0, s, (const T *)rgb, (const T *)tgt,
-                       (T *)dL, vt, (double *)ws);
+                       (T *)dL, vt, scale, (double *)ws);
     hipLaunchKernelGGL(l1_finish_kernel, dim3(1), dim3(64), 0, s, (const double *)ws,
                        (int64_t)LOSS_BLOCKS * vt.nviews, loss);
     return hipGetLastError();
 }
 
 template hipError_t launch_adam<float>(void *, void *, void *, void *, int64_t, const gs_adam_hparams *, int64_t *,
-                                       double *, hipStream_t);
+                                       double *, const int32_t *, hipStream_t);
 template hipError_t launch_adam<double>(void *, void *, void *, void *, int64_t, const gs_adam_hparams *, int64_t *,
-                                        double *, hipStream_t);
-template hipError_t launch_l1<float>(const void *, const void *, const ViewTable &, void *, double *, void *,
+                                        double *, const int32_t *, hipStream_t);
+template hipError_t launch_l1<float>(const void *, const void *, const ViewTable &, double, void *, double *, void *,
                                      hipStream_t);
-template hipError_t launch_l1<double>(const void *, const void *, const ViewTable &, void *, double *, void *,
+template hipError_t launch_l1<double>(const void *, const void *, const ViewTable &, double, void *, double *, void *,
                                       hipStream_t);
 
 }  // namespace gs

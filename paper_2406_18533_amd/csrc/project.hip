@@ -148,9 +148,6 @@ __device__ __forceinline__ void make_geo(const T x[3], const Shape<T> &S, const 
 // Real orthonormal spherical harmonics of degree <= 3 (Condon-Shortley phase)
 // as polynomials in the unit direction; coefficients from
 // K_lm = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) and the Legendre derivatives.
-template <typename T> struct ShK {
-    static constexpr double PI = 3.14159265358979323846;
-};
 #define GS_SQRT(v) ((T)__builtin_sqrt(v))
 
 template <typename T> __device__ __forceinline__ void sh_basis(T x, T y, T z, T Y[16])
@@ -272,8 +269,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ P, int64_t n,
                                                           const gs_camera *__restrict__ cams, int32_t views,
-                                                          const T *__restrict__ proj, const T *__restrict__ dproj,
-                                                          T *__restrict__ grad)
+                                                          const T *__restrict__ proj, T *__restrict__ dproj,
+                                                          int clear, T *__restrict__ grad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -289,8 +286,14 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
     for (int j = 0; j < 48; j++) gsh[j] = T(0);
     for (int v = 0; v < views; v++) {
         if (!((vis >> v) & 1ull)) continue;
-        const V4<T> *dr = reinterpret_cast<const V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
+        V4<T> *dr = reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
         V4<T> d0 = dr[0], d1 = dr[1], d2 = dr[2];
+        if (clear) {
+            const V4<T> zero{T(0), T(0), T(0), T(0)};
+            dr[0] = zero;
+            dr[1] = zero;
+            dr[2] = zero;
+        }
         T du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x, dop = d1.y;
         T drgb[3] = {d1.z, d1.w, d2.x};
         Camera<T> k = load_camera<T>(cams + v);
@@ -423,20 +426,20 @@ hipError_t launch_project_fwd(const void *P, int64_t n, const gs_camera *cams, i
 
 template <typename T>
 hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, int32_t views, const void *proj,
-                              const void *dproj, void *grad, hipStream_t s)
+                              void *dproj, int clear, void *grad, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(project_bwd_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams, views,
-                       (const T *)proj, (const T *)dproj, (T *)grad);
+                       (const T *)proj, (T *)dproj, clear, (T *)grad);
     return hipGetLastError();
 }
 
 template hipError_t launch_project_fwd<float>(const void *, int64_t, const gs_camera *, int32_t, void *, hipStream_t);
 template hipError_t launch_project_fwd<double>(const void *, int64_t, const gs_camera *, int32_t, void *, hipStream_t);
-template hipError_t launch_project_bwd<float>(const void *, int64_t, const gs_camera *, int32_t, const void *,
-                                              const void *, void *, hipStream_t);
-template hipError_t launch_project_bwd<double>(const void *, int64_t, const gs_camera *, int32_t, const void *,
-                                               const void *, void *, hipStream_t);
+template hipError_t launch_project_bwd<float>(const void *, int64_t, const gs_camera *, int32_t, const void *, void *,
+                                              int, void *, hipStream_t);
+template hipError_t launch_project_bwd<double>(const void *, int64_t, const gs_camera *, int32_t, const void *, void *,
+                                               int, void *, hipStream_t);
 
 }  // namespace gs

@@ -37,6 +37,7 @@ template <typename T> struct FwdArgs {
     uint32_t *last;
     uint32_t *work_fwd;
     uint32_t *work_bwd;
+    unsigned long long *stats;   // [2]: pairs evaluated, pairs blended (STATS variants only)
 };
 
 template <typename T> struct BwdArgs {
@@ -75,9 +76,10 @@ __device__ __forceinline__ void stage_records(Stage<T, CHUNK> &st, const T *__re
 }
 
 // ------------------------------------------------------------------ forward tile
-template <typename T, int PX, int CHUNK>
+template <typename T, int PX, int CHUNK, bool STATS>
 __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
 {
+    uint32_t n_eval = 0, n_blend = 0;
     constexpr int NT = 256 / PX;
     int v = view_of_tile(vt, g);
     int local = g - vt.tile_base[v];
@@ -116,11 +118,13 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
             for (int j = 0; j < PX; j++) {
                 if (done[j]) continue;
                 T dx, dy, G, og, alpha;
+                if (STATS) n_eval++;
                 if (eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rb.x, rb.y, rb.z, ra.w, dx, dy, G, og, alpha)) {
                     T Tn = Tr[j] * (T(1) - alpha);
                     if (Tn < K<T>::t_min) {
                         done[j] = true;
                     } else {
+                        if (STATS) n_blend++;
                         T w = alpha * Tr[j];
                         C[j][0] += rc.x * w;
                         C[j][1] += rc.y * w;
@@ -151,6 +155,10 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         mylast = max(mylast, lastp[j]);
     }
     if (A.work_bwd) atomicMax(s_red, mylast);
+    if (STATS) {
+        atomicAdd(A.stats, (unsigned long long)n_eval);
+        atomicAdd(A.stats + 1, (unsigned long long)n_blend);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         if (A.work_fwd) A.work_fwd[g] = walked;
@@ -292,17 +300,17 @@ __device__ __forceinline__ int32_t claim(const SchedState &S, int &qi, int32_t *
     return item;
 }
 
-template <typename T, int PX, int CHUNK>
+template <typename T, int PX, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(256 / PX) render_fwd_kernel(ViewTable vt, FwdArgs<T> A)
 {
     __shared__ Stage<T, CHUNK> st;
     __shared__ uint32_t s_red;
     int32_t g = per_tile_index(blockIdx.x, vt.total_tiles);
     if (g >= vt.total_tiles) return;
-    fwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+    fwd_tile<T, PX, CHUNK, STATS>(g, vt, A, st, &s_red);
 }
 
-template <typename T, int PX, int CHUNK>
+template <typename T, int PX, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(256 / PX) render_fwd_persistent(ViewTable vt, FwdArgs<T> A, SchedState S)
 {
     __shared__ Stage<T, CHUNK> st;
@@ -312,7 +320,7 @@ __global__ void __launch_bounds__(256 / PX) render_fwd_persistent(ViewTable vt, 
     for (;;) {
         int32_t g = claim(S, qi, &s_item);
         if (g < 0) break;
-        fwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+        fwd_tile<T, PX, CHUNK, STATS>(g, vt, A, st, &s_red);
     }
 }
 
@@ -338,13 +346,6 @@ __global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, 
         if (g < 0) break;
         bwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
     }
-}
-
-template <typename T>
-__global__ void fill_kernel(T *p, int64_t n)
-{
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) p[j] = T(0);
 }
 
 // ------------------------------------------------------------------ Algorithm 1 on the device
@@ -415,7 +416,7 @@ __global__ void __launch_bounds__(1024) plan_kernel(const uint32_t *__restrict__
 template <typename T>
 hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, const gs_bins *b, const float *bg,
                              const LaunchShape &sh, void *rgb, void *finalT, uint32_t *last, uint32_t *wf,
-                             uint32_t *wb, hipStream_t s)
+                             uint32_t *wb, uint64_t *stats, hipStream_t s)
 {
     FwdArgs<T> A;
     A.proj = (const T *)proj;
@@ -428,19 +429,24 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     A.last = last;
     A.work_fwd = wf;
     A.work_bwd = wb;
+    A.stats = (unsigned long long *)stats;
     if (vt.total_tiles == 0) return hipSuccess;
     unsigned grid_tiles = (unsigned)(8 * ((vt.total_tiles + 7) / 8));
-#define GS_FWD(TT, P, C)                                                                                     \
+#define GS_FWD_S(TT, P, C, ST)                                                                               \
     if (sh.mode == GS_SCHED_PERSISTENT)                                                                      \
-        hipLaunchKernelGGL((render_fwd_persistent<TT, P, C>), dim3(sh.workers), dim3(256 / P), 0, s, vt, A, sh.S); \
+        hipLaunchKernelGGL((render_fwd_persistent<TT, P, C, ST>), dim3(sh.workers), dim3(256 / P), 0, s, vt, A, \
+                           sh.S);                                                                            \
     else                                                                                                     \
-        hipLaunchKernelGGL((render_fwd_kernel<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
+        hipLaunchKernelGGL((render_fwd_kernel<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
+#define GS_FWD(TT, P, C)                                                                                     \
+    if (stats) { GS_FWD_S(TT, P, C, true) } else { GS_FWD_S(TT, P, C, false) }
     if (sizeof(T) == 8) {
         GS_FWD(T, 1, 64);
     } else {
         GS_DISPATCH_SHAPE(T, sh.px, sh.chunk, GS_FWD);
     }
 #undef GS_FWD
+#undef GS_FWD_S
     return hipGetLastError();
 }
 
@@ -459,9 +465,7 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
     A.last = last;
     A.dL = (const T *)dL;
     A.dproj = (T *)dproj;
-    int64_t nd = (int64_t)vt.nviews * n * REC;
-    if (nd > 0) hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, s, (T *)dproj, nd);
-    if (vt.total_tiles == 0) return hipGetLastError();
+    if (vt.total_tiles == 0) return hipSuccess;
     unsigned grid_tiles = (unsigned)(8 * ((vt.total_tiles + 7) / 8));
 #define GS_BWD(TT, P, C)                                                                                     \
     if (sh.mode == GS_SCHED_PERSISTENT)                                                                      \
@@ -486,10 +490,10 @@ hipError_t launch_plan(const uint32_t *cost, int32_t T_all, int32_t Q, uint64_t 
 
 template hipError_t launch_render_fwd<float>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                                              const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *,
-                                             hipStream_t);
+                                             uint64_t *, hipStream_t);
 template hipError_t launch_render_fwd<double>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                                               const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *,
-                                              hipStream_t);
+                                              uint64_t *, hipStream_t);
 template hipError_t launch_render_bwd<float>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                                              const LaunchShape &, const void *, const uint32_t *, const void *, void *,
                                              hipStream_t);

@@ -186,7 +186,7 @@ def gs_bins_keys64(projected: torch.Tensor, n: int, cams: Cameras, bins: Bins, s
 
 def gs_render_fwd(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras, bg=(0.0, 0.0, 0.0),
                   sched: Sched | None = None, rgb=None, final_T=None, last=None, tile_work_fwd=None,
-                  tile_work_bwd=None, stream=None):
+                  tile_work_bwd=None, pair_stats=None, stream=None):
     P = cams.total_pixels()
     dev = projected.device
     if rgb is None:
@@ -198,22 +198,45 @@ def gs_render_fwd(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras, bg
     check(_lib.load().gs_render_fwd(_dtype_code(projected.dtype), _ptr(projected), n, C.byref(bins.struct),
                                     cams.host_ptr, cams.n, _bg(bg), C.byref(sched.struct) if sched else None,
                                     _ptr(rgb), _ptr(final_T), _ptr(last), _ptr(tile_work_fwd), _ptr(tile_work_bwd),
-                                    _stream(stream)))
+                                    _ptr(pair_stats), _stream(stream)))
     return rgb, final_T, last
 
 
 def gs_render_bwd(params: torch.Tensor, projected: torch.Tensor, bins: Bins, cams: Cameras, final_T, last, dL_drgb,
                   grad: torch.Tensor, bg=(0.0, 0.0, 0.0), sched: Sched | None = None, dprojected=None, stream=None):
-    """Accumulates (+=) the parameter gradient into ``grad``; returns the
-    per-(view, Gaussian) record gradients."""
+    """Both backward halves; accumulates (+=) into ``grad``. ``dprojected``
+    must be all zero on entry and is all zero on return."""
     n = params.shape[1]
     if dprojected is None:
-        dprojected = torch.empty(cams.n, n, _lib.GS_REC, dtype=params.dtype, device=params.device)
+        dprojected = torch.zeros(cams.n, n, _lib.GS_REC, dtype=params.dtype, device=params.device)
     check(_lib.load().gs_render_bwd(_dtype_code(params.dtype), _ptr(params), n, _ptr(projected),
                                     C.byref(bins.struct), cams.dev_ptr, cams.host_ptr, cams.n, _bg(bg),
                                     C.byref(sched.struct) if sched else None, _ptr(final_T), _ptr(last),
                                     _ptr(dL_drgb), _ptr(dprojected), _ptr(grad), _stream(stream)))
     return dprojected
+
+
+def gs_render_bwd_pixels(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras, final_T, last, dL_drgb,
+                         dprojected: torch.Tensor | None = None, bg=(0.0, 0.0, 0.0), sched: Sched | None = None,
+                         stream=None):
+    """Render backward: adds the per-(view, Gaussian) record gradients into
+    ``dprojected`` (zeroed here when not given)."""
+    if dprojected is None:
+        dprojected = torch.zeros(cams.n, n, _lib.GS_REC, dtype=projected.dtype, device=projected.device)
+    check(_lib.load().gs_render_bwd_pixels(_dtype_code(projected.dtype), _ptr(projected), n, C.byref(bins.struct),
+                                           cams.host_ptr, cams.n, _bg(bg), C.byref(sched.struct) if sched else None,
+                                           _ptr(final_T), _ptr(last), _ptr(dL_drgb), _ptr(dprojected),
+                                           _stream(stream)))
+    return dprojected
+
+
+def gs_project_bwd(params: torch.Tensor, cams: Cameras, projected: torch.Tensor, dprojected: torch.Tensor,
+                   grad: torch.Tensor, clear: bool = False, stream=None):
+    n = params.shape[1]
+    check(_lib.load().gs_project_bwd(_dtype_code(params.dtype), _ptr(params), n, cams.dev_ptr, cams.host_ptr,
+                                     cams.n, _ptr(projected), _ptr(dprojected), int(clear), _ptr(grad),
+                                     _stream(stream)))
+    return grad
 
 
 class LossBuffers:
@@ -225,10 +248,11 @@ class LossBuffers:
         self.workspace = torch.empty(wsb, dtype=torch.uint8, device=device)
 
 
-def gs_loss_l1(rgb: torch.Tensor, target: torch.Tensor, cams: Cameras, buf: LossBuffers, stream=None):
+def gs_loss_l1(rgb: torch.Tensor, target: torch.Tensor, cams: Cameras, buf: LossBuffers, scale: float = 1.0,
+               stream=None):
     check(_lib.load().gs_loss_l1(_dtype_code(rgb.dtype), _ptr(rgb), _ptr(target), cams.host_ptr, cams.n,
-                                 _ptr(buf.dL), _ptr(buf.loss), _ptr(buf.workspace), buf.workspace.numel(),
-                                 _stream(stream)))
+                                 float(scale), _ptr(buf.dL), _ptr(buf.loss), _ptr(buf.workspace),
+                                 buf.workspace.numel(), _stream(stream)))
     return buf.loss, buf.dL
 
 
@@ -237,10 +261,11 @@ def adam_hparams(lr6, beta1=0.9, beta2=0.999, eps=1e-15, batch_size=1, zero_grad
                          int(zero_grad))
 
 
-def gs_adam_step(params, grad, m, v, h: GsAdamHparams, step: torch.Tensor, scratch: torch.Tensor, stream=None):
+def gs_adam_step(params, grad, m, v, h: GsAdamHparams, step: torch.Tensor, scratch: torch.Tensor,
+                 skip_flag: torch.Tensor | None = None, stream=None):
     n = params.shape[1]
     check(_lib.load().gs_adam_step(_dtype_code(params.dtype), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), n,
-                                   C.byref(h), _ptr(step), _ptr(scratch), _stream(stream)))
+                                   C.byref(h), _ptr(step), _ptr(scratch), _ptr(skip_flag), _stream(stream)))
 
 
 def gs_sched_plan(sched: Sched, cams: Cameras, dp_out: torch.Tensor | None = None, stream=None):

@@ -1,0 +1,232 @@
+"""Training steps over a batch of views.
+
+BatchedTrainer: the batched step of the paper's training loop (section 2.1:
+transformation, rendering, loss, back-propagation; section 4: Adam with
+lr * sqrt(b) and beta^b) over all b views at once - one projection launch
+for every view, one (view, tile) work queue for the whole batch, render
+kernels scheduled by per-tile work counts of the previous iteration, and the
+whole step captured once as a HIP graph and replayed.
+
+PlainTrainer: the same batched step computed view by view with eager
+launches and one workgroup per tile (the baseline the batched path is
+measured against).
+
+Every arithmetic step runs in libgs.so; torch only owns the buffers and the
+stream.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+from . import raster as R
+
+
+@dataclass
+class TrainConfig:
+    lr: tuple = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4)   # mean, log-scale, quat, opacity, SH0, SH rest
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+    bg: tuple = (0.0, 0.0, 0.0)
+    headroom: float = 1.25          # instance capacity = headroom * first K
+    mode: int = _lib.GS_SCHED_PERSISTENT
+    fwd_shape: tuple = (1, 64)      # (px_per_thread, chunk) of render forward
+    bwd_shape: tuple = (1, 64)      # (px_per_thread, chunk) of render backward
+    queues: int = 64
+    workers: int = 0
+    graph: bool = True
+    extra: dict = field(default_factory=dict)
+
+
+class BatchedTrainer:
+    def __init__(self, params: torch.Tensor, cams_list: list, targets: torch.Tensor, cfg: TrainConfig | None = None):
+        self.cfg = cfg or TrainConfig()
+        assert params.is_cuda and params.dtype == torch.float32 and params.shape[0] == 59
+        self.P = params.contiguous()
+        self.n = self.P.shape[1]
+        self.V = len(cams_list)
+        self.cams = R.Cameras(cams_list)
+        self.targets = targets.contiguous()
+        dev = self.P.device
+        self.grad = torch.zeros_like(self.P)
+        self.m = torch.zeros_like(self.P)
+        self.v = torch.zeros_like(self.P)
+        self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.scratch = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.proj = torch.empty(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        P_all = self.cams.total_pixels()
+        self.rgb = torch.empty(3 * P_all, dtype=torch.float32, device=dev)
+        self.T = torch.empty(P_all, dtype=torch.float32, device=dev)
+        self.last = torch.empty(P_all, dtype=torch.int32, device=dev)
+        self.loss_buf = R.LossBuffers(self.cams, device=dev)
+        T_all = self.cams.total_tiles()
+        self.work_fwd = torch.zeros(T_all, dtype=torch.int32, device=dev)
+        self.work_bwd = torch.zeros(T_all, dtype=torch.int32, device=dev)
+        self.hp = R.adam_hparams(self.cfg.lr, self.cfg.beta1, self.cfg.beta2, self.cfg.eps, batch_size=self.V,
+                                 zero_grad=True)
+        self._make_sched()
+        R.gs_project(self.P, self.cams, self.proj)
+        K = int(self.proj[..., 11].double().sum().item())
+        self.bins = R.Bins(self.n, self.cams, max(int(K * self.cfg.headroom), 1024))
+        self.graph = None
+        self.overflows = 0
+        self._flag_host = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+
+    def _make_sched(self):
+        c = self.cfg
+        self.sched_fwd = R.Sched(self.cams, c.mode, c.fwd_shape[0], c.fwd_shape[1], c.workers, c.queues,
+                                 tile_cost=self.work_fwd)
+        self.sched_bwd = R.Sched(self.cams, c.mode, c.bwd_shape[0], c.bwd_shape[1], c.workers, c.queues,
+                                 tile_cost=self.work_bwd)
+
+    def set_shapes(self, fwd_shape=None, bwd_shape=None, mode=None):
+        if fwd_shape:
+            self.cfg.fwd_shape = tuple(fwd_shape)
+        if bwd_shape:
+            self.cfg.bwd_shape = tuple(bwd_shape)
+        if mode is not None:
+            self.cfg.mode = mode
+        self._make_sched()
+        self.graph = None
+
+    # -- the step -------------------------------------------------------------------------
+    def forward(self, check: bool = False):
+        R.gs_project(self.P, self.cams, self.proj)
+        R.gs_bin_sort(self.proj, self.n, self.cams, self.bins, check_capacity=check)
+        R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
+                        self.last, self.work_fwd, self.work_bwd)
+
+    def backward_and_update(self):
+        R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
+        R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
+                               self.dproj, self.cfg.bg, self.sched_bwd)
+        R.gs_project_bwd(self.P, self.cams, self.proj, self.dproj, self.grad, clear=True)
+        R.gs_adam_step(self.P, self.grad, self.m, self.v, self.hp, self.step_dev, self.scratch,
+                       skip_flag=self.bins.overflow)
+
+    def _body(self, check: bool):
+        self.forward(check)
+        self.backward_and_update()
+
+    def _grow(self):
+        K = int(self.bins.n_instances.item())
+        self.bins = R.Bins(self.n, self.cams, int(K * self.cfg.headroom) + 1024)
+        self.graph = None
+
+    def step_eager(self):
+        """One eager step; grows the instance buffers first if they are too small."""
+        while True:
+            try:
+                R.gs_project(self.P, self.cams, self.proj)
+                R.gs_bin_sort(self.proj, self.n, self.cams, self.bins, check_capacity=True)
+                break
+            except _lib.GsError as e:
+                if e.status != _lib.GS_ERR_CAPACITY:
+                    raise
+                self.overflows += 1
+                self._grow()
+        R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
+                        self.last, self.work_fwd, self.work_bwd)
+        self.backward_and_update()
+
+    def capture(self):
+        """Captures one whole step as a HIP graph (after an eager warm-up)."""
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.step_eager()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._body(check=False)
+        torch.cuda.synchronize()
+        self.graph = g
+
+    def step(self):
+        if self.cfg.graph:
+            if self.graph is None:
+                self.capture()
+            self.graph.replay()
+        else:
+            self.step_eager()
+
+    def check_overflow(self) -> bool:
+        """After a step: if its bins overflowed, the update was skipped on the
+        device; grow the buffers, re-capture and redo the step eagerly."""
+        self._flag_host.copy_(self.bins.overflow)
+        if int(self._flag_host.item()) == 0:
+            return False
+        self.overflows += 1
+        self._grow()
+        self.step_eager()
+        return True
+
+    def loss(self) -> float:
+        return float(self.loss_buf.loss.item())
+
+
+class PlainTrainer:
+    """The batched step computed one view at a time, eagerly, with one
+    workgroup per tile: same loss (per-view losses scaled by 1/b), same
+    gradient, one Adam step with the same scaled hyper-parameters."""
+
+    def __init__(self, params: torch.Tensor, cams_list: list, targets: torch.Tensor, cfg: TrainConfig | None = None):
+        self.cfg = cfg or TrainConfig()
+        self.P = params.contiguous()
+        self.n = self.P.shape[1]
+        self.V = len(cams_list)
+        dev = self.P.device
+        self.cams = [R.Cameras([c]) for c in cams_list]
+        self.targets = []
+        o = 0
+        for c in cams_list:
+            k = 3 * c["width"] * c["height"]
+            self.targets.append(targets[o:o + k])
+            o += k
+        self.grad = torch.zeros_like(self.P)
+        self.m = torch.zeros_like(self.P)
+        self.v = torch.zeros_like(self.P)
+        self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.scratch = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.proj = torch.empty(1, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.dproj = torch.zeros(1, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.hp = R.adam_hparams(self.cfg.lr, self.cfg.beta1, self.cfg.beta2, self.cfg.eps, batch_size=self.V,
+                                 zero_grad=True)
+        Kmax = 0
+        for cm in self.cams:
+            R.gs_project(self.P, cm, self.proj)
+            Kmax = max(Kmax, int(self.proj[..., 11].double().sum().item()))
+        self.bins = R.Bins(self.n, max(self.cams, key=lambda c: c.total_tiles()), max(int(Kmax * self.cfg.headroom), 1024))
+        self.bins_tiles = self.bins.total_tiles
+        self.bufs = [R.LossBuffers(cm, device=dev) for cm in self.cams]
+        self.loss_total = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def step(self):
+        bg = self.cfg.bg
+        for cm, tg, lb in zip(self.cams, self.targets, self.bufs):
+            R.gs_project(self.P, cm, self.proj)
+            while True:
+                try:
+                    if cm.total_tiles() > self.bins_tiles:
+                        raise _lib.GsError(_lib.GS_ERR_CAPACITY, "tiles")
+                    R.gs_bin_sort(self.proj, self.n, cm, self.bins, check_capacity=True)
+                    break
+                except _lib.GsError as e:
+                    if e.status != _lib.GS_ERR_CAPACITY:
+                        raise
+                    K = int(self.bins.n_instances.item())
+                    self.bins = R.Bins(self.n, cm, int(max(K, self.bins.capacity) * self.cfg.headroom))
+                    self.bins_tiles = self.bins.total_tiles
+            rgb, T, last = R.gs_render_fwd(self.proj, self.n, self.bins, cm, bg)
+            R.gs_loss_l1(rgb, tg, cm, lb, scale=1.0 / self.V)
+            R.gs_render_bwd(self.P, self.proj, self.bins, cm, T, last, lb.dL, self.grad, bg, dprojected=self.dproj)
+        R.gs_adam_step(self.P, self.grad, self.m, self.v, self.hp, self.step_dev, self.scratch)
+
+    def loss(self) -> float:
+        return float(sum(b.loss.item() for b in self.bufs))

@@ -38,9 +38,11 @@ def forward(params: torch.Tensor, cams_list: list, bg=(0.0, 0.0, 0.0), sched_kw=
 
 
 def backward(params: torch.Tensor, f: dict, dL_drgb: torch.Tensor, bg=(0.0, 0.0, 0.0), sched=None):
+    """Render backward, then transformation backward; returns (grad, record grads)."""
     grad = torch.zeros_like(params)
-    dproj = R.gs_render_bwd(params, f["proj"], f["bins"], f["cams"], f["T"], f["last"], dL_drgb, grad, bg,
-                            sched=sched)
+    dproj = R.gs_render_bwd_pixels(f["proj"], f["n"], f["bins"], f["cams"], f["T"], f["last"], dL_drgb, bg=bg,
+                                   sched=sched)
+    R.gs_project_bwd(params, f["cams"], f["proj"], dproj, grad, clear=False)
     torch.cuda.synchronize()
     return grad, dproj
 

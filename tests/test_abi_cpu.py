@@ -54,7 +54,7 @@ def test_host_side_sizes_and_argument_checks():
     assert L.gs_project(9, None, 10, None, p, 1, None, None) == _lib.GS_ERR_ARG
     assert L.gs_project(_lib.GS_F32, None, 10, None, p, 1, None, None) == _lib.GS_ERR_ARG
     assert b"null" in L.gs_last_error()
-    assert L.gs_adam_step(_lib.GS_F32, None, None, None, None, 5, None, None, None, None) == _lib.GS_ERR_ARG
+    assert L.gs_adam_step(_lib.GS_F32, None, None, None, None, 5, None, None, None, None, None) == _lib.GS_ERR_ARG
     cams[1].fx = -1.0
     assert L.gs_total_tiles(p, 2) == -1
 

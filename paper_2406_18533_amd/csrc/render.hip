@@ -57,22 +57,102 @@ template <typename T, int CHUNK> struct Stage {
     V4<T> b[CHUNK];    // conic a, b, c, -
     V4<T> c[CHUNK];    // r, g, b, -
     uint32_t id[CHUNK];
+    uint32_t pos[CHUNK];   // position of the record in the tile's list
+    uint32_t wcnt[4];
 };
 
-template <typename T, int CHUNK, int NT>
-__device__ __forceinline__ void stage_records(Stage<T, CHUNK> &st, const T *__restrict__ proj, int64_t vbase,
-                                              const uint32_t *__restrict__ ids, int64_t first, int cnt)
+// Minimum over the box [lx, hx] x [ly, hy] of the quadratic form
+// a dx^2 + 2 b dx dy + c dy^2 (positive definite), with (dx, dy) measured from
+// the centre (u, v); 0 if the centre is inside the box.
+template <typename T>
+__device__ __forceinline__ T box_min_quadratic(T lx, T hx, T ly, T hy, T a, T b, T c)
 {
-    for (int q = threadIdx.x; q < cnt; q += NT) {
-        uint32_t id = ids[first + q];
-        const V4<T> *rec = reinterpret_cast<const V4<T> *>(proj + (vbase + id) * REC);
-        V4<T> r0 = rec[0], r1 = rec[1], r2 = rec[2];
-        T rad = r2.y;
-        st.a[q] = V4<T>{r0.x, r0.y, rad * rad, r1.y};
-        st.b[q] = V4<T>{r0.z, r0.w, r1.x, T(0)};
-        st.c[q] = V4<T>{r1.z, r1.w, r2.x, T(0)};
-        st.id[q] = id;
+    if (lx <= T(0) && hx >= T(0) && ly <= T(0) && hy >= T(0)) return T(0);
+    auto edge_x = [&](T dx) {        // dx fixed, dy free in [ly, hy]
+        T dy = fmin(fmax(-b * dx / c, ly), hy);
+        return a * dx * dx + T(2) * b * dx * dy + c * dy * dy;
+    };
+    auto edge_y = [&](T dy) {        // dy fixed, dx free in [lx, hx]
+        T dx = fmin(fmax(-b * dy / a, lx), hx);
+        return a * dx * dx + T(2) * b * dx * dy + c * dy * dy;
+    };
+    return fmin(fmin(edge_x(lx), edge_x(hx)), fmin(edge_y(ly), edge_y(hy)));
+}
+
+// Conservative test that a record cannot reach alpha >= 1/255 inside its
+// footprint circle at any pixel centre of the tile whose centres span
+// [bx0, bx1] x [by0, by1]. A pixel keeps a Gaussian only if its centre is
+// within the radius and o exp(-q/2) >= 1/255 with q the conic's quadratic
+// form; the test culls when the circle misses the whole box, or when the
+// box minimum of q already gives alpha below 1/255 by a margin that bounds
+// the rounding of the per-pixel evaluation (16 FP32 ulps of the largest
+// term a dx^2 + c dy^2 over the box, plus 0.01). A culled record is thus
+// skipped at every pixel anyway and the image is unchanged.
+template <typename T>
+__device__ __forceinline__ bool tile_culls(T bx0, T bx1, T by0, T by1, T u, T v, T r2, T a, T b, T c, T o)
+{
+    if (o < K<T>::alpha_min) return true;                        // alpha <= opacity everywhere
+    T lx = bx0 - u, hx = bx1 - u, ly = by0 - v, hy = by1 - v;
+    T ex = fmax(fmax(lx, -hx), T(0)), ey = fmax(fmax(ly, -hy), T(0));
+    if (ex * ex + ey * ey > r2 * T(1.001) + T(0.01)) return true;  // circle misses every centre
+    T qmin = box_min_quadratic(lx, hx, ly, hy, a, b, c);
+    T dmax2 = fmax(lx * lx, hx * hx) + fmax(ly * ly, hy * hy);
+    T margin = T(0.01) + T(1e-6) * (a + c) * dmax2;
+    return T(0.5) * qmin > log(o * T(255)) + margin;
+}
+
+// Stages the records of list positions [first, first + cnt) that can touch
+// the tile, compacted in list order; returns how many were kept.
+template <typename T, int CHUNK, int NT>
+__device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__restrict__ proj, int64_t vbase,
+                                             const uint32_t *__restrict__ ids, int64_t first, int cnt,
+                                             uint32_t pos0, T bx0, T by0)
+{
+    constexpr int NW = NT / 64;
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t lt = (1ull << lane) - 1ull;
+    int kept = 0;
+    for (int r0 = 0; r0 < cnt; r0 += NT) {
+        int q = r0 + threadIdx.x;
+        bool keep = false;
+        V4<T> sa, sb, sc;
+        uint32_t id = 0;
+        if (q < cnt) {
+            id = ids[first + q];
+            const V4<T> *rec = reinterpret_cast<const V4<T> *>(proj + (vbase + id) * REC);
+            V4<T> r0v = rec[0], r1 = rec[1], r2 = rec[2];
+            T rad = r2.y;
+            sa = V4<T>{r0v.x, r0v.y, rad * rad, r1.y};
+            sb = V4<T>{r0v.z, r0v.w, r1.x, T(0)};
+            sc = V4<T>{r1.z, r1.w, r2.x, T(0)};
+            keep = !tile_culls(bx0, bx0 + T(15), by0, by0 + T(15), sa.x, sa.y, sa.z, sb.x, sb.y, sb.z, sa.w);
+        }
+        uint64_t m = __ballot(keep);
+        int off = kept;
+        if (NW > 1) {
+            if (lane == 0) st.wcnt[w] = (uint32_t)__popcll(m);
+            __syncthreads();
+            int tot = 0;
+            for (int j = 0; j < NW; j++) {
+                int c = (int)st.wcnt[j];
+                if (j < w) off += c;
+                tot += c;
+            }
+            __syncthreads();
+            kept += tot;
+        } else {
+            kept += __popcll(m);
+        }
+        if (keep) {
+            int slot = off + __popcll(m & lt);
+            st.a[slot] = sa;
+            st.b[slot] = sb;
+            st.c[slot] = sc;
+            st.id[slot] = id;
+            st.pos[slot] = pos0 + (uint32_t)q;
+        }
     }
+    return kept;
 }
 
 // ------------------------------------------------------------------ forward tile
@@ -105,14 +185,15 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
     int64_t vbase = (int64_t)v * A.n;
     uint32_t walked = 0;
     if (threadIdx.x == 0) *s_red = 0;
+    T bx0 = (T)(tx * TILE) + T(0.5), by0 = (T)(ty * TILE) + T(0.5);
     for (uint32_t base = s; base < e; base += CHUNK) {
         int cnt = (int)min((uint32_t)CHUNK, e - base);
         __syncthreads();
-        stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, base, cnt);
+        int kept = stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, base, cnt, base - s, bx0, by0);
         __syncthreads();
         bool alldone = true;
         for (int j = 0; j < PX; j++) alldone &= done[j];
-        for (int q = 0; q < cnt && !alldone; q++) {
+        for (int q = 0; q < kept && !alldone; q++) {
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q];
             alldone = true;
             for (int j = 0; j < PX; j++) {
@@ -130,7 +211,7 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
                         C[j][1] += rc.y * w;
                         C[j][2] += rc.z * w;
                         Tr[j] = Tn;
-                        lastp[j] = base - s + q + 1;
+                        lastp[j] = st.pos[q] + 1;
                     }
                 }
                 alldone &= done[j];
@@ -212,14 +293,15 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     uint32_t Lmax = *s_red;
     uint32_t s = A.ranges[2 * (int64_t)g];
     int64_t vbase = (int64_t)v * A.n;
+    T bx0 = (T)(tx * TILE) + T(0.5), by0 = (T)(ty * TILE) + T(0.5);
     for (int64_t hi = Lmax; hi > 0; hi -= CHUNK) {
         int64_t lo = hi - CHUNK > 0 ? hi - CHUNK : 0;
         int cnt = (int)(hi - lo);
         __syncthreads();
-        stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, (int64_t)s + lo, cnt);
+        int kept = stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, (int64_t)s + lo, cnt, (uint32_t)lo, bx0, by0);
         __syncthreads();
-        for (int q = cnt - 1; q >= 0; q--) {
-            uint32_t k = (uint32_t)(lo + q);
+        for (int q = kept - 1; q >= 0; q--) {
+            uint32_t k = st.pos[q];
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q];
             T acc[9];
             for (int c = 0; c < 9; c++) acc[c] = T(0);

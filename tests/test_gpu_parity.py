@@ -56,9 +56,22 @@ def small_multiview():
     return P, cams
 
 
+def needles():
+    """Long thin footprints (one axis 55x the others) crossing many tiles:
+    stresses the per-tile culling of staged records."""
+    P = scenes.uniform_cube_gaussians(3000, 8)
+    gen = torch.Generator().manual_seed(18)
+    P[3] = -1.5 + 0.2 * torch.randn(3000, generator=gen)
+    P[4:6] = -5.5 + 0.2 * torch.randn(2, 3000, generator=gen)
+    P[10] = 1.0 + torch.randn(3000, generator=gen)
+    cams = [scenes.orbit_camera(128, 96, 3.5, 0.7, 0.4), scenes.orbit_camera(96, 128, 3.0, 2.2, -0.2)]
+    return P, cams
+
+
 WORKLOADS = {
     "single_view_256": lambda: (scenes.plain_single_view().params, scenes.plain_single_view().cameras),
     "ragged_3_views": small_multiview,
+    "needles": needles,
 }
 
 

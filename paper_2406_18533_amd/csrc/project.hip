@@ -30,9 +30,10 @@ template <typename T> __device__ __forceinline__ Camera<T> load_camera(const gs_
     return k;
 }
 
-// View-independent part: scale, rotation, 3D covariance, opacity.
+// View-independent part: scale, rotation, opacity and the factor
+// M = R(q) diag(s) of the 3D covariance Sigma = M M^T.
 template <typename T> struct Shape {
-    T s[3], q[4], qn, Rq[9], Sig[6];  // Sig: 00 01 02 11 12 22
+    T s[3], q[4], qn, Rq[9], M[9];
     T opac;
     bool ok;
 };
@@ -62,22 +63,9 @@ __device__ __forceinline__ void make_shape(const T *P, int64_t n, int64_t i, Sha
     T iq = T(1) / S.qn;
     for (int j = 0; j < 4; j++) S.q[j] = qr[j] * iq;
     quat_matrix(S.q, S.Rq);
-    T M[9];
     for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
-    const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
-    for (int e = 0; e < 6; e++) {
-        int r = rr[e], c = cc[e];
-        S.Sig[e] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
-    }
+        for (int c = 0; c < 3; c++) S.M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
     S.opac = T(1) / (T(1) + exp(-logit));
-}
-
-template <typename T> __device__ __forceinline__ T sig_at(const T Sig[6], int r, int c)
-{
-    // full symmetric 3x3 from the 6 stored entries
-    const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
-    return Sig[idx[3 * r + c]];
 }
 
 // Per-view geometry of one Gaussian.
@@ -86,6 +74,7 @@ template <typename T> struct Geo {
     bool xi_cl, eta_cl;
     T J00, J02, J11, J12;
     T Tm[6];
+    T N[6];           // Tm M: the screen covariance is N N^T + 0.3 I
     T A, B, C, det;
     T u, v, conic[3], radius;
     bool visible;   // in front of znear, finite
@@ -117,27 +106,30 @@ __device__ __forceinline__ void make_geo(const T x[3], const Shape<T> &S, const 
         g.Tm[c] = g.J00 * k.R[c] + g.J02 * k.R[6 + c];
         g.Tm[3 + c] = g.J11 * k.R[3 + c] + g.J12 * k.R[6 + c];
     }
-    // S' = Tm Sig Tm^T
-    T TS[6];
+    // Screen covariance N N^T + 0.3 I with N = Tm M (2x3). Its entries and
+    // determinant are formed as sums of squares (Lagrange identity
+    // |n0|^2 |n1|^2 - (n0.n1)^2 = |n0 x n1|^2), so thin footprints keep
+    // their FP32 accuracy.
     for (int r = 0; r < 2; r++)
         for (int c = 0; c < 3; c++)
-            TS[3 * r + c] = g.Tm[3 * r] * sig_at(S.Sig, 0, c) + g.Tm[3 * r + 1] * sig_at(S.Sig, 1, c) +
-                            g.Tm[3 * r + 2] * sig_at(S.Sig, 2, c);
-    T s00 = TS[0] * g.Tm[0] + TS[1] * g.Tm[1] + TS[2] * g.Tm[2];
-    T s01 = TS[0] * g.Tm[3] + TS[1] * g.Tm[4] + TS[2] * g.Tm[5];
-    T s11 = TS[3] * g.Tm[3] + TS[4] * g.Tm[4] + TS[5] * g.Tm[5];
-    g.A = s00 + T(0.3);
-    g.B = s01;
-    g.C = s11 + T(0.3);
-    g.det = g.A * g.C - g.B * g.B;
+            g.N[3 * r + c] = g.Tm[3 * r] * S.M[c] + g.Tm[3 * r + 1] * S.M[3 + c] + g.Tm[3 * r + 2] * S.M[6 + c];
+    const T *n0 = g.N, *n1 = g.N + 3;
+    T a0 = n0[0] * n0[0] + n0[1] * n0[1] + n0[2] * n0[2];
+    T c0 = n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2];
+    T b0 = n0[0] * n1[0] + n0[1] * n1[1] + n0[2] * n1[2];
+    T x0 = n0[1] * n1[2] - n0[2] * n1[1], x1 = n0[2] * n1[0] - n0[0] * n1[2], x2 = n0[0] * n1[1] - n0[1] * n1[0];
+    g.A = a0 + T(0.3);
+    g.B = b0;
+    g.C = c0 + T(0.3);
+    g.det = (x0 * x0 + x1 * x1 + x2 * x2) + T(0.3) * (a0 + c0) + T(0.09);
     if (!(g.det > T(0)) || !finite(g.det)) return;
     T id = T(1) / g.det;
     g.conic[0] = g.C * id;
     g.conic[1] = -g.B * id;
     g.conic[2] = g.A * id;
     T mid = T(0.5) * (g.A + g.C);
-    T disc = mid * mid - g.det;
-    T lmax = mid + sqrt(disc > T(0) ? disc : T(0));
+    T hd = T(0.5) * (g.A - g.C);
+    T lmax = mid + sqrt(hd * hd + g.B * g.B);
     g.radius = ceil(T(3) * sqrt(lmax));
     if (!finite(g.radius) || !finite(g.u) || !finite(g.v)) return;
     g.visible = true;
@@ -281,7 +273,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
     T x[3] = {P[i], P[n + i], P[2 * n + i]};
     Shape<T> S;
     make_shape(P, n, i, S);
-    T gmean[3] = {0, 0, 0}, gS[6] = {0, 0, 0, 0, 0, 0}, gop = T(0);
+    T gmean[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = T(0);
     T gsh[48];
     for (int j = 0; j < 48; j++) gsh[j] = T(0);
     for (int v = 0; v < views; v++) {
@@ -309,27 +301,20 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
         T dA = -da * g.C * g.C * id2 + db * g.B * g.C * id2 - dc * g.B * g.B * id2;
         T dB = T(2) * da * g.B * g.C * id2 + db * (-id - T(2) * g.B * g.B * id2) + T(2) * dc * g.A * g.B * id2;
         T dC = -da * g.B * g.B * id2 + db * g.A * g.B * id2 - dc * g.A * g.A * id2;
-        // S'00 = t0 Sig t0^T, S'01 = t0 Sig t1^T, S'11 = t1 Sig t1^T (t0, t1 rows of Tm)
-        T SigT0[3], SigT1[3];
-        for (int m = 0; m < 3; m++) {
-            SigT0[m] = sig_at(S.Sig, m, 0) * g.Tm[0] + sig_at(S.Sig, m, 1) * g.Tm[1] + sig_at(S.Sig, m, 2) * g.Tm[2];
-            SigT1[m] = sig_at(S.Sig, m, 0) * g.Tm[3] + sig_at(S.Sig, m, 1) * g.Tm[4] + sig_at(S.Sig, m, 2) * g.Tm[5];
+        // A = |n0|^2 + 0.3, B = n0.n1, C = |n1|^2 + 0.3 with N = Tm M:
+        // dN0 = 2 dA n0 + dB n1, dN1 = dB n0 + 2 dC n1; dTm = dN M^T, dM += Tm^T dN
+        T dN[6];
+        for (int c = 0; c < 3; c++) {
+            dN[c] = T(2) * dA * g.N[c] + dB * g.N[3 + c];
+            dN[3 + c] = dB * g.N[c] + T(2) * dC * g.N[3 + c];
         }
         T dT0[3], dT1[3];
-        for (int m = 0; m < 3; m++) {
-            dT0[m] = T(2) * dA * SigT0[m] + dB * SigT1[m];
-            dT1[m] = T(2) * dC * SigT1[m] + dB * SigT0[m];
+        for (int c = 0; c < 3; c++) {
+            dT0[c] = dN[0] * S.M[3 * c] + dN[1] * S.M[3 * c + 1] + dN[2] * S.M[3 * c + 2];
+            dT1[c] = dN[3] * S.M[3 * c] + dN[4] * S.M[3 * c + 1] + dN[5] * S.M[3 * c + 2];
         }
-        // dSig (symmetric, stored as the 6 unique entries with off-diagonals summed)
-        {
-            const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
-            for (int e = 0; e < 6; e++) {
-                int m = rr[e], q = cc[e];
-                T val = dA * g.Tm[m] * g.Tm[q] + dC * g.Tm[3 + m] * g.Tm[3 + q] +
-                        T(0.5) * dB * (g.Tm[m] * g.Tm[3 + q] + g.Tm[q] * g.Tm[3 + m]);
-                gS[e] += (m == q) ? val : T(2) * val;
-            }
-        }
+        for (int c = 0; c < 3; c++)
+            for (int k2 = 0; k2 < 3; k2++) gM[3 * c + k2] += g.Tm[c] * dN[k2] + g.Tm[3 + c] * dN[3 + k2];
         // Tm = J R
         T dJ00 = dT0[0] * k.R[0] + dT0[1] * k.R[1] + dT0[2] * k.R[2];
         T dJ02 = dT0[0] * k.R[6] + dT0[1] * k.R[7] + dT0[2] * k.R[8];
@@ -352,8 +337,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
         for (int k2 = 0; k2 < 16; k2++) w[k2] = T(0);
         bool any = false;
         for (int ch = 0; ch < 3; ch++) {
-            T raw = T(0.5);
+            T raw = T(0);   // same summation order as the forward, so the clamp mask agrees
             for (int k2 = 0; k2 < 16; k2++) raw += P[(11 + 3 * k2 + ch) * n + i] * Y[k2];
+            raw += T(0.5);
             if (!(raw > T(0))) continue;
             any = true;
             for (int k2 = 0; k2 < 16; k2++) {
@@ -369,23 +355,8 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
             for (int c = 0; c < 3; c++) gmean[c] += (gd[c] - dir[c] * dd) * idn;
         }
     }
-    // Sig = Rq diag(s^2) Rq^T -> scale and rotation
-    T dM[9];
-    {
-        // dL/dM = (dSig + dSig^T) M with dSig the full symmetric gradient
-        T M[9];
-        for (int r = 0; r < 3; r++)
-            for (int c = 0; c < 3; c++) M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
-        T Gs[9];
-        const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
-        for (int e = 0; e < 9; e++) {
-            int r = e / 3, c = e % 3;
-            Gs[e] = (r == c) ? gS[idx[e]] : T(0.5) * gS[idx[e]];
-        }
-        for (int r = 0; r < 3; r++)
-            for (int c = 0; c < 3; c++)
-                dM[3 * r + c] = T(2) * (Gs[3 * r] * M[c] + Gs[3 * r + 1] * M[3 + c] + Gs[3 * r + 2] * M[6 + c]);
-    }
+    // M = Rq diag(s) -> scale and rotation
+    const T *dM = gM;
     T gls[3], dRq[9];
     for (int c = 0; c < 3; c++) {
         T acc = T(0);

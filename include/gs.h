@@ -129,7 +129,8 @@ const char *gs_last_error(void);
 gs_status gs_init(int32_t device);
 
 /* ------------------------------------------------------------------ sizes */
-/* Bytes of a projected-record buffer: views * n records of GS_REC scalars. */
+/* Bytes of a projected buffer: views * n records of GS_REC scalars, then two
+ * planar uint32 side arrays [views][n]: tiles touched and FP32 depth bits. */
 size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views);
 /* Sum over the views of ceil(W/16) * ceil(H/16) [host cameras]. */
 int64_t gs_total_tiles(const gs_camera *cams_host, int32_t views);
@@ -151,7 +152,10 @@ size_t gs_loss_workspace_bytes(const gs_camera *cams_host, int32_t views);
  * (its x/z, y/z clamped to 1.3x the half field of view); radius =
  * ceil(3 sqrt(largest eigenvalue)); rgb = max(0, SH(direction) + 1/2).
  * A record with radius 0 is culled (behind znear or non-finite); then only
- * radius and tiles touched (0) are defined.
+ * radius and tiles touched (0) are defined; rgb is computed only for records
+ * with tiles touched > 0. After the records the buffer holds tiles touched
+ * and the FP32 bits of depth of every (view, Gaussian) as planar uint32
+ * arrays (see gs_projected_bytes).
  * params: [59][n]. cams_dev: [views] cameras in device memory (read by the
  * kernel, so a captured graph sees updated poses); cams_host: the same
  * cameras [host] (image sizes). Requires 1 <= views <= GS_MAX_VIEWS,

@@ -25,7 +25,8 @@ hipError_t launch_render_fwd(const ViewTable &, const void *, int64_t, const gs_
 template <typename T>
 hipError_t launch_render_bwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                              const LaunchShape &, const void *, const uint32_t *, const void *, void *, hipStream_t);
-hipError_t launch_plan(const uint32_t *, int32_t, int32_t, uint64_t *, int32_t *, int32_t *, int32_t *, hipStream_t);
+hipError_t launch_plan(const uint32_t *, int32_t, int32_t, uint64_t *, uint64_t *, int32_t *, int32_t *, int32_t *,
+                       hipStream_t);
 template <typename T>
 hipError_t launch_adam(void *, void *, void *, void *, int64_t, const gs_adam_hparams *, int64_t *, double *,
                        const int32_t *, hipStream_t);
@@ -132,7 +133,7 @@ gs_status gs_init(int32_t device)
 size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views)
 {
     if (n < 0 || views < 0 || !dtype_ok(dtype)) return 0;
-    return (size_t)n * (size_t)views * GS_REC * (dtype == GS_F64 ? 8 : 4);
+    return (size_t)n * (size_t)views * (GS_REC * (dtype == GS_F64 ? 8 : 4) + 8);
 }
 
 int64_t gs_total_tiles(const gs_camera *cams, int32_t views)
@@ -156,10 +157,28 @@ size_t gs_bin_workspace_bytes(int64_t n, int32_t views, int64_t capacity, int64_
     return bin_ws_layout(n * views, capacity, nullptr, nullptr);
 }
 
+// Scheduler workspace: cursor[Q] | dp[Q + 1] | ct[T] (uint64) | scan partials, each 256-byte aligned.
+struct SchedWS {
+    size_t cursor, dp, ct, partial, total;
+};
+
+static SchedWS sched_ws(int64_t total_tiles, int32_t q)
+{
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    SchedWS w;
+    size_t t = (size_t)(total_tiles > 0 ? total_tiles : 1);
+    w.cursor = 0;
+    w.dp = al(4 * (size_t)q);
+    w.ct = w.dp + al(4 * ((size_t)q + 1));
+    w.partial = w.ct + al(8 * t);
+    w.total = w.partial + al(8 * (t / 4096 + 8));
+    return w;
+}
+
 size_t gs_sched_workspace_bytes(int64_t total_tiles, int32_t queues)
 {
     if (queues <= 0) queues = 64;
-    return 256 + (size_t)8 * (size_t)(total_tiles > 0 ? total_tiles : 1) + (size_t)4 * (2 * (size_t)queues + 1) + 256;
+    return sched_ws(total_tiles, queues).total;
 }
 
 size_t gs_loss_workspace_bytes(const gs_camera *cams, int32_t views)
@@ -254,9 +273,10 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
         }
         if (sc->workers < 0 || sc->workers % 8 != 0) { why = "workers must be a multiple of 8"; return false; }
         char *w = (char *)sc->workspace;
+        SchedWS L = sched_ws(total_tiles, q);
         sh.S.queues = q;
-        sh.S.cursor = (int32_t *)(w);
-        sh.S.dp = (int32_t *)(w + ((4 * (size_t)q + 255) & ~(size_t)255));
+        sh.S.cursor = (int32_t *)(w + L.cursor);
+        sh.S.dp = (int32_t *)(w + L.dp);
         int wk = sc->workers;
         if (wk == 0) wk = cu_count() * 8 * sh.px;  // about 32 wavefronts per CU
         sh.workers = wk;
@@ -264,17 +284,13 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     return true;
 }
 
-static uint64_t *sched_ct(const gs_sched *sc)
-{
-    int q = sc->queues > 0 ? sc->queues : 64;
-    size_t off = ((4 * (size_t)q + 255) & ~(size_t)255) + ((4 * (size_t)(q + 1) + 255) & ~(size_t)255);
-    return (uint64_t *)((char *)sc->workspace + off);
-}
-
 static hipError_t run_plan(const gs_sched *sc, const LaunchShape &sh, int32_t total_tiles, int32_t *dp_out,
                            hipStream_t s)
 {
-    return launch_plan(sc->tile_cost, total_tiles, sh.S.queues, sched_ct(sc), sh.S.dp, sh.S.cursor, dp_out, s);
+    SchedWS L = sched_ws(total_tiles, sh.S.queues);
+    char *w = (char *)sc->workspace;
+    return launch_plan(sc->tile_cost, total_tiles, sh.S.queues, (uint64_t *)(w + L.ct), (uint64_t *)(w + L.partial),
+                       sh.S.dp, sh.S.cursor, dp_out, s);
 }
 
 gs_status gs_sched_plan(const gs_sched *sched, const gs_camera *cams_host, int32_t views, int32_t *dp_out, void *stream)

@@ -128,28 +128,26 @@ static hipError_t device_scan(Load load, Store store, const int64_t *n_dev, int6
 }
 
 // ---------------------------------------------------------------- functors
-template <typename T> struct FlagLoad {
-    const T *proj;
-    __device__ uint32_t operator()(int64_t f) const { return proj[f * REC + R_TILES] > T(0) ? 1u : 0u; }
+struct FlagLoad {
+    const uint32_t *tiles;
+    __device__ uint32_t operator()(int64_t f) const { return tiles[f] > 0u ? 1u : 0u; }
 };
 
-__device__ __forceinline__ uint32_t depth_bits(float d) { return __float_as_uint(d); }
-
-template <typename T> struct CompactStore {
-    const T *proj;
+struct CompactStore {
+    const uint32_t *depth;
     uint32_t *keys, *vals;
     __device__ void operator()(int64_t f, uint32_t pos, uint32_t flag) const
     {
         if (!flag) return;
-        keys[pos] = depth_bits((float)proj[f * REC + R_DEPTH]);
+        keys[pos] = depth[f];
         vals[pos] = (uint32_t)f;
     }
 };
 
-template <typename T> struct CountLoad {
-    const T *proj;
+struct CountLoad {
+    const uint32_t *tiles;
     const uint32_t *flat;
-    __device__ uint64_t operator()(int64_t j) const { return (uint64_t)proj[(int64_t)flat[j] * REC + R_TILES]; }
+    __device__ uint64_t operator()(int64_t j) const { return (uint64_t)tiles[flat[j]]; }
 };
 
 struct U64Store {
@@ -343,32 +341,57 @@ static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uin
 }
 
 // ---------------------------------------------------------------- emit and ranges
+// One block emits the instances of 256 consecutive depth-sorted pairs: their
+// offsets and tile rectangles go to LDS, then every thread writes one
+// instance at a time (coalesced), finding its pair by binary search over the
+// block's offsets and its tile from the position inside the pair's rectangle.
 template <typename T>
 __global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, int64_t n, ViewTable vt,
                                                    const uint32_t *__restrict__ flat, const uint64_t *__restrict__ off,
-                                                   const int64_t *m_dev, int64_t m_max, uint32_t *__restrict__ tile_out,
-                                                   uint32_t *__restrict__ id_out, int64_t capacity)
+                                                   const int64_t *m_dev, int64_t m_max, const int64_t *k_dev,
+                                                   uint32_t *__restrict__ tile_out, uint32_t *__restrict__ id_out,
+                                                   int64_t capacity)
 {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint64_t s_off[257];
+    __shared__ uint32_t s_x0[256], s_w[256], s_y0[256], s_base[256], s_tx[256], s_id[256];
     int64_t m = count_of(m_dev, m_max);
-    if (j >= m) return;
-    uint32_t f = flat[j];
-    uint32_t v = f / (uint32_t)n;
-    uint32_t i = f - v * (uint32_t)n;
-    const T *rec = proj + (int64_t)f * REC;
-    TileRect r;
-    if (!tile_rect((float)rec[R_U], (float)rec[R_V], (float)rec[R_RADIUS], vt.width[v], vt.height[v], r)) return;
-    uint64_t o = off[j];
-    uint32_t tb = (uint32_t)vt.tile_base[v];
-    uint32_t tx = (uint32_t)vt.tiles_x[v];
-    for (int ty = r.y0; ty <= r.y1; ty++)
-        for (int tx2 = r.x0; tx2 <= r.x1; tx2++) {
-            if (o < (uint64_t)capacity) {
-                tile_out[o] = tb + (uint32_t)ty * tx + (uint32_t)tx2;
-                id_out[o] = i;
-            }
-            o++;
+    int64_t j0 = (int64_t)blockIdx.x * 256;
+    if (j0 >= m) return;
+    int64_t j = j0 + threadIdx.x;
+    int cnt = (int)(m - j0 < 256 ? m - j0 : 256);
+    if (j < m) {
+        uint32_t f = flat[j];
+        uint32_t v = f / (uint32_t)n;
+        uint32_t i = f - v * (uint32_t)n;
+        const T *rec = proj + (int64_t)f * REC;
+        TileRect r;
+        if (!tile_rect((float)rec[R_U], (float)rec[R_V], (float)rec[R_RADIUS], vt.width[v], vt.height[v], r))
+            r.x0 = r.x1 = r.y0 = r.y1 = 0;   // not reached: compacted pairs touch at least one tile
+        s_off[threadIdx.x] = off[j];
+        s_x0[threadIdx.x] = (uint32_t)r.x0;
+        s_w[threadIdx.x] = (uint32_t)(r.x1 - r.x0 + 1);
+        s_y0[threadIdx.x] = (uint32_t)r.y0;
+        s_base[threadIdx.x] = (uint32_t)vt.tile_base[v];
+        s_tx[threadIdx.x] = (uint32_t)vt.tiles_x[v];
+        s_id[threadIdx.x] = i;
+    }
+    if (threadIdx.x == 0) s_off[256] = (j0 + 256 < m) ? off[j0 + 256] : (uint64_t)*k_dev;
+    __syncthreads();
+    uint64_t e_beg = s_off[0], e_end = s_off[256];
+    if (e_end > (uint64_t)capacity) e_end = (uint64_t)capacity;
+    for (uint64_t e = e_beg + threadIdx.x; e < e_end; e += 256) {
+        int lo = 0, hi = cnt - 1;     // last pair with s_off <= e
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= e) lo = mid;
+            else hi = mid - 1;
         }
+        uint32_t local = (uint32_t)(e - s_off[lo]);
+        uint32_t w = s_w[lo];
+        uint32_t dy = local / w, dx = local - dy * w;
+        tile_out[e] = s_base[lo] + (s_y0[lo] + dy) * s_tx[lo] + s_x0[lo] + dx;
+        id_out[e] = s_id[lo];
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
@@ -402,8 +425,8 @@ __global__ void keys64_kernel(const T *__restrict__ proj, int64_t n, ViewTable v
     if (k >= count_of(k_dev, cap)) return;
     uint32_t t = tiles[k];
     int v = view_of_tile(vt, (int32_t)t);
-    float d = (float)proj[((int64_t)v * n + ids[k]) * REC + R_DEPTH];
-    out[k] = ((uint64_t)t << 32) | (uint64_t)__float_as_uint(d);
+    const uint32_t *depth = side_depth<T>(proj, (int64_t)vt.nviews * n);
+    out[k] = ((uint64_t)t << 32) | (uint64_t)depth[(int64_t)v * n + ids[k]];
 }
 
 // ---------------------------------------------------------------- workspace
@@ -456,15 +479,16 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
     // ranges start empty
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((2 * T_all + 255) / 256)), dim3(256), 0, s, b->ranges,
                        2 * T_all, 0u);
+    const uint32_t *tiles = side_tiles<T>(proj, vn), *depth = side_depth<T>(proj, vn);
     // 1. compaction of pairs that touch a tile
-    e = device_scan<uint32_t>(FlagLoad<T>{proj}, CompactStore<T>{proj, ws.k1, ws.v1}, nullptr, vn,
+    e = device_scan<uint32_t>(FlagLoad{tiles}, CompactStore{depth, ws.k1, ws.v1}, nullptr, vn,
                               (uint32_t *)ws.partial, ws.m_dev, s);
     if (e != hipSuccess) return e;
     // 2. stable sort by FP32 depth bits (positive depths: 31 significant bits)
     e = radix_sort(ws.k1, ws.v1, ws.k1b, ws.v1b, ws.m_dev, vn, 32, ws.hist, (uint32_t *)ws.partial, s);
     if (e != hipSuccess) return e;
     // 3. instance offsets in depth order
-    e = device_scan<uint64_t>(CountLoad<T>{proj, ws.v1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
+    e = device_scan<uint64_t>(CountLoad{tiles, ws.v1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap, b->overflow);
     if (check) {
@@ -482,7 +506,7 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
     if (vn > 0)
         hipLaunchKernelGGL(emit_kernel<T>, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj, n, vt,
                            (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
-                           b->tile_keys, b->ids, cap);
+                           (const int64_t *)b->n_instances, b->tile_keys, b->ids, cap);
     // 5. stable sort by global tile id
     int bits = 1;
     while ((int64_t(1) << bits) < T_all) bits++;
@@ -514,6 +538,56 @@ template hipError_t launch_keys64<float>(const void *, int64_t, const ViewTable 
                                          hipStream_t);
 template hipError_t launch_keys64<double>(const void *, int64_t, const ViewTable &, const gs_bins *, uint64_t *,
                                           hipStream_t);
+
+// ---------------------------------------------------------------- Algorithm 1
+// Division points of the serialised tiles into Q cost-balanced chunks
+// (Algorithm 1): CT = cumsum(ET) with ET_j = cost_j + 1 (a tile costs at
+// least its fixed overhead), thresholds q * CT[last] / Q, DP[q] = first j
+// with CT[j] >= threshold (left searchsorted), DP[Q] = T. Also resets the
+// per-chunk cursors of the persistent render kernels.
+struct CostLoad {
+    const uint32_t *cost;
+    __device__ uint64_t operator()(int64_t j) const { return (cost ? (uint64_t)cost[j] : 0ull) + 1ull; }
+};
+
+struct InclStore {
+    uint64_t *ct;
+    __device__ void operator()(int64_t j, uint64_t excl, uint64_t x) const { ct[j] = excl + x; }
+};
+
+__global__ void division_points_kernel(const uint64_t *__restrict__ ct, int32_t T_all, int32_t Q,
+                                       int32_t *__restrict__ dp, int32_t *__restrict__ cursor,
+                                       int32_t *__restrict__ dp_out)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > Q) return;
+    int32_t r;
+    if (q == Q) r = T_all;
+    else {
+        double th = (double)q * ((double)ct[T_all - 1] / (double)Q);
+        int32_t lo = 0, hi = T_all;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if ((double)ct[mid] < th) lo = mid + 1;
+            else hi = mid;
+        }
+        r = lo;
+    }
+    dp[q] = r;
+    if (q < Q) cursor[q] = r;
+    if (dp_out) dp_out[q] = r;
+}
+
+hipError_t launch_plan(const uint32_t *cost, int32_t T_all, int32_t Q, uint64_t *ct, uint64_t *partial, int32_t *dp,
+                       int32_t *cursor, int32_t *dp_out, hipStream_t s)
+{
+    if (T_all <= 0) return hipSuccess;
+    hipError_t e = device_scan<uint64_t>(CostLoad{cost}, InclStore{ct}, nullptr, T_all, partial, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(division_points_kernel, dim3((unsigned)((Q + 256) / 256)), dim3(256), 0, s,
+                       (const uint64_t *)ct, T_all, Q, dp, cursor, dp_out);
+    return hipGetLastError();
+}
 
 // Exposed for the scheduler (cumulative tile cost).
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)

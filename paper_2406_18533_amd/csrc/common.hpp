@@ -17,6 +17,19 @@ enum : int { R_U = 0, R_V = 1, R_A = 2, R_B = 3, R_C = 4, R_OPAC = 5, R_RGB = 6,
 // Slots of a projected-gradient entry.
 enum : int { D_U = 0, D_V = 1, D_A = 2, D_B = 3, D_C = 4, D_OPAC = 5, D_RGB = 6 };
 
+// The projected buffer holds the [views][n][REC] records followed by two
+// planar side arrays over the same (view, Gaussian) index: tiles touched
+// (uint32) and the FP32 bits of depth (uint32). Binning and the backward
+// read these 4-byte fields contiguously instead of one field per record.
+template <typename T> __host__ __device__ inline uint32_t *side_tiles(const void *proj, int64_t vn)
+{
+    return (uint32_t *)((char *)proj + vn * (int64_t)REC * (int64_t)sizeof(T));
+}
+template <typename T> __host__ __device__ inline uint32_t *side_depth(const void *proj, int64_t vn)
+{
+    return side_tiles<T>(proj, vn) + vn;
+}
+
 // Per-view image geometry, passed by value as a kernel argument.
 struct ViewTable {
     int32_t nviews;
@@ -88,24 +101,35 @@ template <> struct K<double> {
     static constexpr double t_min = 1e-4;
 };
 
-__device__ __forceinline__ float exp_t(float x) { return __expf(x); }
-__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+__device__ __forceinline__ float exp2_t(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double exp2_t(double x) { return exp2(x); }
+
+// Conic pre-scaled for the per-pixel exponent: with (na, nb, nc) =
+// -(a/2, b, c/2) log2(e), the Gaussian falloff exp(-(a dx^2 + c dy^2)/2 -
+// b dx dy) is exp2(na dx^2 + nb dx dy + nc dy^2).
+template <typename T> __device__ __forceinline__ void scaled_conic(T a, T b, T c, T &na, T &nb, T &nc)
+{
+    const T l2e = T(1.4426950408889634);
+    na = T(-0.5) * l2e * a;
+    nb = -l2e * b;
+    nc = T(-0.5) * l2e * c;
+}
 
 // One (pixel, Gaussian) pair: circle test, Gaussian falloff, alpha with
 // clamp and skip. Returns false if the Gaussian does not touch the pixel.
 // The forward and backward kernels both call this, so their decisions agree
 // bit for bit.
 template <typename T>
-__device__ __forceinline__ bool eval_alpha(T pxc, T pyc, T u, T v, T r2, T a, T b, T c, T o,
+__device__ __forceinline__ bool eval_alpha(T pxc, T pyc, T u, T v, T r2, T na, T nb, T nc, T o,
                                            T &dx, T &dy, T &G, T &og, T &alpha)
 {
     dx = pxc - u;
     dy = pyc - v;
-    T d2 = dx * dx + dy * dy;
+    T d2 = fma(dx, dx, dy * dy);
     if (d2 > r2) return false;
-    T power = T(-0.5) * (a * dx * dx + c * dy * dy) - b * dx * dy;
-    if (power > T(0)) return false;
-    G = exp_t(power);
+    T p2 = fma(na * dx, dx, fma(nc * dy, dy, (nb * dx) * dy));   // exponent in log2 units
+    if (p2 > T(0)) return false;
+    G = exp2_t(p2);
     og = o * G;
     alpha = og < K<T>::alpha_max ? og : K<T>::alpha_max;
     return !(alpha < K<T>::alpha_min);

@@ -212,11 +212,15 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
     else S.ok = false;
     S.ok = S.ok && xok;
     uint64_t need_colour = 0;
+    const int64_t vn = (int64_t)views * n;
+    uint32_t *tiles_out = side_tiles<T>(out, vn), *depth_out = side_depth<T>(out, vn);
     for (int v = 0; v < views; v++) {
         V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
         Camera<T> k = load_camera<T>(cams + v);
         Geo<T> g;
         make_geo(x, S, k, g);
+        tiles_out[(int64_t)v * n + i] = g.visible ? (uint32_t)g.tiles : 0u;
+        depth_out[(int64_t)v * n + i] = g.visible ? __float_as_uint((float)g.y[2]) : 0u;
         if (!g.visible) {
             rec[2] = V4<T>{T(0), T(0), T(0), T(0)};
             continue;
@@ -267,8 +271,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint64_t vis = 0;
+    const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
     for (int v = 0; v < views; v++)
-        if (proj[((int64_t)v * n + i) * REC + R_TILES] > T(0)) vis |= 1ull << v;
+        if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
     if (!vis) return;
     T x[3] = {P[i], P[n + i], P[2 * n + i]};
     Shape<T> S;

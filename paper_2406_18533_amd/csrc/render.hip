@@ -56,8 +56,10 @@ template <typename T, int CHUNK> struct Stage {
     V4<T> a[CHUNK];    // u, v, r^2, opacity
     V4<T> b[CHUNK];    // conic a, b, c, -
     V4<T> c[CHUNK];    // r, g, b, -
+    V4<T> d[CHUNK];    // scaled conic na, nb, nc (see scaled_conic), -
     uint32_t id[CHUNK];
     uint32_t pos[CHUNK];   // position of the record in the tile's list
+    uint32_t band[CHUNK];  // bit k: the record may touch pixel rows 4k..4k+3 of the tile
     uint32_t wcnt[4];
 };
 
@@ -102,7 +104,10 @@ __device__ __forceinline__ bool tile_culls(T bx0, T bx1, T by0, T by1, T u, T v,
 }
 
 // Stages the records of list positions [first, first + cnt) that can touch
-// the tile, compacted in list order; returns how many were kept.
+// the tile, compacted in list order, with a mask of the four 16x4 pixel
+// bands of the tile they can touch; returns how many were kept. A band is
+// exactly one wavefront's pixels in every launch shape, so the render loops
+// skip a band with a wave-uniform branch.
 template <typename T, int CHUNK, int NT>
 __device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__restrict__ proj, int64_t vbase,
                                              const uint32_t *__restrict__ ids, int64_t first, int cnt,
@@ -114,7 +119,7 @@ __device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__res
     int kept = 0;
     for (int r0 = 0; r0 < cnt; r0 += NT) {
         int q = r0 + threadIdx.x;
-        bool keep = false;
+        uint32_t bands = 0;
         V4<T> sa, sb, sc;
         uint32_t id = 0;
         if (q < cnt) {
@@ -125,8 +130,13 @@ __device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__res
             sa = V4<T>{r0v.x, r0v.y, rad * rad, r1.y};
             sb = V4<T>{r0v.z, r0v.w, r1.x, T(0)};
             sc = V4<T>{r1.z, r1.w, r2.x, T(0)};
-            keep = !tile_culls(bx0, bx0 + T(15), by0, by0 + T(15), sa.x, sa.y, sa.z, sb.x, sb.y, sb.z, sa.w);
+            if (!tile_culls(bx0, bx0 + T(15), by0, by0 + T(15), sa.x, sa.y, sa.z, sb.x, sb.y, sb.z, sa.w))
+                for (int k = 0; k < 4; k++)
+                    if (!tile_culls(bx0, bx0 + T(15), by0 + T(4 * k), by0 + T(4 * k + 3), sa.x, sa.y, sa.z, sb.x, sb.y,
+                                    sb.z, sa.w))
+                        bands |= 1u << k;
         }
+        bool keep = bands != 0;
         uint64_t m = __ballot(keep);
         int off = kept;
         if (NW > 1) {
@@ -145,11 +155,15 @@ __device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__res
         }
         if (keep) {
             int slot = off + __popcll(m & lt);
+            T na, nb, nc;
+            scaled_conic(sb.x, sb.y, sb.z, na, nb, nc);
             st.a[slot] = sa;
             st.b[slot] = sb;
             st.c[slot] = sc;
+            st.d[slot] = V4<T>{na, nb, nc, T(0)};
             st.id[slot] = id;
             st.pos[slot] = pos0 + (uint32_t)q;
+            st.band[slot] = bands;
         }
     }
     return kept;
@@ -160,6 +174,7 @@ template <typename T, int PX, int CHUNK, bool STATS>
 __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
 {
     uint32_t n_eval = 0, n_blend = 0;
+    const int wave_id = threadIdx.x >> 6;
     constexpr int NT = 256 / PX;
     int v = view_of_tile(vt, g);
     int local = g - vt.tile_base[v];
@@ -194,13 +209,16 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         bool alldone = true;
         for (int j = 0; j < PX; j++) alldone &= done[j];
         for (int q = 0; q < kept && !alldone; q++) {
-            V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q];
+            V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
+            uint32_t bm = st.band[q] >> wave_id;
             alldone = true;
             for (int j = 0; j < PX; j++) {
-                if (done[j]) continue;
+                bool skip = done[j] || !((bm >> (j * (NT / 64))) & 1u);
+                alldone &= done[j];
+                if (skip) continue;
                 T dx, dy, G, og, alpha;
                 if (STATS) n_eval++;
-                if (eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rb.x, rb.y, rb.z, ra.w, dx, dy, G, og, alpha)) {
+                if (eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha)) {
                     T Tn = Tr[j] * (T(1) - alpha);
                     if (Tn < K<T>::t_min) {
                         done[j] = true;
@@ -266,6 +284,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     int tx = local % TX, ty = local / TX;
     int W = vt.width[v], H = vt.height[v];
     int lane = threadIdx.x & 63;
+    const int wave_id = threadIdx.x >> 6;
     T pxc[PX], pyc[PX], Tr[PX], gr[PX][3], Bc[PX][3];
     uint32_t L[PX];
     uint32_t mymax = 0;
@@ -302,14 +321,16 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         __syncthreads();
         for (int q = kept - 1; q >= 0; q--) {
             uint32_t k = st.pos[q];
-            V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q];
+            V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
+            uint32_t bm = st.band[q] >> wave_id;
             T acc[9];
             for (int c = 0; c < 9; c++) acc[c] = T(0);
             bool any = false;
             for (int j = 0; j < PX; j++) {
+                if (!((bm >> (j * (NT / 64))) & 1u)) continue;
                 if (k >= L[j]) continue;
                 T dx, dy, G, og, alpha;
-                if (!eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rb.x, rb.y, rb.z, ra.w, dx, dy, G, og, alpha))
+                if (!eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha))
                     continue;
                 any = true;
                 T Tk = Tr[j] / (T(1) - alpha);
@@ -430,54 +451,6 @@ __global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, 
     }
 }
 
-// ------------------------------------------------------------------ Algorithm 1 on the device
-// CT = cumsum(ET) with ET_j = cost_j + 1; DP[q] = first j with CT[j] >= q * CT[last] / Q;
-// DP[Q] = T. Resets cursor[q] = DP[q].
-__global__ void __launch_bounds__(1024) plan_kernel(const uint32_t *__restrict__ cost, int32_t T_all, int32_t Q,
-                                                    uint64_t *__restrict__ ct, int32_t *__restrict__ dp,
-                                                    int32_t *__restrict__ cursor, int32_t *__restrict__ dp_out)
-{
-    __shared__ uint64_t s_w[16];
-    __shared__ uint64_t s_carry;
-    int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_carry = 0;
-    __syncthreads();
-    for (int32_t base = 0; base < T_all; base += 1024) {
-        int32_t j = base + tid;
-        uint64_t x = j < T_all ? (uint64_t)(cost ? cost[j] : 0u) + 1ull : 0ull;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint64_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) s_w[w] = x;
-        __syncthreads();
-        uint64_t pre = s_carry;
-        for (int q = 0; q < w; q++) pre += s_w[q];
-        if (j < T_all) ct[j] = pre + x;
-        __syncthreads();
-        if (tid == 1023) s_carry = pre + x;
-        __syncthreads();
-    }
-    double total = (double)s_carry;
-    for (int q = tid; q <= Q; q += 1024) {
-        int32_t r;
-        if (q == Q) r = T_all;
-        else {
-            double th = (double)q * (total / (double)Q);
-            int32_t lo = 0, hi = T_all;
-            while (lo < hi) {
-                int32_t mid = (lo + hi) >> 1;
-                if ((double)ct[mid] < th) lo = mid + 1;
-                else hi = mid;
-            }
-            r = lo;
-        }
-        dp[q] = r;
-        if (q < Q) cursor[q] = r;
-        if (dp_out) dp_out[q] = r;
-    }
-}
-
 // ------------------------------------------------------------------ launchers
 #define GS_DISPATCH_SHAPE(T, PX, CH, CALL)                                                                   \
     do {                                                                                                     \
@@ -560,13 +533,6 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
         GS_DISPATCH_SHAPE(T, sh.px, sh.chunk, GS_BWD);
     }
 #undef GS_BWD
-    return hipGetLastError();
-}
-
-hipError_t launch_plan(const uint32_t *cost, int32_t T_all, int32_t Q, uint64_t *ct, int32_t *dp, int32_t *cursor,
-                       int32_t *dp_out, hipStream_t s)
-{
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, cost, T_all, Q, ct, dp, cursor, dp_out);
     return hipGetLastError();
 }
 

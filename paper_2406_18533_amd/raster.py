@@ -159,13 +159,33 @@ def _bg(bg):
     return (C.c_float * 3)(*[float(x) for x in bg])
 
 
+def alloc_projected(n: int, views: int, dtype=torch.float32, device="cuda") -> torch.Tensor:
+    """A projected buffer of gs_projected_bytes(n, views); returns the
+    [views][n][12] record view (the planar side arrays follow it in the same
+    allocation)."""
+    nbytes = int(_lib.load().gs_projected_bytes(_dtype_code(dtype), n, views))
+    item = torch.empty(0, dtype=dtype).element_size()
+    flat = torch.empty(max((nbytes + item - 1) // item, 1), dtype=dtype, device=device)
+    return flat[: views * n * _lib.GS_REC].view(views, n, _lib.GS_REC)
+
+
+def projected_side_arrays(projected: torch.Tensor):
+    """(tiles touched, FP32 depth bits) planar side arrays, each [views][n] int32."""
+    V, n, _ = projected.shape
+    item = projected.element_size()
+    total = V * n * _lib.GS_REC + (V * n * 8 + item - 1) // item
+    flat = torch.as_strided(projected, (total,), (1,), projected.storage_offset())
+    side = flat[V * n * _lib.GS_REC:].view(torch.int32)[: 2 * V * n]
+    return side[: V * n].view(V, n), side[V * n:].view(V, n)
+
+
 # --------------------------------------------------------------------------- entry points
 def gs_project(params: torch.Tensor, cams: Cameras, projected: torch.Tensor | None = None, stream=None):
     """Records [views][n][12] (see include/gs.h gs_project)."""
     assert params.is_cuda and params.is_contiguous() and params.shape[0] == 59
     n = params.shape[1]
     if projected is None:
-        projected = torch.empty(cams.n, n, _lib.GS_REC, dtype=params.dtype, device=params.device)
+        projected = alloc_projected(n, cams.n, params.dtype, params.device)
     check(_lib.load().gs_project(_dtype_code(params.dtype), _ptr(params), n, cams.dev_ptr, cams.host_ptr, cams.n,
                                  _ptr(projected), _stream(stream)))
     return projected

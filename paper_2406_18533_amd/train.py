@@ -56,7 +56,7 @@ class BatchedTrainer:
         self.v = torch.zeros_like(self.P)
         self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(2, dtype=torch.float64, device=dev)
-        self.proj = torch.empty(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.proj = R.alloc_projected(self.n, self.V, torch.float32, dev)
         self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
         P_all = self.cams.total_pixels()
         self.rgb = torch.empty(3 * P_all, dtype=torch.float32, device=dev)
@@ -194,7 +194,7 @@ class PlainTrainer:
         self.v = torch.zeros_like(self.P)
         self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(2, dtype=torch.float64, device=dev)
-        self.proj = torch.empty(1, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.proj = R.alloc_projected(self.n, 1, torch.float32, dev)
         self.dproj = torch.zeros(1, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
         self.hp = R.adam_hparams(self.cfg.lr, self.cfg.beta1, self.cfg.beta2, self.cfg.eps, batch_size=self.V,
                                  zero_grad=True)

@@ -379,3 +379,41 @@ def test_view_alone_equals_view_in_batch():
     for v, c in enumerate(cams):
         alone = gp.forward(Pd, [c], BG)
         assert (gp.split_views(alone["rgb"], [c], 3)[0] == rgb_b[v]).all()
+
+
+# ----------------------------------------------------------------------------- scheduler (Algorithm 1)
+def test_side_arrays_agree_with_records():
+    from paper_2406_18533_amd import raster as R
+    P, cams = small_multiview()
+    C = R.Cameras(cams)
+    proj = R.gs_project(P.cuda(), C)
+    tiles, depth = R.projected_side_arrays(proj)
+    torch.cuda.synchronize()
+    rec = proj.cpu()
+    assert torch.equal(tiles.cpu(), rec[..., 11].to(torch.int32))
+    vis = rec[..., 11] > 0
+    assert torch.equal(depth.cpu()[vis], rec[..., 10][vis].contiguous().view(torch.int32))
+
+
+@pytest.mark.parametrize("Q", [8, 64])
+def test_division_points_match_algorithm_1(Q):
+    """Algorithm 1 with torch.cumsum / torch.searchsorted (the paper's own
+    library calls) on ET = cost + 1, against the device plan."""
+    from paper_2406_18533_amd import _lib
+    from paper_2406_18533_amd import raster as R
+    P, cams = small_multiview()
+    C = R.Cameras(cams)
+    T_all = C.total_tiles()
+    cost = torch.from_numpy(np.random.default_rng(Q).integers(0, 500, T_all).astype(np.int32))
+    cost[5:40] = 0
+    s = R.Sched(C, _lib.GS_SCHED_PERSISTENT, 1, 64, 0, Q, tile_cost=cost.cuda())
+    dp = torch.zeros(Q + 1, dtype=torch.int32, device="cuda")
+    R.gs_sched_plan(s, C, dp)
+    torch.cuda.synchronize()
+    ET = cost.double() + 1
+    CT = torch.cumsum(ET, 0)
+    ET_gpu = CT[-1] / Q
+    TH = torch.arange(0, Q, dtype=torch.float64) * ET_gpu
+    DP = torch.searchsorted(CT, TH)
+    assert DP[0] == 0
+    assert dp[:Q].cpu().tolist() == DP.tolist() and dp[Q].item() == T_all

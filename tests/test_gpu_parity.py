@@ -204,12 +204,55 @@ def test_render_bwd_matches_oracle(name):
             b = do[comp]
             err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
             assert err <= 1e-3, (v, comp, err)
-    # parameter gradients: the oracle's whole FP64 backward from its own projection
+    # transformation backward alone: both sides fed the same record gradients
+    from paper_2406_18533_amd import raster as R
+    g_iso = torch.zeros_like(Pd)
+    R.gs_project_bwd(Pd, f["cams"], f["proj"], dproj, g_iso, clear=False)
+    torch.cuda.synchronize()
+    go_iso = np.zeros((59, P.shape[1]))
+    for v, cam in enumerate(cams):
+        go_iso += oracle.project_bwd(P.double(), cam, dpg[v][:, :9].T.astype(np.float64))
+    gi = g_iso.double().cpu().numpy()
+    for k, sl in GROUPS.items():
+        err = np.linalg.norm(gi[sl] - go_iso[sl]) / max(np.linalg.norm(go_iso[sl]), 1e-30)
+        assert err <= 1e-4, ("transformation backward", k, err)
+    # parameter gradients: the oracle's whole FP64 backward from its own projection.
+    # Thin needle footprints flip about 1% of pixel decisions between FP32 and
+    # FP64 (see the end-to-end image test), which moves these sums by ~1e-3.
+    tol = 2e-3 if name == "needles" else 1e-3
     fo = oracle.forward(P.double(), cams, BG)
     go, _ = oracle.backward(P.double(), cams, fo, dLv, BG)
     gg = grad.double().cpu().numpy()
     for k, sl in GROUPS.items():
         err = np.linalg.norm(gg[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        assert err <= tol, (k, err)
+
+
+def test_diff_check_1080p_gradients_match_oracle():
+    """1,000,000 clustered Gaussians, one 1920x1080 view: FP32 gradients of the
+    L1 loss against a jittered-scene target, versus the FP64 oracle's, per
+    parameter group within 1e-3 (norm-relative)."""
+    gp = _gp()
+    from paper_2406_18533_amd import raster as R
+    w = scenes.diff_check_large()
+    cams = w.cameras
+    Pd = gp.to_dev(w.params)
+    tgt = gp.forward(gp.to_dev(w.target_params), cams, BG)["rgb"]
+    f = gp.forward(Pd, cams, BG)
+    buf = R.LossBuffers(f["cams"])
+    loss, dL = R.gs_loss_l1(f["rgb"], tgt, f["cams"], buf)
+    grad, dproj = gp.backward(Pd, f, dL, BG)
+    print(f"1080p: K={int(f['bins'].n_instances.item())}", flush=True)
+    # the oracle sees the same target image and its own FP64 forward
+    P64 = w.params.double()
+    fo = oracle.forward(P64, cams, BG)
+    lo, go_img = oracle.l1_loss([fo["views"][0]["rgb"]], gp.split_views(tgt, cams, 3))
+    assert abs(loss.item() - lo) <= 1e-4 * lo
+    go, _ = oracle.backward(P64, cams, fo, go_img, BG)
+    gg = grad.double().cpu().numpy()
+    for k, sl in GROUPS.items():
+        err = np.linalg.norm(gg[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        print(f"1080p gradient {k}: {err:.2e}", flush=True)
         assert err <= 1e-3, (k, err)
 
 

@@ -165,7 +165,6 @@ def test_overflow_skips_update_and_recovers():
     P, cams, tgt = _small_batch()
     tr = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
     tr.bins = R.Bins(tr.n, tr.cams, 1000)            # far too small
-    tr.capture_needed = True
     P_before = tr.P.clone()
     tr.graph = None
     # capture runs one eager step first (which grows the buffers), so force the

@@ -195,6 +195,66 @@ def cpu_baseline(workload, sample_views: int = 1):
                       f"extrapolated linearly to the batch"}
 
 
+def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, max_views: int = 8):
+    """Render-only serving of a device-resident model (5M clustered
+    Gaussians): one-at-a-time capacity, then Poisson arrivals at 0.7x that
+    rate through the continuous-batching server (p50/p99 latency = completion
+    minus arrival), then saturation throughput."""
+    import threading
+    import torch
+    from paper_2406_18533_amd.serve import GPUBackend, RenderServer, percentile
+    from synthetic import scenes
+    P = scenes.serving_scene(n_gaussians).cuda()
+    be = GPUBackend(P, slots=slots, max_views=max_views)
+    probe = [c for _, c in scenes.serving_requests(warmup + 40, qps=1.0, seed=16)]
+    # one at a time: service time of single-request batches
+    for c in probe[:warmup]:
+        be.render_now(0, [c], 120 << 20)
+    t0 = time.perf_counter()
+    for c in probe[warmup:]:
+        be.render_now(0, [c], 120 << 20)
+    single = (time.perf_counter() - t0) / (len(probe) - warmup)
+    qps = 0.7 / single
+    reqs = scenes.serving_requests(requests, qps=qps, seed=15)
+    srv = RenderServer(be, mem_budget_bytes=8 << 30, max_batch_views=max_views).start()
+    for _, c in reqs[:warmup]:
+        srv.submit(c).result()
+    srv.completed.clear()
+    futs = []
+
+    def client():
+        t_start = time.perf_counter()
+        for arr, c in reqs:
+            d = t_start + arr - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            futs.append(srv.submit(c))
+    th = threading.Thread(target=client)
+    t0 = time.perf_counter()
+    th.start()
+    th.join()
+    for f in list(futs):
+        f.result()
+    t_fixed = time.perf_counter() - t0
+    lat = srv.latencies_ms()
+    p50, p99 = percentile(lat, 50), percentile(lat, 99)
+    mean_batch = sum(srv.batches) / max(len(srv.batches), 1)
+    # saturation: everything queued at once
+    srv.completed.clear()
+    t0 = time.perf_counter()
+    futs = [srv.submit(c) for _, c in reqs[: min(len(reqs), 200)]]
+    for f in futs:
+        f.result()
+    sat = len(futs) / (time.perf_counter() - t0)
+    srv.stop()
+    torch.cuda.synchronize()
+    return {"workload": f"serving_{n_gaussians // 1_000_000}M_mixed_res", "qps": round(qps, 2),
+            "requests": requests, "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+            "views_per_s_at_qps": round(requests / t_fixed, 2), "saturation_views_per_s": round(sat, 2),
+            "one_at_a_time_views_per_s": round(1.0 / single, 2), "mean_batch": round(mean_batch, 2),
+            "resolutions": ["512x512", "1280x720", "1920x1080", "3840x2160"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +266,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (a multi-GPU run would "
@@ -267,6 +329,13 @@ def main():
         t1 = time.perf_counter()
         plain = {"views_per_s": round(pt.V * k / (t1 - t0), 2), "ms_per_step": round((t1 - t0) * 1e3 / k, 3)}
         del pt
+    serving = None
+    if not args.no_serve:
+        log("serving (render-only, continuous batching)")
+        del tr
+        torch.cuda.empty_cache()
+        serving = serve_bench(5_000_000, args.serve_requests, warmup=20)
+        log(f"serving {json.dumps(serving)}")
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (sample)")
@@ -284,6 +353,7 @@ def main():
                                                             "modes": tr.cfg.extra}},
         "plain_path": plain,
         "speedup_vs_plain": round(views_s / plain["views_per_s"], 3) if plain else None,
+        "serving": serving,
         "roofline": roof,
         "per_kernel": per,
         "counts": counts,

@@ -183,20 +183,34 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
     return peers;
 }
 
+// Each block owns a contiguous run of 4096-key tiles (tiles_per_block of
+// them, computed from the device-side count so both kernels agree) and
+// writes one histogram column; the grid is bounded, so the histogram and its
+// scan stay small whatever the key count.
+__device__ __forceinline__ void block_tiles(int64_t n, int64_t grid, int64_t &t0, int64_t &t1)
+{
+    int64_t ntiles = (n + STILE - 1) / STILE;
+    int64_t per = (ntiles + grid - 1) / grid;
+    t0 = (int64_t)blockIdx.x * per;
+    t1 = t0 + per < ntiles ? t0 + per : ntiles;
+}
+
 template <int BITS>
 __global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restrict__ kin, const int64_t *n_dev,
                                                          int64_t n_max, int shift, uint32_t *__restrict__ hist,
-                                                         int64_t nbmax)
+                                                         int64_t nblocks)
 {
     constexpr int RADIX = 1 << BITS;
     __shared__ uint32_t s_cnt[SB / 64][RADIX];
     int64_t n = count_of(n_dev, n_max);
-    int64_t base = (int64_t)blockIdx.x * STILE;
+    int64_t t0, t1;
+    block_tiles(n, nblocks, t0, t1);
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
     __syncthreads();
-    if (base < n) {
-        uint64_t lt = (1ull << lane) - 1ull;
+    uint64_t lt = (1ull << lane) - 1ull;
+    for (int64_t t = t0; t < t1; t++) {
+        int64_t base = t * STILE;
         for (int it = 0; it < SITEMS; it++) {
             int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
             bool valid = idx < n;
@@ -210,7 +224,7 @@ __global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restr
     for (int d = threadIdx.x; d < RADIX; d += SB) {
         uint32_t c = 0;
         for (int j = 0; j < SB / 64; j++) c += s_cnt[j][d];
-        hist[(int64_t)d * nbmax + blockIdx.x] = c;
+        hist[(int64_t)d * nblocks + blockIdx.x] = c;
     }
 }
 
@@ -219,7 +233,7 @@ __global__ void __launch_bounds__(SB) radix_scatter_kernel(const uint32_t *__res
                                                            const uint32_t *__restrict__ vin,
                                                            uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                            const int64_t *n_dev, int64_t n_max, int shift,
-                                                           const uint32_t *__restrict__ offs, int64_t nbmax)
+                                                           const uint32_t *__restrict__ offs, int64_t nblocks)
 {
     constexpr int RADIX = 1 << BITS;
     constexpr int PER = (RADIX + SB - 1) / SB;
@@ -229,84 +243,97 @@ __global__ void __launch_bounds__(SB) radix_scatter_kernel(const uint32_t *__res
     __shared__ uint32_t s_start[RADIX];
     __shared__ uint32_t s_goff[RADIX];
     int64_t n = count_of(n_dev, n_max);
-    int64_t base = (int64_t)blockIdx.x * STILE;
-    if (base >= n) return;
+    int64_t t0, t1;
+    block_tiles(n, nblocks, t0, t1);
+    if (t0 >= t1) return;
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
-    for (int d = threadIdx.x; d < RADIX; d += SB) s_goff[d] = offs[(int64_t)d * nbmax + blockIdx.x];
-    __syncthreads();
-    uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
+    for (int d = threadIdx.x; d < RADIX; d += SB) s_goff[d] = offs[(int64_t)d * nblocks + blockIdx.x];
     uint64_t lt = (1ull << lane) - 1ull;
-    for (int it = 0; it < SITEMS; it++) {
-        int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
-        bool valid = idx < n;
-        uint32_t k = valid ? kin[idx] : 0u;
-        uint32_t v = valid ? vin[idx] : 0u;
-        uint32_t d = (k >> shift) & (RADIX - 1);
-        uint64_t peers = match_digit<BITS>(d, valid);
-        uint32_t before = s_cnt[w][d];
-        if (valid && (peers & lt) == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
-        rank[it] = before + (uint32_t)__popcll(peers & lt);
-        key[it] = k;
-        val[it] = v;
-    }
-    __syncthreads();
-    // wave prefixes per digit, then block-local digit starts
-    uint32_t tot[PER];
-    uint32_t mysum = 0;
-    for (int j = 0; j < PER; j++) {
-        int d = threadIdx.x * PER + j;
-        uint32_t t = 0;
-        if (d < RADIX) {
-            uint32_t run = 0;
-            for (int q = 0; q < SB / 64; q++) {
-                uint32_t c = s_cnt[q][d];
-                s_cnt[q][d] = run;
-                run += c;
+    for (int64_t t = t0; t < t1; t++) {
+        int64_t base = t * STILE;
+        for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
+        __syncthreads();
+        uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
+        for (int it = 0; it < SITEMS; it++) {
+            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
+            bool valid = idx < n;
+            uint32_t k = valid ? kin[idx] : 0u;
+            uint32_t v = valid ? vin[idx] : 0u;
+            uint32_t d = (k >> shift) & (RADIX - 1);
+            uint64_t peers = match_digit<BITS>(d, valid);
+            uint32_t before = s_cnt[w][d];
+            if (valid && (peers & lt) == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
+            rank[it] = before + (uint32_t)__popcll(peers & lt);
+            key[it] = k;
+            val[it] = v;
+        }
+        __syncthreads();
+        // wave prefixes per digit, then tile-local digit starts
+        uint32_t tot[PER];
+        uint32_t mysum = 0;
+        for (int j = 0; j < PER; j++) {
+            int d = threadIdx.x * PER + j;
+            uint32_t tt = 0;
+            if (d < RADIX) {
+                uint32_t run = 0;
+                for (int q = 0; q < SB / 64; q++) {
+                    uint32_t c = s_cnt[q][d];
+                    s_cnt[q][d] = run;
+                    run += c;
+                }
+                tt = run;
             }
-            t = run;
+            tot[j] = tt;
+            mysum += tt;
         }
-        tot[j] = t;
-        mysum += t;
-    }
-    uint32_t total;
-    uint32_t run = block_excl_scan(mysum, total);
-    for (int j = 0; j < PER; j++) {
-        int d = threadIdx.x * PER + j;
-        if (d < RADIX) s_start[d] = run;
-        run += tot[j];
-    }
-    __syncthreads();
-    for (int it = 0; it < SITEMS; it++) {
-        int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
-        if (idx < n) {
-            uint32_t d = (key[it] >> shift) & (RADIX - 1);
-            uint32_t pos = s_start[d] + s_cnt[w][d] + rank[it];
-            s_key[pos] = key[it];
-            s_val[pos] = val[it];
+        uint32_t total;
+        uint32_t run = block_excl_scan(mysum, total);
+        for (int j = 0; j < PER; j++) {
+            int d = threadIdx.x * PER + j;
+            if (d < RADIX) s_start[d] = run;
+            run += tot[j];
         }
-    }
-    __syncthreads();
-    int64_t cnt = n - base < STILE ? n - base : STILE;
-    for (int p = threadIdx.x; p < cnt; p += SB) {
-        uint32_t k = s_key[p];
-        uint32_t d = (k >> shift) & (RADIX - 1);
-        int64_t g = (int64_t)s_goff[d] + (p - (int64_t)s_start[d]);
-        kout[g] = k;
-        vout[g] = s_val[p];
+        __syncthreads();
+        for (int it = 0; it < SITEMS; it++) {
+            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
+            if (idx < n) {
+                uint32_t d = (key[it] >> shift) & (RADIX - 1);
+                uint32_t pos = s_start[d] + s_cnt[w][d] + rank[it];
+                s_key[pos] = key[it];
+                s_val[pos] = val[it];
+            }
+        }
+        __syncthreads();
+        int64_t cnt = n - base < STILE ? n - base : STILE;
+        for (int p = threadIdx.x; p < cnt; p += SB) {
+            uint32_t k = s_key[p];
+            uint32_t d = (k >> shift) & (RADIX - 1);
+            int64_t g = (int64_t)s_goff[d] + (p - (int64_t)s_start[d]);
+            kout[g] = k;
+            vout[g] = s_val[p];
+        }
+        __syncthreads();
+        // this tile's counts advance the block's running digit offsets
+        for (int j = 0; j < PER; j++) {
+            int d = threadIdx.x * PER + j;
+            if (d < RADIX) s_goff[d] += tot[j];
+        }
+        __syncthreads();
     }
 }
 
+constexpr int64_t RADIX_GRID = 2048;   // blocks per radix pass (upper bound)
+
 template <int BITS>
 static void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *ko, uint32_t *vo, const int64_t *n_dev,
-                       int64_t n_max, int shift, uint32_t *hist, uint32_t *partial, int64_t nbmax, hipStream_t s)
+                       int64_t n_max, int shift, uint32_t *hist, uint32_t *partial, int64_t nblocks, hipStream_t s)
 {
-    int64_t hn = (int64_t)(1 << BITS) * nbmax;
-    hipLaunchKernelGGL(radix_count_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, n_dev, n_max, shift, hist,
-                       nbmax);
+    int64_t hn = (int64_t)(1 << BITS) * nblocks;
+    hipLaunchKernelGGL(radix_count_kernel<BITS>, dim3((unsigned)nblocks), dim3(SB), 0, s, kin, n_dev, n_max, shift,
+                       hist, nblocks);
     (void)device_scan<uint32_t>(U32Load{hist}, U32Store{hist}, nullptr, hn, partial, nullptr, s);
-    hipLaunchKernelGGL(radix_scatter_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, vin, ko, vo, n_dev,
-                       n_max, shift, (const uint32_t *)hist, nbmax);
+    hipLaunchKernelGGL(radix_scatter_kernel<BITS>, dim3((unsigned)nblocks), dim3(SB), 0, s, kin, vin, ko, vo, n_dev,
+                       n_max, shift, (const uint32_t *)hist, nblocks);
 }
 
 // Sorts (keys, vals) over their lowest `bits` key bits; the result lands back
@@ -317,6 +344,7 @@ static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uin
 {
     int64_t nbmax = (n_max + STILE - 1) / STILE;
     if (nbmax == 0) return hipSuccess;
+    if (nbmax > RADIX_GRID) nbmax = RADIX_GRID;
     int passes = (bits + 8) / 9;
     if (passes & 1) passes++;
     int digit = (bits + passes - 1) / passes;

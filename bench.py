@@ -255,6 +255,49 @@ def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, ma
             "resolutions": ["512x512", "1280x720", "1920x1080", "3840x2160"]}
 
 
+def aerial_bench(steps: int, warmup: int, plain: bool):
+    """The large aerial scene (20M Gaussians, 2 views 4608x3456 + 2 views
+    3840x2160): batched graph-captured step vs the plain per-view path."""
+    import torch
+    from paper_2406_18533_amd import autotune, train
+    w = make_workload("aerial_4k")
+    P = w.params.cuda()
+    targets = render_targets(w.target_params.cuda(), w.cameras)
+    tr = train.BatchedTrainer(P.clone(), w.cameras, targets, train.TrainConfig())
+    autotune.tune(tr)
+    for _ in range(warmup):
+        tr.step()
+        tr.check_overflow()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tr.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tr.check_overflow()
+    out = {"workload": w.name, "gaussians": P.shape[1], "views": len(w.cameras),
+           "views_per_s": round(tr.V * steps / dt, 2), "ms_per_step": round(dt * 1e3 / steps, 3),
+           "instances": int(tr.bins.n_instances.item())}
+    del tr
+    torch.cuda.empty_cache()
+    if plain:
+        pt = train.PlainTrainer(P.clone(), w.cameras, targets, train.TrainConfig())
+        pt.step()
+        torch.cuda.synchronize()
+        k = max(2, min(steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(k):
+            pt.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["plain_views_per_s"] = round(pt.V * k / dt, 2)
+        out["speedup_vs_plain"] = round(out["views_per_s"] / out["plain_views_per_s"], 3)
+        del pt
+    del P, targets
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +310,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-aerial", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -330,12 +374,19 @@ def main():
         plain = {"views_per_s": round(pt.V * k / (t1 - t0), 2), "ms_per_step": round((t1 - t0) * 1e3 / k, 3)}
         del pt
     serving = None
+    sched_cfg = {"fwd": list(tr.cfg.fwd_shape), "bwd": list(tr.cfg.bwd_shape), "modes": dict(tr.cfg.extra)}
+    n_gauss = P.shape[1]
+    del tr, P, targets
+    torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving (render-only, continuous batching)")
-        del tr
-        torch.cuda.empty_cache()
         serving = serve_bench(5_000_000, args.serve_requests, warmup=20)
         log(f"serving {json.dumps(serving)}")
+    aerial = None
+    if not args.no_aerial and args.workload == "batched_1080p":
+        log("aerial 4K-class scene (20M Gaussians)")
+        aerial = aerial_bench(max(3, min(args.steps, 10)), 2, not args.no_plain)
+        log(f"aerial {json.dumps(aerial)}")
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (sample)")
@@ -346,13 +397,13 @@ def main():
         "value": round(views_s, 2), "unit": "views/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "gaussians": P.shape[1], "views": len(cams),
+        "config": {"workload": w.name, "gaussians": n_gauss, "views": len(cams),
                    "resolution": sorted({f"{c['width']}x{c['height']}" for c in cams}),
                    "global_batch": len(cams), "parallelism": "single-gpu",
-                   "graph": not args.no_graph, "scheduler": {"fwd": list(tr.cfg.fwd_shape), "bwd": list(tr.cfg.bwd_shape),
-                                                            "modes": tr.cfg.extra}},
+                   "graph": not args.no_graph, "scheduler": sched_cfg},
         "plain_path": plain,
         "speedup_vs_plain": round(views_s / plain["views_per_s"], 3) if plain else None,
+        "aerial_4k": aerial,
         "serving": serving,
         "roofline": roof,
         "per_kernel": per,

@@ -96,18 +96,18 @@ def aerial_camera(width: int, height: int, pos_xy, altitude: float, tilt: float,
 
 # --------------------------------------------------------------------------- gaussians
 def _finish_params(gen, means: torch.Tensor, log_scale_mu: float, log_scale_sd: float, dtype) -> torch.Tensor:
-    """Draws the non-position rows in a fixed order: log-scales, quaternions,
-    opacity logits, SH DC, SH rest."""
+    """Draws the non-position rows in a fixed order, in the output dtype:
+    log-scales, quaternions, opacity logits, SH DC, SH rest."""
     n = means.shape[1]
-    P = torch.empty(N_PARAM_ROWS, n, dtype=torch.float64)
-    P[0:3] = means
-    P[3:6] = log_scale_mu + log_scale_sd * torch.randn(3, n, generator=gen, dtype=torch.float64)
-    q = torch.randn(4, n, generator=gen, dtype=torch.float64)
+    P = torch.empty(N_PARAM_ROWS, n, dtype=dtype)
+    P[0:3] = means.to(dtype)
+    P[3:6] = torch.randn(3, n, generator=gen, dtype=dtype).mul_(log_scale_sd).add_(log_scale_mu)
+    q = torch.randn(4, n, generator=gen, dtype=dtype)
     P[6:10] = q / q.norm(dim=0, keepdim=True)
-    P[10] = torch.randn(n, generator=gen, dtype=torch.float64)
-    P[11:14] = 0.5 + 0.2 * torch.randn(3, n, generator=gen, dtype=torch.float64)
-    P[14:59] = 0.05 * torch.randn(45, n, generator=gen, dtype=torch.float64)
-    return P.to(dtype)
+    P[10] = torch.randn(n, generator=gen, dtype=dtype)
+    P[11:14] = torch.randn(3, n, generator=gen, dtype=dtype).mul_(0.2).add_(0.5)
+    P[14:59] = torch.randn(45, n, generator=gen, dtype=dtype).mul_(0.05)
+    return P
 
 
 def uniform_cube_gaussians(n: int, seed: int, dtype=torch.float32) -> torch.Tensor:

@@ -170,6 +170,27 @@ class BatchedTrainer:
     def loss(self) -> float:
         return float(self.loss_buf.loss.item())
 
+    # -- checkpoint / resume --------------------------------------------------------------------
+    def state_dict(self) -> dict:
+        """Parameters, both Adam moments, the device step counter and the
+        per-tile cost history the scheduler uses (all that a resumed run needs
+        to continue the same trajectory)."""
+        return {"params": self.P.detach().clone(), "m": self.m.clone(), "v": self.v.clone(),
+                "step": self.step_dev.clone(), "work_fwd": self.work_fwd.clone(), "work_bwd": self.work_bwd.clone(),
+                "lr": tuple(self.cfg.lr), "batch": self.V}
+
+    def load_state_dict(self, sd: dict) -> None:
+        assert sd["params"].shape == self.P.shape and sd["batch"] == self.V
+        with torch.no_grad():
+            self.P.copy_(sd["params"])
+            self.m.copy_(sd["m"])
+            self.v.copy_(sd["v"])
+            self.step_dev.copy_(sd["step"])
+            self.work_fwd.copy_(sd["work_fwd"])
+            self.work_bwd.copy_(sd["work_bwd"])
+            self.grad.zero_()
+        torch.cuda.synchronize()
+
 
 class PlainTrainer:
     """The batched step computed one view at a time, eagerly, with one

@@ -199,3 +199,24 @@ def test_server_result_alone_equals_result_in_the_mix():
         assert np.array_equal(alone[0], img)
     lat = srv.latencies_ms()
     assert len(lat) == len(reqs)
+
+
+def test_checkpoint_resume_continues_the_trajectory(tmp_path):
+    """6 steps, save, 6 more == 12 steps straight (to float-atomic rounding)."""
+    from paper_2406_18533_amd import train
+    P, cams, tgt = _small_batch()
+    ref = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
+    for _ in range(12):
+        ref.step()
+    a = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
+    for _ in range(6):
+        a.step()
+    torch.save(a.state_dict(), tmp_path / "ck.pt")
+    b = train.BatchedTrainer(P.cuda() * 0 + P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
+    b.load_state_dict(torch.load(tmp_path / "ck.pt", weights_only=True))
+    for _ in range(6):
+        b.step()
+    torch.cuda.synchronize()
+    assert b.step_dev.item() == ref.step_dev.item() == 12
+    err = (b.P - ref.P).abs().max().item()
+    assert err < 1e-4, err

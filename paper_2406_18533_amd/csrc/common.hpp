@@ -115,10 +115,12 @@ template <typename T> __device__ __forceinline__ void scaled_conic(T a, T b, T c
     nc = T(-0.5) * l2e * c;
 }
 
-// One (pixel, Gaussian) pair: circle test, Gaussian falloff, alpha with
-// clamp and skip. Returns false if the Gaussian does not touch the pixel.
-// The forward and backward kernels both call this, so their decisions agree
-// bit for bit.
+// One (pixel, Gaussian) pair, evaluated without branches: offset from the
+// Gaussian's centre, falloff G, opacity times falloff og, alpha =
+// min(0.99, og), and whether the pair counts (centre inside the radius
+// circle, exponent <= 0, alpha >= 1/255). Invalid lanes may hold inf or NaN
+// in G/og/alpha; callers select on `ok`, never multiply by it. The forward
+// and backward kernels both call this, so their decisions agree bit for bit.
 template <typename T>
 __device__ __forceinline__ bool eval_alpha(T pxc, T pyc, T u, T v, T r2, T na, T nb, T nc, T o,
                                            T &dx, T &dy, T &G, T &og, T &alpha)
@@ -126,13 +128,11 @@ __device__ __forceinline__ bool eval_alpha(T pxc, T pyc, T u, T v, T r2, T na, T
     dx = pxc - u;
     dy = pyc - v;
     T d2 = fma(dx, dx, dy * dy);
-    if (d2 > r2) return false;
     T p2 = fma(na * dx, dx, fma(nc * dy, dy, (nb * dx) * dy));   // exponent in log2 units
-    if (p2 > T(0)) return false;
     G = exp2_t(p2);
     og = o * G;
-    alpha = og < K<T>::alpha_max ? og : K<T>::alpha_max;
-    return !(alpha < K<T>::alpha_min);
+    alpha = fmin(og, K<T>::alpha_max);
+    return (d2 <= r2) & (p2 <= T(0)) & (alpha >= K<T>::alpha_min);
 }
 
 template <typename T> struct Vec4;

@@ -211,25 +211,27 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         for (int q = 0; q < kept && !alldone; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
             uint32_t bm = st.band[q] >> wave_id;
+            uint32_t pos1 = st.pos[q] + 1;
             alldone = true;
             for (int j = 0; j < PX; j++) {
-                bool skip = done[j] || !((bm >> (j * (NT / 64))) & 1u);
-                alldone &= done[j];
-                if (skip) continue;
-                T dx, dy, G, og, alpha;
-                if (STATS) n_eval++;
-                if (eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha)) {
+                if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
+                    T dx, dy, G, og, alpha;
+                    bool ok = eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha);
+                    bool was_done = done[j];
+                    ok = ok && !was_done;
                     T Tn = Tr[j] * (T(1) - alpha);
-                    if (Tn < K<T>::t_min) {
-                        done[j] = true;
-                    } else {
-                        if (STATS) n_blend++;
-                        T w = alpha * Tr[j];
-                        C[j][0] += rc.x * w;
-                        C[j][1] += rc.y * w;
-                        C[j][2] += rc.z * w;
-                        Tr[j] = Tn;
-                        lastp[j] = st.pos[q] + 1;
+                    bool stop = ok && (Tn < K<T>::t_min);
+                    bool bl = ok && !stop;
+                    T w = bl ? alpha * Tr[j] : T(0);
+                    C[j][0] += rc.x * w;
+                    C[j][1] += rc.y * w;
+                    C[j][2] += rc.z * w;
+                    Tr[j] = bl ? Tn : Tr[j];
+                    lastp[j] = bl ? pos1 : lastp[j];
+                    done[j] = done[j] || stop;
+                    if (STATS) {
+                        n_eval += was_done ? 0u : 1u;
+                        n_blend += bl ? 1u : 0u;
                     }
                 }
                 alldone &= done[j];
@@ -327,32 +329,31 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             for (int c = 0; c < 9; c++) acc[c] = T(0);
             bool any = false;
             for (int j = 0; j < PX; j++) {
-                if (!((bm >> (j * (NT / 64))) & 1u)) continue;
-                if (k >= L[j]) continue;
+                if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
                 T dx, dy, G, og, alpha;
-                if (!eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha))
-                    continue;
-                any = true;
+                bool ok = eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha);
+                ok = ok && (k < L[j]);
+                any = any || ok;
                 T Tk = Tr[j] / (T(1) - alpha);
                 T w = alpha * Tk;
-                acc[6] += w * gr[j][0];
-                acc[7] += w * gr[j][1];
-                acc[8] += w * gr[j][2];
-                T dalpha = ((rc.x - Bc[j][0]) * gr[j][0] + (rc.y - Bc[j][1]) * gr[j][1] + (rc.z - Bc[j][2]) * gr[j][2]) * Tk;
+                T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
+                T dalpha = ((rc.x - Bc[j][0]) * gx + (rc.y - Bc[j][1]) * gy + (rc.z - Bc[j][2]) * gz) * Tk;
                 T om = T(1) - alpha;
-                Bc[j][0] = alpha * rc.x + om * Bc[j][0];
-                Bc[j][1] = alpha * rc.y + om * Bc[j][1];
-                Bc[j][2] = alpha * rc.z + om * Bc[j][2];
-                Tr[j] = Tk;
-                if (og <= K<T>::alpha_max) {
-                    T dpow = dalpha * og;
-                    acc[5] += dalpha * G;
-                    acc[0] += dpow * (rb.x * dx + rb.y * dy);
-                    acc[1] += dpow * (rb.y * dx + rb.z * dy);
-                    acc[2] += T(-0.5) * dpow * dx * dx;
-                    acc[3] += -dpow * dx * dy;
-                    acc[4] += T(-0.5) * dpow * dy * dy;
-                }
+                acc[6] += ok ? w * gx : T(0);
+                acc[7] += ok ? w * gy : T(0);
+                acc[8] += ok ? w * gz : T(0);
+                Bc[j][0] = ok ? alpha * rc.x + om * Bc[j][0] : Bc[j][0];
+                Bc[j][1] = ok ? alpha * rc.y + om * Bc[j][1] : Bc[j][1];
+                Bc[j][2] = ok ? alpha * rc.z + om * Bc[j][2] : Bc[j][2];
+                Tr[j] = ok ? Tk : Tr[j];
+                bool grad_ok = ok && (og <= K<T>::alpha_max);   // the 0.99 clamp has no gradient
+                T dpow = grad_ok ? dalpha * og : T(0);
+                acc[5] += grad_ok ? dalpha * G : T(0);
+                acc[0] += grad_ok ? dpow * (rb.x * dx + rb.y * dy) : T(0);
+                acc[1] += grad_ok ? dpow * (rb.y * dx + rb.z * dy) : T(0);
+                acc[2] += grad_ok ? T(-0.5) * dpow * dx * dx : T(0);
+                acc[3] += grad_ok ? -dpow * dx * dy : T(0);
+                acc[4] += grad_ok ? T(-0.5) * dpow * dy * dy : T(0);
             }
             if (__ballot(any) == 0) continue;
             for (int c = 0; c < 9; c++) acc[c] = wave_sum(acc[c]);

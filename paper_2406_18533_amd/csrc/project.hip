@@ -260,13 +260,17 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
 }
 
 // Transformation backward: chain rule from the per-view record gradients
-// d(u, v, a, b, c, opacity, rgb) to the 59 parameters; sums over views in
-// registers and adds each parameter gradient once (no atomics).
+// d(u, v, a, b, c, opacity, rgb) to the 59 parameters, summed over views in
+// registers; each parameter gradient is added once per kernel (no atomics).
+// Two kernels keep register pressure low: the geometry kernel covers
+// position (through u, v and the perspective Jacobian), scale, rotation and
+// opacity; the colour kernel covers the SH coefficients and the position
+// gradient through the viewing direction, one colour channel at a time.
 template <typename T>
-__global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ P, int64_t n,
-                                                          const gs_camera *__restrict__ cams, int32_t views,
-                                                          const T *__restrict__ proj, T *__restrict__ dproj,
-                                                          int clear, T *__restrict__ grad)
+__global__ void __launch_bounds__(256) project_bwd_geom_kernel(const T *__restrict__ P, int64_t n,
+                                                               const gs_camera *__restrict__ cams, int32_t views,
+                                                               const T *__restrict__ proj, const T *__restrict__ dproj,
+                                                               T *__restrict__ grad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -279,24 +283,15 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
     Shape<T> S;
     make_shape(P, n, i, S);
     T gmean[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = T(0);
-    T gsh[48];
-    for (int j = 0; j < 48; j++) gsh[j] = T(0);
     for (int v = 0; v < views; v++) {
         if (!((vis >> v) & 1ull)) continue;
-        V4<T> *dr = reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
-        V4<T> d0 = dr[0], d1 = dr[1], d2 = dr[2];
-        if (clear) {
-            const V4<T> zero{T(0), T(0), T(0), T(0)};
-            dr[0] = zero;
-            dr[1] = zero;
-            dr[2] = zero;
-        }
+        const V4<T> *dr = reinterpret_cast<const V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
+        V4<T> d0 = dr[0], d1 = dr[1];
         T du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x, dop = d1.y;
-        T drgb[3] = {d1.z, d1.w, d2.x};
         Camera<T> k = load_camera<T>(cams + v);
         Geo<T> g;
         make_geo(x, S, k, g);
-        T z = g.y[2], iz = g.iz, iz2 = iz * iz;
+        T iz = g.iz, iz2 = iz * iz;
         T dy[3];
         dy[0] = du * k.fx * iz;
         dy[1] = dv * k.fy * iz;
@@ -329,45 +324,16 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
         T dxi = -dJ02 * k.fx * iz, deta = -dJ12 * k.fy * iz;
         if (!g.xi_cl) { dy[0] += dxi * iz; dy[2] -= dxi * g.y[0] * iz2; }
         if (!g.eta_cl) { dy[1] += deta * iz; dy[2] -= deta * g.y[1] * iz2; }
-        (void)z;
         for (int c = 0; c < 3; c++) gmean[c] += k.R[c] * dy[0] + k.R[3 + c] * dy[1] + k.R[6 + c] * dy[2];
         gop += dop;
-        // colour
-        T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
-        T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
-        T Y[16];
-        sh_basis(dir[0], dir[1], dir[2], Y);
-        T w[16];
-        for (int k2 = 0; k2 < 16; k2++) w[k2] = T(0);
-        bool any = false;
-        for (int ch = 0; ch < 3; ch++) {
-            T raw = T(0);   // same summation order as the forward, so the clamp mask agrees
-            for (int k2 = 0; k2 < 16; k2++) raw += P[(11 + 3 * k2 + ch) * n + i] * Y[k2];
-            raw += T(0.5);
-            if (!(raw > T(0))) continue;
-            any = true;
-            for (int k2 = 0; k2 < 16; k2++) {
-                T coef = P[(11 + 3 * k2 + ch) * n + i];
-                gsh[3 * k2 + ch] += drgb[ch] * Y[k2];
-                w[k2] += drgb[ch] * coef;
-            }
-        }
-        if (any) {
-            T gd[3];
-            sh_grad(dir[0], dir[1], dir[2], w, gd);
-            T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
-            for (int c = 0; c < 3; c++) gmean[c] += (gd[c] - dir[c] * dd) * idn;
-        }
     }
     // M = Rq diag(s) -> scale and rotation
-    const T *dM = gM;
     T gls[3], dRq[9];
     for (int c = 0; c < 3; c++) {
         T acc = T(0);
         for (int r = 0; r < 3; r++) {
-            dRq[3 * r + c] = dM[3 * r + c] * S.s[c];
-            acc += dM[3 * r + c] * S.Rq[3 * r + c];
+            dRq[3 * r + c] = gM[3 * r + c] * S.s[c];
+            acc += gM[3 * r + c] * S.Rq[3 * r + c];
         }
         gls[c] = acc * S.s[c];
     }
@@ -386,7 +352,69 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(const T *__restrict__ 
     for (int c = 0; c < 3; c++) grad[(3 + c) * n + i] += gls[c];
     for (int j = 0; j < 4; j++) grad[(6 + j) * n + i] += (dq[j] - S.q[j] * dot) * iqn;
     grad[10 * n + i] += gop * S.opac * (T(1) - S.opac);
-    for (int j = 0; j < 48; j++) grad[(11 + j) * n + i] += gsh[j];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) project_bwd_colour_kernel(const T *__restrict__ P, int64_t n,
+                                                                 const gs_camera *__restrict__ cams, int32_t views,
+                                                                 const T *__restrict__ proj, T *__restrict__ dproj,
+                                                                 int clear, T *__restrict__ grad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t vis = 0;
+    const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
+    for (int v = 0; v < views; v++)
+        if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
+    if (!vis) return;
+    T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    T gmean[3] = {0, 0, 0};
+    for (int ch = 0; ch < 3; ch++) {
+        T sh[16], gsh[16];
+        for (int k2 = 0; k2 < 16; k2++) {
+            sh[k2] = P[(11 + 3 * k2 + ch) * n + i];
+            gsh[k2] = T(0);
+        }
+        for (int v = 0; v < views; v++) {
+            if (!((vis >> v) & 1ull)) continue;
+            const T *dr = dproj + ((int64_t)v * n + i) * REC;
+            T drgb = dr[D_RGB + ch];
+            const gs_camera *c = cams + v;
+            T cen[3];
+            for (int j = 0; j < 3; j++)
+                cen[j] = (T)(-(c->R[j] * c->t[0] + c->R[3 + j] * c->t[1] + c->R[6 + j] * c->t[2]));
+            T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
+            T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
+            T Y[16];
+            sh_basis(dir[0], dir[1], dir[2], Y);
+            T raw = T(0);   // same summation order as the forward, so the clamp mask agrees
+            for (int k2 = 0; k2 < 16; k2++) raw += sh[k2] * Y[k2];
+            raw += T(0.5);
+            if (!(raw > T(0))) continue;
+            T wk[16];
+            for (int k2 = 0; k2 < 16; k2++) {
+                gsh[k2] += drgb * Y[k2];
+                wk[k2] = drgb * sh[k2];
+            }
+            T gd[3];
+            sh_grad(dir[0], dir[1], dir[2], wk, gd);
+            T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+            for (int j = 0; j < 3; j++) gmean[j] += (gd[j] - dir[j] * dd) * idn;
+        }
+        for (int k2 = 0; k2 < 16; k2++) grad[(11 + 3 * k2 + ch) * n + i] += gsh[k2];
+    }
+    for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
+    if (clear) {
+        const V4<T> zero{T(0), T(0), T(0), T(0)};
+        for (int v = 0; v < views; v++) {
+            if (!((vis >> v) & 1ull)) continue;
+            V4<T> *dr = reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
+            dr[0] = zero;
+            dr[1] = zero;
+            dr[2] = zero;
+        }
+    }
 }
 
 template <typename T>
@@ -406,8 +434,10 @@ hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, i
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(project_bwd_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams, views,
-                       (const T *)proj, (T *)dproj, clear, (T *)grad);
+    hipLaunchKernelGGL(project_bwd_geom_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams,
+                       views, (const T *)proj, (const T *)dproj, (T *)grad);
+    hipLaunchKernelGGL(project_bwd_colour_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams,
+                       views, (const T *)proj, (T *)dproj, clear, (T *)grad);
     return hipGetLastError();
 }
 

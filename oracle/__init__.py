@@ -38,7 +38,7 @@ def lib():
         L.oracle_tiles_touched.restype = i64
         L.oracle_bin.argtypes = [d, d, d, d, i64, i32, d, d, i64, d, d, d]
         L.oracle_bin.restype = i64
-        L.oracle_render.argtypes = [d, i64, i32, i32, d, d, d, d, i32, d, d, d, d, d, d]
+        L.oracle_render.argtypes = [d, i64, i32, i32, d, d, d, d, i32, C.c_double, C.c_double, d, d, d, d, d, d]
         L.oracle_render_brute.argtypes = [d, i64, i32, i32, d, d, d, d]
         L.oracle_render_bwd.argtypes = [d, i64, i32, i32, d, d, d, d, d]
         L.oracle_render_bwd.restype = C.c_int
@@ -135,8 +135,10 @@ def bin_sort(u, v, r, depth, cams: list):
     return keys[:K], ids[:K], ranges
 
 
-def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, depth_check=False) -> dict:
-    """Tiled render of one view from projected fields [ONF][N] (FP64)."""
+def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, depth_check=False,
+           pos_tol: float = 0.0, t_tol: float = 1e-5) -> dict:
+    """Tiled render of one view from projected fields [ONF][N] (FP64).
+    fragile/depth_check/pos_tol/t_tol only widen the ambiguity flags."""
     proj = _f64(proj)
     N = proj.shape[1]
     W, H = cam["width"], cam["height"]
@@ -151,7 +153,7 @@ def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, 
     counts = np.zeros(2, dtype=np.int64)
     fr = None if fragile is None else np.ascontiguousarray(fragile, dtype=np.uint8)
     lib().oracle_render(_p(proj), N, W, H, _p(ids) if ids.size else None, _p(ranges_view), _p(bgv),
-                        _p(fr) if fr is not None else None, int(depth_check),
+                        _p(fr) if fr is not None else None, int(depth_check), float(pos_tol), float(t_tol),
                         _p(rgb), _p(T), _p(last), _p(nc), _p(amb), _p(counts))
     return {"rgb": rgb, "T": T, "last": last, "ncontrib": nc, "amb": amb,
             "evaluated": int(counts[0]), "blended": int(counts[1])}
@@ -223,8 +225,13 @@ def rounded_for_binning(proj: np.ndarray):
             proj[F_RADIUS].astype(np.float32), proj[F_DEPTH].astype(np.float32))
 
 
-def forward(P, cams: list, bg=(0.0, 0.0, 0.0), fragile_tol: float = 0.0) -> dict:
-    """Whole forward for a batch of views from the oracle's own projection."""
+def forward(P, cams: list, bg=(0.0, 0.0, 0.0), fragile_tol: float = 0.0, pos_rel: float = 0.0,
+            t_tol: float = 1e-5) -> dict:
+    """Whole forward for a batch of views from the oracle's own projection.
+    For comparison with another implementation's own projection, fragile_tol
+    flags radii within that relative distance of an integer, pos_rel the
+    centre's possible offset as a fraction of the image size, t_tol the
+    transmittance threshold margin (flags only; the arithmetic is the same)."""
     projs = [project(P, c) for c in cams]
     parts = [rounded_for_binning(pr) for pr in projs]
     u, v, r, d = (np.stack([p[j] for p in parts]) for j in range(4))
@@ -236,7 +243,8 @@ def forward(P, cams: list, bg=(0.0, 0.0, 0.0), fragile_tol: float = 0.0) -> dict
         if fragile_tol > 0.0:
             re = pr[F_REXACT]
             fragile = (np.abs(re - np.round(re)) <= fragile_tol * np.maximum(re, 1.0)).astype(np.uint8)
-        views.append(render(pr, c, ids, ranges[base[vi]:base[vi + 1]], bg, fragile, depth_check=fragile_tol > 0.0))
+        views.append(render(pr, c, ids, ranges[base[vi]:base[vi + 1]], bg, fragile, depth_check=fragile_tol > 0.0,
+                            pos_tol=pos_rel * max(c["width"], c["height"]), t_tol=t_tol))
     return {"proj": projs, "keys": keys, "ids": ids, "ranges": ranges, "views": views, "tile_base": base}
 
 

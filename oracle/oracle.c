@@ -416,17 +416,24 @@ typedef struct {
     int amb;       /* a decision within rounding of its threshold */
 } pair_t;
 
+/* Ambiguity margins. A decision is flagged when the quantity it compares is
+ * within rounding of its threshold: pos_tol (pixels) bounds how far the
+ * compared implementation's projected centre may sit from this one's (0
+ * when both render the same projected records). */
+typedef struct { double pos_tol, t_tol; } tol_t;
+
 /* One (pixel, Gaussian) pair. proj is planar [ONF][N]. */
-static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py, pair_t *e)
+static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py, const tol_t *tol, pair_t *e)
 {
     double u = proj[0 * N + id], v = proj[1 * N + id], r = proj[10 * N + id];
     double a = proj[3 * N + id], b = proj[4 * N + id], c = proj[5 * N + id], o = proj[6 * N + id];
+    double pt = tol ? tol->pos_tol : 0.0;
     e->amb = 0;
     e->inside = 0;
     e->dx = px + 0.5 - u;
     e->dy = py + 0.5 - v;
     double d2 = e->dx * e->dx + e->dy * e->dy, r2 = r * r;
-    if (fabs(d2 - r2) <= 1e-6 * (r2 > 1.0 ? r2 : 1.0)) e->amb = 1;
+    if (fabs(d2 - r2) <= 1e-6 * (r2 > 1.0 ? r2 : 1.0) + 2.0 * r * pt + pt * pt) e->amb = 1;
     if (d2 > r2) return;
     double qa = 0.5 * a * e->dx * e->dx, qc = 0.5 * c * e->dy * e->dy, qb = b * e->dx * e->dy;
     double power = -qa - qc - qb;
@@ -435,7 +442,10 @@ static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py
     e->G = exp(power);
     e->og = o * e->G;
     e->alpha = e->og < ALPHA_MAX ? e->og : ALPHA_MAX;
-    if (fabs(e->alpha - ALPHA_MIN) <= 1e-5 * ALPHA_MIN) e->amb = 1;
+    /* alpha threshold in the log domain: rounding of the exponent, plus the
+     * exponent's change when the centre moves by pos_tol */
+    double lmargin = 1e-5 + 1e-5 * fabs(power) + 2.0 * sqrt(fabs(power) * (a + c)) * pt;
+    if (fabs(log(e->alpha / ALPHA_MIN)) <= lmargin) e->amb = 1;
     if (e->alpha < ALPHA_MIN) return;
     e->inside = 1;
 }
@@ -453,7 +463,7 @@ static int depth_near(const double *proj, int64_t N, uint32_t i0, uint32_t i1)
 /* Forward composition of one pixel over list[0..n). Writes colour, T, the
  * position after the last blended entry, the number blended, and flags. */
 static void composite_pixel(const double *proj, int64_t N, const uint32_t *list, int64_t n, int px, int py,
-                            const double *bg, const uint8_t *fragile, int depth_check,
+                            const double *bg, const uint8_t *fragile, int depth_check, const tol_t *tol,
                             double out[3], double *Tout, uint32_t *last, uint32_t *ncontrib,
                             uint8_t *amb, int64_t *evaluated)
 {
@@ -465,7 +475,7 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
     for (int64_t k = 0; k < n; k++) {
         uint32_t id = list[k];
         pair_t e;
-        eval_pair(proj, N, id, px, py, &e);
+        eval_pair(proj, N, id, px, py, tol, &e);
         ev++;
         if (e.amb) am = 1;
         if (fragile && fragile[id]) {
@@ -475,7 +485,7 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
         }
         if (!e.inside) continue;
         double Tn = T * (1.0 - e.alpha);
-        if (fabs(Tn - T_MIN) <= 1e-5 * T_MIN) am = 1;
+        if (fabs(Tn - T_MIN) <= (tol ? tol->t_tol : 1e-5) * T_MIN) am = 1;
         if (Tn < T_MIN) break;
         if (depth_check && prev >= 0 && depth_near(proj, N, (uint32_t)prev, id)) am = 1;
         for (int ch = 0; ch < 3; ch++) C[ch] += proj[(7 + ch) * N + id] * e.alpha * T;
@@ -499,8 +509,10 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
  * counts[0] = list entries evaluated, counts[1] = blended pairs. */
 int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uint32_t *ids,
                   const uint32_t *ranges, const double *bg, const uint8_t *fragile, int32_t depth_check,
+                  double pos_tol, double t_tol,
                   double *rgb, double *Tout, uint32_t *last, uint32_t *ncontrib, uint8_t *amb, int64_t *counts)
 {
+    tol_t tol = {pos_tol, t_tol};
     int64_t TX = tiles_of(W), TY = tiles_of(H);
     int64_t ev_total = 0, nc_total = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : ev_total, nc_total)
@@ -513,7 +525,8 @@ int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uin
                 uint32_t l, nc;
                 uint8_t a;
                 int64_t ev;
-                composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, c, &T, &l, &nc, &a, &ev);
+                composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, &tol, c, &T, &l, &nc, &a,
+                                &ev);
                 int64_t p = (int64_t)py * W + px;
                 for (int ch = 0; ch < 3; ch++) rgb[(int64_t)ch * W * H + p] = c[ch];
                 Tout[p] = T;
@@ -561,7 +574,7 @@ int oracle_render_brute(const double *proj, int64_t N, int32_t W, int32_t H, con
         uint32_t l, nc;
         uint8_t a;
         int64_t ev;
-        composite_pixel(proj, N, order, n, px, py, bg, NULL, 0, c, &T, &l, &nc, &a, &ev);
+        composite_pixel(proj, N, order, n, px, py, bg, NULL, 0, NULL, c, &T, &l, &nc, &a, &ev);
         for (int ch = 0; ch < 3; ch++) rgb[(int64_t)ch * W * H + p] = c[ch];
         Tout[p] = T;
         if (ncontrib) ncontrib[p] = nc;
@@ -611,7 +624,7 @@ int oracle_render_bwd(const double *proj, int64_t N, int32_t W, int32_t H, const
                 int64_t nr = 0;
                 for (int64_t k = s; k < e; k++) {
                     pair_t pe;
-                    eval_pair(proj, N, ids[k], px, py, &pe);
+                    eval_pair(proj, N, ids[k], px, py, NULL, &pe);
                     if (!pe.inside) continue;
                     double Tn = T * (1.0 - pe.alpha);
                     if (Tn < T_MIN) break;

@@ -103,29 +103,55 @@ __device__ __forceinline__ bool tile_culls(T bx0, T bx1, T by0, T by1, T u, T v,
     return T(0.5) * qmin > log(o * T(255)) + margin;
 }
 
-// Stages the records of list positions [first, first + cnt) that can touch
-// the tile, compacted in list order, with a mask of the four 16x4 pixel
-// bands of the tile they can touch; returns how many were kept. A band is
-// exactly one wavefront's pixels in every launch shape, so the render loops
-// skip a band with a wave-uniform branch.
+// Records of one chunk held in registers between the gather and the LDS
+// commit, so the next chunk's gathers are in flight while the current chunk
+// is composited.
+template <typename T, int CHUNK, int NT> struct Fetched {
+    static constexpr int R = (CHUNK + NT - 1) / NT;
+    V4<T> r0[R], r1[R], r2[R];
+    uint32_t id[R];
+    int cnt;
+    uint32_t pos0;
+};
+
 template <typename T, int CHUNK, int NT>
-__device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__restrict__ proj, int64_t vbase,
-                                             const uint32_t *__restrict__ ids, int64_t first, int cnt,
-                                             uint32_t pos0, T bx0, T by0)
+__device__ __forceinline__ void fetch_records(Fetched<T, CHUNK, NT> &f, const T *__restrict__ proj, int64_t vbase,
+                                              const uint32_t *__restrict__ ids, int64_t first, int cnt, uint32_t pos0)
+{
+    f.cnt = cnt;
+    f.pos0 = pos0;
+    for (int rr = 0; rr < Fetched<T, CHUNK, NT>::R; rr++) {
+        int q = rr * NT + threadIdx.x;
+        if (q < cnt) {
+            uint32_t id = ids[first + q];
+            const V4<T> *rec = reinterpret_cast<const V4<T> *>(proj + (vbase + id) * REC);
+            f.id[rr] = id;
+            f.r0[rr] = rec[0];
+            f.r1[rr] = rec[1];
+            f.r2[rr] = rec[2];
+        }
+    }
+}
+
+// Commits fetched records that can touch the tile to LDS, compacted in list
+// order, with a mask of the four 16x4 pixel bands of the tile each can touch;
+// returns how many were kept. A band is exactly one wavefront's pixels in
+// every launch shape, so the render loops skip a band with a wave-uniform
+// branch.
+template <typename T, int CHUNK, int NT>
+__device__ __forceinline__ int commit_records(Stage<T, CHUNK> &st, const Fetched<T, CHUNK, NT> &f, T bx0, T by0)
 {
     constexpr int NW = NT / 64;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint64_t lt = (1ull << lane) - 1ull;
     int kept = 0;
-    for (int r0 = 0; r0 < cnt; r0 += NT) {
-        int q = r0 + threadIdx.x;
+    for (int rr = 0; rr < Fetched<T, CHUNK, NT>::R; rr++) {
+        int q = rr * NT + threadIdx.x;
+        if (rr * NT >= f.cnt) break;
         uint32_t bands = 0;
         V4<T> sa, sb, sc;
-        uint32_t id = 0;
-        if (q < cnt) {
-            id = ids[first + q];
-            const V4<T> *rec = reinterpret_cast<const V4<T> *>(proj + (vbase + id) * REC);
-            V4<T> r0v = rec[0], r1 = rec[1], r2 = rec[2];
+        if (q < f.cnt) {
+            V4<T> r0v = f.r0[rr], r1 = f.r1[rr], r2 = f.r2[rr];
             T rad = r2.y;
             sa = V4<T>{r0v.x, r0v.y, rad * rad, r1.y};
             sb = V4<T>{r0v.z, r0v.w, r1.x, T(0)};
@@ -161,8 +187,8 @@ __device__ __forceinline__ int stage_records(Stage<T, CHUNK> &st, const T *__res
             st.b[slot] = sb;
             st.c[slot] = sc;
             st.d[slot] = V4<T>{na, nb, nc, T(0)};
-            st.id[slot] = id;
-            st.pos[slot] = pos0 + (uint32_t)q;
+            st.id[slot] = f.id[rr];
+            st.pos[slot] = f.pos0 + (uint32_t)q;
             st.band[slot] = bands;
         }
     }
@@ -201,11 +227,15 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
     uint32_t walked = 0;
     if (threadIdx.x == 0) *s_red = 0;
     T bx0 = (T)(tx * TILE) + T(0.5), by0 = (T)(ty * TILE) + T(0.5);
+    Fetched<T, CHUNK, NT> fr;
+    if (s < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, s, (int)min((uint32_t)CHUNK, e - s), 0u);
     for (uint32_t base = s; base < e; base += CHUNK) {
-        int cnt = (int)min((uint32_t)CHUNK, e - base);
         __syncthreads();
-        int kept = stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, base, cnt, base - s, bx0, by0);
+        int kept = commit_records<T, CHUNK, NT>(st, fr, bx0, by0);
+        int cnt = fr.cnt;
         __syncthreads();
+        uint32_t nb = base + CHUNK;
+        if (nb < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, nb, (int)min((uint32_t)CHUNK, e - nb), nb - s);
         bool alldone = true;
         for (int j = 0; j < PX; j++) alldone &= done[j];
         for (int q = 0; q < kept && !alldone; q++) {
@@ -315,12 +345,20 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     uint32_t s = A.ranges[2 * (int64_t)g];
     int64_t vbase = (int64_t)v * A.n;
     T bx0 = (T)(tx * TILE) + T(0.5), by0 = (T)(ty * TILE) + T(0.5);
+    Fetched<T, CHUNK, NT> fr;
+    if (Lmax > 0) {
+        int64_t lo0 = (int64_t)Lmax - CHUNK > 0 ? (int64_t)Lmax - CHUNK : 0;
+        fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, (int64_t)s + lo0, (int)(Lmax - lo0), (uint32_t)lo0);
+    }
     for (int64_t hi = Lmax; hi > 0; hi -= CHUNK) {
+        __syncthreads();
+        int kept = commit_records<T, CHUNK, NT>(st, fr, bx0, by0);
+        __syncthreads();
         int64_t lo = hi - CHUNK > 0 ? hi - CHUNK : 0;
-        int cnt = (int)(hi - lo);
-        __syncthreads();
-        int kept = stage_records<T, CHUNK, NT>(st, A.proj, vbase, A.ids, (int64_t)s + lo, cnt, (uint32_t)lo, bx0, by0);
-        __syncthreads();
+        if (lo > 0) {
+            int64_t lo2 = lo - CHUNK > 0 ? lo - CHUNK : 0;
+            fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, (int64_t)s + lo2, (int)(lo - lo2), (uint32_t)lo2);
+        }
         for (int q = kept - 1; q >= 0; q--) {
             uint32_t k = st.pos[q];
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
@@ -332,28 +370,30 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
                 if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
                 T dx, dy, G, og, alpha;
                 bool ok = eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha);
-                ok = ok && (k < L[j]);
-                any = any || ok;
-                T Tk = Tr[j] / (T(1) - alpha);
-                T w = alpha * Tk;
-                T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
-                T dalpha = ((rc.x - Bc[j][0]) * gx + (rc.y - Bc[j][1]) * gy + (rc.z - Bc[j][2]) * gz) * Tk;
-                T om = T(1) - alpha;
-                acc[6] += ok ? w * gx : T(0);
-                acc[7] += ok ? w * gy : T(0);
-                acc[8] += ok ? w * gz : T(0);
-                Bc[j][0] = ok ? alpha * rc.x + om * Bc[j][0] : Bc[j][0];
-                Bc[j][1] = ok ? alpha * rc.y + om * Bc[j][1] : Bc[j][1];
-                Bc[j][2] = ok ? alpha * rc.z + om * Bc[j][2] : Bc[j][2];
-                Tr[j] = ok ? Tk : Tr[j];
-                bool grad_ok = ok && (og <= K<T>::alpha_max);   // the 0.99 clamp has no gradient
-                T dpow = grad_ok ? dalpha * og : T(0);
-                acc[5] += grad_ok ? dalpha * G : T(0);
-                acc[0] += grad_ok ? dpow * (rb.x * dx + rb.y * dy) : T(0);
-                acc[1] += grad_ok ? dpow * (rb.y * dx + rb.z * dy) : T(0);
-                acc[2] += grad_ok ? T(-0.5) * dpow * dx * dx : T(0);
-                acc[3] += grad_ok ? -dpow * dx * dy : T(0);
-                acc[4] += grad_ok ? T(-0.5) * dpow * dy * dy : T(0);
+                if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian
+                    any = true;
+                    T Tk = Tr[j] / (T(1) - alpha);
+                    T w = alpha * Tk;
+                    T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
+                    acc[6] += w * gx;
+                    acc[7] += w * gy;
+                    acc[8] += w * gz;
+                    T dalpha = ((rc.x - Bc[j][0]) * gx + (rc.y - Bc[j][1]) * gy + (rc.z - Bc[j][2]) * gz) * Tk;
+                    T om = T(1) - alpha;
+                    Bc[j][0] = alpha * rc.x + om * Bc[j][0];
+                    Bc[j][1] = alpha * rc.y + om * Bc[j][1];
+                    Bc[j][2] = alpha * rc.z + om * Bc[j][2];
+                    Tr[j] = Tk;
+                    if (og <= K<T>::alpha_max) {   // the 0.99 clamp has no gradient
+                        T dpow = dalpha * og;
+                        acc[5] += dalpha * G;
+                        acc[0] += dpow * (rb.x * dx + rb.y * dy);
+                        acc[1] += dpow * (rb.y * dx + rb.z * dy);
+                        acc[2] += T(-0.5) * dpow * dx * dx;
+                        acc[3] += -dpow * dx * dy;
+                        acc[4] += T(-0.5) * dpow * dy * dy;
+                    }
+                }
             }
             if (__ballot(any) == 0) continue;
             for (int c = 0; c < 9; c++) acc[c] = wave_sum(acc[c]);

@@ -75,6 +75,7 @@ class BatchedTrainer:
         self.graph = None
         self.overflows = 0
         self._flag_host = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        self._skip_flag = torch.ones(1, dtype=torch.int32, device=dev)
 
     def _make_sched(self):
         c = self.cfg
@@ -133,13 +134,38 @@ class BatchedTrainer:
                         self.last, self.work_fwd, self.work_bwd)
         self.backward_and_update()
 
+    def warmup(self):
+        """Runs every kernel of the step once (sizing the instance buffers on
+        the way) without changing the training state: the Adam launch gets a
+        skip flag, so parameters, moments and the step counter stay as they
+        were and the gradient is cleared."""
+        while True:
+            try:
+                R.gs_project(self.P, self.cams, self.proj)
+                R.gs_bin_sort(self.proj, self.n, self.cams, self.bins, check_capacity=True)
+                break
+            except _lib.GsError as e:
+                if e.status != _lib.GS_ERR_CAPACITY:
+                    raise
+                self.overflows += 1
+                self._grow()
+        R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
+                        self.last, self.work_fwd, self.work_bwd)
+        R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
+        R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
+                               self.dproj, self.cfg.bg, self.sched_bwd)
+        R.gs_project_bwd(self.P, self.cams, self.proj, self.dproj, self.grad, clear=True)
+        R.gs_adam_step(self.P, self.grad, self.m, self.v, self.hp, self.step_dev, self.scratch,
+                       skip_flag=self._skip_flag)
+
     def capture(self):
-        """Captures one whole step as a HIP graph (after an eager warm-up)."""
+        """Captures one whole step as a HIP graph (after a state-preserving
+        warm-up of every kernel)."""
         torch.cuda.synchronize()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.step_eager()
+            self.warmup()
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()

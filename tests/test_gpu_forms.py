@@ -106,19 +106,39 @@ def _small_batch():
 
 
 def test_batched_step_equals_plain_per_view_step():
+    """Same loss and the same gradient (to float-atomic order) from the batched
+    step and the view-by-view plain path; over three steps the losses track."""
     from paper_2406_18533_amd import _lib, train
+    from paper_2406_18533_amd import raster as R
     P, cams, tgt = _small_batch()
     cfg = train.TrainConfig(graph=False, mode=_lib.GS_SCHED_PER_TILE)
     bt = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), cfg)
     pt = train.PlainTrainer(P.cuda(), cams, tgt.cuda(), cfg)
+    # gradients of one step (Adam not applied: its normalisation amplifies the
+    # rounding differences of near-zero gradient components)
+    bt.forward(check=True)
+    R.gs_loss_l1(bt.rgb, bt.targets, bt.cams, bt.loss_buf)
+    R.gs_render_bwd(bt.P, bt.proj, bt.bins, bt.cams, bt.T, bt.last, bt.loss_buf.dL, bt.grad, cfg.bg,
+                    bt.sched_bwd, dprojected=bt.dproj)
+    g_plain = torch.zeros_like(pt.P)
+    for cm, tg, lb in zip(pt.cams, pt.targets, pt.bufs):
+        R.gs_project(pt.P, cm, pt.proj)
+        R.gs_bin_sort(pt.proj, pt.n, cm, pt.bins)
+        rgb, T, last = R.gs_render_fwd(pt.proj, pt.n, pt.bins, cm, cfg.bg)
+        R.gs_loss_l1(rgb, tg, cm, lb, scale=1.0 / pt.V)
+        R.gs_render_bwd(pt.P, pt.proj, pt.bins, cm, T, last, lb.dL, g_plain, cfg.bg, dprojected=pt.dproj)
+    torch.cuda.synchronize()
+    assert abs(bt.loss() - pt.loss()) <= 1e-6 * pt.loss()
+    err = (bt.grad - g_plain).norm() / g_plain.norm()
+    assert err < 1e-5, err
+    bt.grad.zero_()
     for _ in range(3):
         bt.step()
         pt.step()
         torch.cuda.synchronize()
-        assert abs(bt.loss() - pt.loss()) <= 1e-6 * max(pt.loss(), 1e-12)
-    err = (bt.P - pt.P).abs().max().item()
-    assert err < 1e-5, err
+        assert abs(bt.loss() - pt.loss()) <= 1e-4 * pt.loss()
     assert bt.step_dev.item() == pt.step_dev.item() == 3
+    assert (bt.P - pt.P).abs().max().item() < 1e-3
 
 
 def test_graph_replay_equals_eager_steps():

@@ -167,7 +167,7 @@ def roofline(timings: dict, counts: dict):
     return out, per
 
 
-def cpu_baseline(workload, sample_views: int = 1):
+def cpu_baseline(workload, sample_views: int = 6):
     """The FP64 oracle on a bounded sample: the whole per-view pipeline of one
     view of the batch (transformation, binning, render, loss, render and
     transformation backward) plus one Adam step, extrapolated to the batch."""

@@ -210,12 +210,15 @@ __global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restr
     __syncthreads();
     uint64_t lt = (1ull << lane) - 1ull;
     for (int64_t t = t0; t < t1; t++) {
-        int64_t base = t * STILE;
+        int64_t base = t * STILE + (int64_t)w * (SITEMS * 64) + lane;
+        uint32_t kk[SITEMS];
+        for (int it = 0; it < SITEMS; it++) {      // all loads of the tile in flight at once
+            int64_t idx = base + it * 64;
+            kk[it] = idx < n ? kin[idx] : 0u;
+        }
         for (int it = 0; it < SITEMS; it++) {
-            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
-            bool valid = idx < n;
-            uint32_t k = valid ? kin[idx] : 0u;
-            uint32_t d = (k >> shift) & (RADIX - 1);
+            bool valid = base + it * 64 < n;
+            uint32_t d = (kk[it] >> shift) & (RADIX - 1);
             uint64_t peers = match_digit<BITS>(d, valid);
             if (valid && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
         }
@@ -254,11 +257,16 @@ __global__ void __launch_bounds__(SB) radix_scatter_kernel(const uint32_t *__res
         for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
         __syncthreads();
         uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
+        for (int it = 0; it < SITEMS; it++) {      // all loads of the tile in flight at once
+            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
+            key[it] = idx < n ? kin[idx] : 0u;
+            val[it] = idx < n ? vin[idx] : 0u;
+        }
         for (int it = 0; it < SITEMS; it++) {
             int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
             bool valid = idx < n;
-            uint32_t k = valid ? kin[idx] : 0u;
-            uint32_t v = valid ? vin[idx] : 0u;
+            uint32_t k = key[it];
+            uint32_t v = val[it];
             uint32_t d = (k >> shift) & (RADIX - 1);
             uint64_t peers = match_digit<BITS>(d, valid);
             uint32_t before = s_cnt[w][d];

@@ -164,6 +164,73 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+{
+    for (int off = 32; off > 0; off >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, off, 64));
+    return x;
+}
+
+// Row-local inclusive scan over rows of 16 lanes: lane 15 of each row ends
+// with the row's sum.
+__device__ __forceinline__ float row_sum16(float x)
+{
+    x += dpp_move<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_move<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_move<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_move<0x118, 0xf>(x);  // row_shr:8
+    return x;
+}
+
+// One butterfly step of a transposed reduction: permlane32_swap exchanges
+// the upper 32 lanes of `a` with the lower 32 lanes of `b`, so the sum holds
+// a's pairwise half-sums in lanes 0-31 and b's in lanes 32-63.
+__device__ __forceinline__ float fold32(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// permlane16_swap exchanges the odd rows of `a` with the even rows of `b`:
+// the sum holds a's row-pair sums in rows 0 and 2 and b's in rows 1 and 3.
+__device__ __forceinline__ float fold16(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Adds the wavefront sums of the 9 per-lane values v[0..8] to dst[0..8] with
+// three global atomics (8 values through a transposed permlane/DPP reduction,
+// the ninth through a plain one).
+__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst)
+{
+    int lane = threadIdx.x & 63;
+    // after fold32, rows 0-1 hold the first value of a pair, rows 2-3 the second
+    float x01 = fold32(v[0], v[1]), x23 = fold32(v[2], v[3]);
+    float x45 = fold32(v[4], v[5]), x67 = fold32(v[6], v[7]);
+    // after fold16, rows 0..3 hold values (0, 2, 1, 3) and (4, 6, 5, 7)
+    float z0 = row_sum16(fold16(x01, x23));
+    float z1 = row_sum16(fold16(x45, x67));
+    float s8 = wave_sum(v[8]);
+    if ((lane & 15) == 15) {
+        int row = lane >> 4;
+        int comp = (row & 1) * 2 + (row >> 1);   // row 0 -> 0, 1 -> 2, 2 -> 1, 3 -> 3
+        unsafeAtomicAdd(dst + comp, z0);
+        unsafeAtomicAdd(dst + 4 + comp, z1);
+    }
+    if (lane == 0) unsafeAtomicAdd(dst + 8, s8);
+}
+
+__device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *dst)
+{
+    int lane = threadIdx.x & 63;
+    double r = v[0];
+    for (int c = 0; c < 9; c++) {
+        double t = wave_sum(v[c]);
+        r = lane == c ? t : r;
+    }
+    if (lane < 9) unsafeAtomicAdd(dst + lane, r);
+}
+
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 

@@ -298,14 +298,6 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
 }
 
 // ------------------------------------------------------------------ backward tile
-template <typename T>
-__device__ __forceinline__ T lane_pick(const T (&acc)[9], int lane)
-{
-    T r = acc[0];
-    for (int c = 1; c < 9; c++) r = lane == c ? acc[c] : r;
-    return r;
-}
-
 template <typename T, int PX, int CHUNK>
 __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
 {
@@ -337,6 +329,8 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         }
         mymax = max(mymax, L[j]);
     }
+    uint32_t Lband[PX];     // per band (one wavefront's pixels): the largest last
+    for (int j = 0; j < PX; j++) Lband[j] = wave_max(L[j]);
     if (threadIdx.x == 0) *s_red = 0;
     __syncthreads();
     atomicMax(s_red, mymax);
@@ -368,6 +362,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             bool any = false;
             for (int j = 0; j < PX; j++) {
                 if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
+                if (k >= Lband[j]) continue;                         // past every last contributor of the band
                 T dx, dy, G, og, alpha;
                 bool ok = eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha);
                 if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian
@@ -396,11 +391,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
                 }
             }
             if (__ballot(any) == 0) continue;
-            for (int c = 0; c < 9; c++) acc[c] = wave_sum(acc[c]);
-            if (lane < 9) {
-                T *dst = A.dproj + (vbase + st.id[q]) * REC;
-                atomic_add(dst + lane, lane_pick(acc, lane));
-            }
+            wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC);
         }
     }
 }

@@ -222,21 +222,33 @@ def test_server_result_alone_equals_result_in_the_mix():
 
 
 def test_checkpoint_resume_continues_the_trajectory(tmp_path):
-    """6 steps, save, 6 more == 12 steps straight (to float-atomic rounding)."""
+    """6 steps, save, load into a fresh trainer, 6 more == 12 steps straight.
+
+    The saved state round-trips exactly. The two continuations then differ
+    only by float-atomic summation order, which Adam turns into steps of up
+    to lr on near-zero gradients, so they are compared by how far each moved
+    the parameters (relative), by loss, and by the step counter."""
     from paper_2406_18533_amd import train
     P, cams, tgt = _small_batch()
-    ref = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
+    P0 = P.cuda()
+    ref = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=True))
     for _ in range(12):
         ref.step()
-    a = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
+    a = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=True))
     for _ in range(6):
         a.step()
     torch.save(a.state_dict(), tmp_path / "ck.pt")
-    b = train.BatchedTrainer(P.cuda() * 0 + P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=True))
-    b.load_state_dict(torch.load(tmp_path / "ck.pt", weights_only=True))
+    sd = torch.load(tmp_path / "ck.pt", weights_only=True)
+    b = train.BatchedTrainer(P0.clone() * 0, cams, tgt.cuda(), train.TrainConfig(graph=True))
+    b.load_state_dict(sd)
+    for name, x in (("params", b.P), ("m", b.m), ("v", b.v), ("step", b.step_dev),
+                    ("work_fwd", b.work_fwd), ("work_bwd", b.work_bwd)):
+        assert torch.equal(x.detach(), sd[name]), name
     for _ in range(6):
         b.step()
     torch.cuda.synchronize()
     assert b.step_dev.item() == ref.step_dev.item() == 12
-    err = (b.P - ref.P).abs().max().item()
-    assert err < 1e-4, err
+    moved = (ref.P - P0).norm().item()
+    rel = (b.P - ref.P).norm().item() / moved
+    assert moved > 0 and rel < 0.05, (rel, moved)
+    assert abs(b.loss() - ref.loss()) <= 1e-3 * abs(ref.loss()) + 1e-6, (b.loss(), ref.loss())

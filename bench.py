@@ -143,6 +143,39 @@ def algorithmic(c: dict) -> dict:
     }
 
 
+# Kernel sources whose HBM traffic per launch was measured with hardware counters.
+TRAFFIC_SOURCES = {"gs_render_bwd_pixels": ["render.hip", "common.hpp"],
+                   "gs_render_fwd": ["render.hip", "common.hpp"]}
+
+
+def source_digest(entry: str):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES.get(entry, []):
+        with open(os.path.join(ROOT, "paper_2406_18533_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(entry: str):
+    """HBM bytes per launch of the entry's kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
+    None when there is none or the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "render_16x1080p_1M_hbm_traffic.md")
+    if entry not in TRAFFIC_SOURCES or not os.path.exists(path):
+        return None
+    rows = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("| `gs_"):
+                cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+                rows[cells[0]] = cells
+    r = rows.get(entry)
+    if r is None or r[1] != source_digest(entry):
+        return None
+    return int(float(r[-1]))
+
+
 def roofline(timings: dict, counts: dict):
     work = algorithmic(counts)
     dom = max(timings, key=lambda k: timings[k])
@@ -155,7 +188,7 @@ def roofline(timings: dict, counts: dict):
         achieved = amount / sec / 1e12
         out = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
     out["frac"] = round(achieved / out["peak"], 4)
-    out["traffic"] = None
+    out["traffic"] = measured_traffic(dom)
     out["kernel"] = dom
     out["ms"] = round(timings[dom], 4)
     per = {}
@@ -312,6 +345,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-aerial", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="end with a fill and a copy of this many MiB (calibration for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (a multi-GPU run would "
@@ -391,6 +426,14 @@ def main():
     if not args.no_cpu:
         log("CPU oracle baseline (sample)")
         cpu = cpu_baseline(w)
+    if args.copy_mib:
+        log(f"calibration: fill then copy of {args.copy_mib} MiB")
+        a = torch.empty(args.copy_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     cams = w.cameras
     out = {
         "metric": "train views/s fwd+bwd (1080p, 4K) vs plain path; render p50/p99 ms at fixed QPS",

@@ -66,7 +66,9 @@ typedef enum { GS_F32 = 0, GS_F64 = 1 } gs_dtype;
 /* A pinhole camera. R is world -> camera (row-major), t its translation, so a
  * world point x maps to R x + t in the camera frame (+x right, +y down, +z
  * forward); the camera centre is -R^T t. Pixels project to
- * (fx X/Z + cx, fy Y/Z + cy). Gaussians with Z <= znear are culled. */
+ * (fx X/Z + cx, fy Y/Z + cy). Gaussians with Z <= znear are culled.
+ * Image sides are 1..65536 pixels with at most 2^22 16x16 tiles per view
+ * (e.g. 32768 x 32768); other sizes are rejected with GS_ERR_ARG. */
 typedef struct gs_camera {
     int32_t width, height;
     double fx, fy, cx, cy;
@@ -132,9 +134,10 @@ gs_status gs_init(int32_t device);
 /* Bytes of a projected buffer: views * n records of GS_REC scalars, then two
  * planar uint32 side arrays [views][n]: tiles touched and FP32 depth bits. */
 size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views);
-/* Sum over the views of ceil(W/16) * ceil(H/16) [host cameras]. */
+/* Sum over the views of ceil(W/16) * ceil(H/16) [host cameras]; -1 (with
+ * gs_last_error set) when a camera is rejected. */
 int64_t gs_total_tiles(const gs_camera *cams_host, int32_t views);
-/* Total pixels over the views [host cameras]. */
+/* Total pixels over the views [host cameras]; -1 as above. */
 int64_t gs_total_pixels(const gs_camera *cams_host, int32_t views);
 size_t gs_bin_workspace_bytes(int64_t n, int32_t views, int64_t capacity, int64_t total_tiles);
 size_t gs_sched_workspace_bytes(int64_t total_tiles, int32_t queues);

@@ -87,7 +87,9 @@ static bool cams_ok(const gs_camera *cams, int32_t views, std::string &why)
             why = "bad intrinsics";
             return false;
         }
-        tiles += (int64_t)((c.width + 15) / 16) * ((c.height + 15) / 16);
+        int64_t vt = (int64_t)((c.width + 15) / 16) * ((c.height + 15) / 16);
+        if (vt > (int64_t(1) << 22)) { why = "image too large (at most 2^22 tiles per view)"; return false; }
+        tiles += vt;
     }
     if (tiles >= (int64_t(1) << 31)) { why = "too many tiles"; return false; }
     return true;
@@ -139,14 +141,14 @@ size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views)
 int64_t gs_total_tiles(const gs_camera *cams, int32_t views)
 {
     std::string why;
-    if (!cams_ok(cams, views, why)) return -1;
+    if (!cams_ok(cams, views, why)) { fail(GS_ERR_ARG, why); return -1; }
     return make_view_table(cams, views).total_tiles;
 }
 
 int64_t gs_total_pixels(const gs_camera *cams, int32_t views)
 {
     std::string why;
-    if (!cams_ok(cams, views, why)) return -1;
+    if (!cams_ok(cams, views, why)) { fail(GS_ERR_ARG, why); return -1; }
     return make_view_table(cams, views).pix_base[views];
 }
 

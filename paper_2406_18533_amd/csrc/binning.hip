@@ -92,25 +92,47 @@ __global__ void __launch_bounds__(SB) scan_partials_kernel(U *partial, int64_t n
     if (threadIdx.x == 0 && total_out) *total_out = (int64_t)total;
 }
 
+// LDS slot of item i of a 4096-item tile: one pad word per 32 items keeps
+// the per-thread (blocked) accesses off a single bank.
+__device__ __forceinline__ int pad_slot(int i) { return i + (i >> 5); }
+
+// Second pass of the scan: each block scans its tile of 4096 items and
+// stores the exclusive prefix of every item (plus the block's offset).
+// Items are loaded and stored coalesced (item j*256 + thread of the tile)
+// and transposed through LDS to the blocked order the scan needs.
 template <typename U, typename Load, typename Store>
 __global__ void __launch_bounds__(SB) scan_down_kernel(Load load, Store store, const int64_t *n_dev, int64_t n_max,
                                                        const U *partial)
 {
+    __shared__ U sm[STILE + STILE / 32];
     int64_t n = count_of(n_dev, n_max);
     int64_t base = (int64_t)blockIdx.x * STILE;
     if (base >= n) return;
-    int64_t t0 = base + (int64_t)threadIdx.x * SITEMS;
+    for (int j = 0; j < SITEMS; j++) {
+        int i = j * SB + threadIdx.x;
+        sm[pad_slot(i)] = base + i < n ? load(base + i) : U(0);
+    }
+    __syncthreads();
     U vals[SITEMS];
     U acc = 0;
     for (int j = 0; j < SITEMS; j++) {
-        vals[j] = (t0 + j < n) ? load(t0 + j) : U(0);
+        vals[j] = sm[pad_slot(threadIdx.x * SITEMS + j)];
         acc += vals[j];
     }
     U total;
-    U run = block_excl_scan(acc, total) + partial[blockIdx.x];
+    U run = block_excl_scan(acc, total) + partial[blockIdx.x];   // (synchronises the block)
     for (int j = 0; j < SITEMS; j++) {
-        if (t0 + j < n) store(t0 + j, run, vals[j]);
+        sm[pad_slot(threadIdx.x * SITEMS + j)] = run;             // exclusive prefix, in place
         run += vals[j];
+    }
+    __syncthreads();
+    U end = partial[blockIdx.x] + total;
+    for (int j = 0; j < SITEMS; j++) {
+        int i = j * SB + threadIdx.x;
+        if (base + i >= n) break;
+        U pre = sm[pad_slot(i)];
+        U nxt = i + 1 < STILE ? sm[pad_slot(i + 1)] : end;
+        store(base + i, pre, (U)(nxt - pre));
     }
 }
 
@@ -144,10 +166,9 @@ struct CompactStore {
     }
 };
 
-struct CountLoad {
-    const uint32_t *tiles;
-    const uint32_t *flat;
-    __device__ uint64_t operator()(int64_t j) const { return (uint64_t)tiles[flat[j]]; }
+struct U32AsU64Load {
+    const uint32_t *p;
+    __device__ uint64_t operator()(int64_t j) const { return (uint64_t)p[j]; }
 };
 
 struct U64Store {
@@ -377,10 +398,18 @@ static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uin
 }
 
 // ---------------------------------------------------------------- emit and ranges
-// One block emits the instances of 256 consecutive depth-sorted pairs: their
-// offsets and tile rectangles go to LDS, then every thread writes one
-// instance at a time (coalesced), finding its pair by binary search over the
-// block's offsets and its tile from the position inside the pair's rectangle.
+// One block emits the instances of 256 consecutive depth-sorted pairs. Their
+// first-instance offsets (relative to the block's first instance) and tile
+// rectangles go to LDS; each wavefront then writes a contiguous quarter of
+// the block's instances, 64 at a time (coalesced). A wavefront finds the
+// pair of its first instance by binary search once; inside a window of 64
+// instances the pairs that start there are flagged in LDS, and each lane's
+// pair is the window's first pair plus the flags at or below its lane
+// (ballot + mbcnt). The tile follows from the position inside the pair's
+// rectangle: row = floor((local + 1/2) / width) through a float reciprocal,
+// exact because a view has at most 2^22 tiles, so local + 1/2 < 2^22 keeps
+// the rounding error (below (local + 1/2) 2^-23 / width) under the
+// 1/(2 width) distance of the quotient from an integer.
 template <typename T>
 __global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, int64_t n, ViewTable vt,
                                                    const uint32_t *__restrict__ flat, const uint64_t *__restrict__ off,
@@ -388,13 +417,16 @@ __global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, i
                                                    uint32_t *__restrict__ tile_out, uint32_t *__restrict__ id_out,
                                                    int64_t capacity)
 {
-    __shared__ uint64_t s_off[257];
-    __shared__ uint32_t s_x0[256], s_w[256], s_y0[256], s_base[256], s_tx[256], s_id[256];
+    __shared__ uint32_t s_off[256], s_xy[256], s_w[256], s_base[256], s_tx[256], s_id[256];
+    __shared__ float s_rw[256];
+    __shared__ uint32_t s_end;
+    __shared__ uint8_t s_start[4][64];
     int64_t m = count_of(m_dev, m_max);
     int64_t j0 = (int64_t)blockIdx.x * 256;
     if (j0 >= m) return;
     int64_t j = j0 + threadIdx.x;
     int cnt = (int)(m - j0 < 256 ? m - j0 : 256);
+    uint64_t e_beg = off[j0];
     if (j < m) {
         uint32_t f = flat[j];
         uint32_t v = f / (uint32_t)n;
@@ -403,31 +435,66 @@ __global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, i
         TileRect r;
         if (!tile_rect((float)rec[R_U], (float)rec[R_V], (float)rec[R_RADIUS], vt.width[v], vt.height[v], r))
             r.x0 = r.x1 = r.y0 = r.y1 = 0;   // not reached: compacted pairs touch at least one tile
-        s_off[threadIdx.x] = off[j];
-        s_x0[threadIdx.x] = (uint32_t)r.x0;
-        s_w[threadIdx.x] = (uint32_t)(r.x1 - r.x0 + 1);
-        s_y0[threadIdx.x] = (uint32_t)r.y0;
+        uint32_t w = (uint32_t)(r.x1 - r.x0 + 1);
+        s_off[threadIdx.x] = (uint32_t)(off[j] - e_beg);
+        s_xy[threadIdx.x] = (uint32_t)r.x0 | ((uint32_t)r.y0 << 16);
+        s_w[threadIdx.x] = w;
+        s_rw[threadIdx.x] = 1.0f / (float)w;
         s_base[threadIdx.x] = (uint32_t)vt.tile_base[v];
         s_tx[threadIdx.x] = (uint32_t)vt.tiles_x[v];
         s_id[threadIdx.x] = i;
     }
-    if (threadIdx.x == 0) s_off[256] = (j0 + 256 < m) ? off[j0 + 256] : (uint64_t)*k_dev;
+    if (threadIdx.x == 0) s_end = (uint32_t)(((j0 + 256 < m) ? off[j0 + 256] : (uint64_t)*k_dev) - e_beg);
     __syncthreads();
-    uint64_t e_beg = s_off[0], e_end = s_off[256];
+    uint64_t e_end = e_beg + s_end;
     if (e_end > (uint64_t)capacity) e_end = (uint64_t)capacity;
-    for (uint64_t e = e_beg + threadIdx.x; e < e_end; e += 256) {
-        int lo = 0, hi = cnt - 1;     // last pair with s_off <= e
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= e) lo = mid;
-            else hi = mid - 1;
-        }
-        uint32_t local = (uint32_t)(e - s_off[lo]);
-        uint32_t w = s_w[lo];
-        uint32_t dy = local / w, dx = local - dy * w;
-        tile_out[e] = s_base[lo] + (s_y0[lo] + dy) * s_tx[lo] + s_x0[lo] + dx;
-        id_out[e] = s_id[lo];
+    if (e_end <= e_beg) return;
+    uint32_t tot = (uint32_t)(e_end - e_beg);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t per = ((tot + 3) / 4 + 63) & ~63u;   // whole windows per wavefront
+    uint32_t a = (uint32_t)w * per;
+    uint32_t b = min(a + per, tot);
+    if (a >= b) return;                            // wave-uniform
+    int lo = 0, hi = cnt - 1;                      // last pair starting at or before a
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= a) lo = mid;
+        else hi = mid - 1;
     }
+    int p = lo;   // every pair after p starts at or after the current window
+    for (uint32_t e0 = a; e0 < b; e0 += 64) {
+        int q = p + 1 + lane;
+        uint32_t st = q < cnt ? s_off[q] : 0xffffffffu;
+        s_start[w][lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (st - e0 < 64u) s_start[w][st - e0] = 1;   // pairs have distinct starts (each has >= 1 instance)
+        __builtin_amdgcn_wave_barrier();
+        uint32_t fl = s_start[w][lane];
+        uint64_t mask = __ballot(fl != 0);
+        uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        int pr = p + (int)(below + fl);            // pair of instance e0 + lane
+        uint32_t e = e0 + (uint32_t)lane;
+        if (e < b) {
+            uint32_t local = e - s_off[pr];
+            uint32_t wd = s_w[pr];
+            uint32_t dy = (uint32_t)(((float)local + 0.5f) * s_rw[pr]);
+            uint32_t dx = local - dy * wd;
+            uint32_t xy = s_xy[pr];
+            tile_out[e_beg + e] = s_base[pr] + ((xy >> 16) + dy) * s_tx[pr] + (xy & 0xffffu) + dx;
+            id_out[e_beg + e] = s_id[pr];
+        }
+        p = __shfl(pr, 63, 64);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Tile counts of the visible pairs in depth order (one gather, so the two
+// passes of the offsets scan read them coalesced).
+__global__ void gather_counts_kernel(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ flat,
+                                     const int64_t *m_dev, int64_t m_max, uint32_t *__restrict__ out)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count_of(m_dev, m_max)) out[j] = tiles[flat[j]];
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
@@ -436,16 +503,33 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
     if (j < n) p[j] = value;
 }
 
+// Start and end of every tile's run in the sorted keys. Each thread checks
+// four consecutive keys (one 16-byte load) against their neighbours.
 __global__ void ranges_kernel(const uint32_t *__restrict__ tiles, const int64_t *k_dev, int64_t cap,
                               int64_t n_tiles, uint32_t *__restrict__ ranges)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     int64_t K = count_of(k_dev, cap);
-    if (k >= K) return;
-    uint32_t t = tiles[k];
-    if (t >= (uint32_t)n_tiles) return;
-    if (k == 0 || tiles[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
-    if (k == K - 1 || tiles[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+    if (k0 >= K) return;
+    uint32_t t[4];
+    if (k0 + 4 <= K && (reinterpret_cast<uintptr_t>(tiles) & 15) == 0) {
+        uint4 q = *reinterpret_cast<const uint4 *>(tiles + k0);   // k0 is a multiple of 4
+        t[0] = q.x; t[1] = q.y; t[2] = q.z; t[3] = q.w;
+    } else {
+        for (int i = 0; i < 4; i++) t[i] = k0 + i < K ? tiles[k0 + i] : 0u;
+    }
+    uint32_t prev = k0 > 0 ? tiles[k0 - 1] : 0u;
+    uint32_t next = k0 + 4 < K ? tiles[k0 + 4] : 0u;
+    for (int i = 0; i < 4; i++) {
+        int64_t k = k0 + i;
+        if (k >= K) break;
+        uint32_t ti = t[i];
+        if (ti >= (uint32_t)n_tiles) continue;
+        uint32_t before = i == 0 ? prev : t[i - 1];
+        uint32_t after = i == 3 ? next : t[i + 1];
+        if (k == 0 || before != ti) ranges[2 * (int64_t)ti] = (uint32_t)k;
+        if (k == K - 1 || after != ti) ranges[2 * (int64_t)ti + 1] = (uint32_t)(k + 1);
+    }
 }
 
 __global__ void overflow_kernel(const int64_t *k_dev, int64_t cap, int32_t *overflow)
@@ -523,8 +607,12 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
     // 2. stable sort by FP32 depth bits (positive depths: 31 significant bits)
     e = radix_sort(ws.k1, ws.v1, ws.k1b, ws.v1b, ws.m_dev, vn, 32, ws.hist, (uint32_t *)ws.partial, s);
     if (e != hipSuccess) return e;
-    // 3. instance offsets in depth order
-    e = device_scan<uint64_t>(CountLoad{tiles, ws.v1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
+    // 3. instance offsets in depth order (the sorted depth keys are dead now:
+    // their buffer holds the gathered tile counts)
+    if (vn > 0)
+        hipLaunchKernelGGL(gather_counts_kernel, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, tiles,
+                           (const uint32_t *)ws.v1, (const int64_t *)ws.m_dev, vn, ws.k1);
+    e = device_scan<uint64_t>(U32AsU64Load{ws.k1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap, b->overflow);
     if (check) {
@@ -550,7 +638,7 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
                    s);
     if (e != hipSuccess) return e;
     if (cap > 0)
-        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((cap + 1023) / 1024)), dim3(256), 0, s,
                            (const uint32_t *)b->tile_keys, (const int64_t *)b->n_instances, cap, T_all, b->ranges);
     return hipGetLastError();
 }

@@ -115,25 +115,45 @@ template <typename T> __device__ __forceinline__ void scaled_conic(T a, T b, T c
     nc = T(-0.5) * l2e * c;
 }
 
-// One (pixel, Gaussian) pair, evaluated without branches: offset from the
-// Gaussian's centre, falloff G, opacity times falloff og, alpha =
-// min(0.99, og), and whether the pair counts (centre inside the radius
-// circle, exponent <= 0, alpha >= 1/255). Invalid lanes may hold inf or NaN
-// in G/og/alpha; callers select on `ok`, never multiply by it. The forward
-// and backward kernels both call this, so their decisions agree bit for bit.
-template <typename T>
-__device__ __forceinline__ bool eval_alpha(T pxc, T pyc, T u, T v, T r2, T na, T nb, T nc, T o,
-                                           T &dx, T &dy, T &G, T &og, T &alpha)
+// Falloff terms that depend on the pixel column only. Every pixel a thread
+// owns sits in the same column of the tile, so these are computed once per
+// (thread, Gaussian) and shared by the thread's pixels.
+template <typename T> struct ColTerms {
+    T dx, dx2, qx, nbdx;   // offset, offset^2, na*offset^2, nb*offset
+};
+
+template <typename T> __device__ __forceinline__ ColTerms<T> col_terms(T pxc, T u, T na, T nb)
 {
-    dx = pxc - u;
+    ColTerms<T> c;
+    c.dx = pxc - u;
+    c.dx2 = c.dx * c.dx;
+    c.qx = (na * c.dx) * c.dx;
+    c.nbdx = nb * c.dx;
+    return c;
+}
+
+// One (pixel, Gaussian) pair, evaluated without branches: row offset dy,
+// falloff G, opacity times falloff og, alpha = min(0.99, og), and whether
+// the pair counts (centre inside the radius circle, exponent <= 0,
+// alpha >= 1/255). The exponent is qx + dy (nb dx + nc dy) in log2 units.
+// Invalid lanes may hold inf or NaN in G/og/alpha; callers select on `ok`,
+// never multiply by it. The forward and backward kernels both call this, so
+// their decisions agree bit for bit.
+template <typename T>
+__device__ __forceinline__ bool eval_alpha(const ColTerms<T> &c, T pyc, T v, T r2, T nc, T o,
+                                           T &dy, T &G, T &og, T &alpha)
+{
     dy = pyc - v;
-    T d2 = fma(dx, dx, dy * dy);
-    T p2 = fma(na * dx, dx, fma(nc * dy, dy, (nb * dx) * dy));   // exponent in log2 units
+    T d2 = fma(dy, dy, c.dx2);
+    T p2 = fma(dy, fma(nc, dy, c.nbdx), c.qx);
     G = exp2_t(p2);
     og = o * G;
     alpha = fmin(og, K<T>::alpha_max);
     return (d2 <= r2) & (p2 <= T(0)) & (alpha >= K<T>::alpha_min);
 }
+
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };

@@ -7,8 +7,9 @@
 // (one gathered 48-byte record per entry), and every thread walks the staged
 // records for its pixels. In the backward pass the list is walked in reverse
 // from the tile's largest `last`, the blend is undone with T_k = T_{k+1} /
-// (1 - alpha_k), and the per-Gaussian gradients of a wavefront are summed
-// with DPP before one global atomic per component.
+// (1 - alpha_k), and the nine per-Gaussian gradient sums of a wavefront are
+// reduced together (a transposed permlane/DPP reduction) before three global
+// atomics.
 //
 // Work distribution:
 //  - per-tile mode: one workgroup per tile; workgroup b runs tile
@@ -200,27 +201,28 @@ template <typename T, int PX, int CHUNK, bool STATS>
 __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
 {
     uint32_t n_eval = 0, n_blend = 0;
-    const int wave_id = threadIdx.x >> 6;
+    const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NT = 256 / PX;
     int v = view_of_tile(vt, g);
     int local = g - vt.tile_base[v];
     int TX = vt.tiles_x[v];
     int tx = local % TX, ty = local / TX;
     int W = vt.width[v], H = vt.height[v];
-    T pxc[PX], pyc[PX], Tr[PX], C[PX][3];
+    // a thread's pixels share one column: NT is a multiple of the tile width
+    const T pxc = (T)(tx * TILE + (threadIdx.x & 15)) + T(0.5);
+    // Tr: transmittance, stored negated once the pixel is finished (it
+    // saturated, or it lies outside the image), which saves a flag per pixel
+    T pyc[PX], Tr[PX], C[PX][3];
     uint32_t lastp[PX];
-    bool done[PX];
     bool inside[PX];
     for (int j = 0; j < PX; j++) {
         int p = threadIdx.x + j * NT;
         int px = tx * TILE + (p & 15), py = ty * TILE + (p >> 4);
         inside[j] = px < W && py < H;
-        pxc[j] = (T)px + T(0.5);
         pyc[j] = (T)py + T(0.5);
-        Tr[j] = T(1);
+        Tr[j] = inside[j] ? T(1) : T(-1);
         C[j][0] = C[j][1] = C[j][2] = T(0);
         lastp[j] = 0;
-        done[j] = !inside[j];
     }
     uint32_t s = A.ranges[2 * (int64_t)g], e = A.ranges[2 * (int64_t)g + 1];
     int64_t vbase = (int64_t)v * A.n;
@@ -237,36 +239,43 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         uint32_t nb = base + CHUNK;
         if (nb < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, nb, (int)min((uint32_t)CHUNK, e - nb), nb - s);
         bool alldone = true;
-        for (int j = 0; j < PX; j++) alldone &= done[j];
-        for (int q = 0; q < kept && !alldone; q++) {
+        for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);
+        if (__ballot(!alldone) == 0) kept = 0;   // this wavefront's pixels are all finished
+        for (int q = 0; q < kept; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
-            uint32_t bm = st.band[q] >> wave_id;
-            uint32_t pos1 = st.pos[q] + 1;
-            alldone = true;
+            uint32_t bm = __builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id;   // wave-uniform
+            uint32_t pos1 = __builtin_amdgcn_readfirstlane(st.pos[q]) + 1;
+            ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             for (int j = 0; j < PX; j++) {
                 if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
-                    T dx, dy, G, og, alpha;
-                    bool ok = eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha);
-                    bool was_done = done[j];
-                    ok = ok && !was_done;
-                    T Tn = Tr[j] * (T(1) - alpha);
+                    T dy, G, og, alpha;
+                    bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
+                    T Tj = Tr[j];
+                    bool live = Tj > T(0);
+                    ok = ok && live;
+                    T Tn = Tj * (T(1) - alpha);
                     bool stop = ok && (Tn < K<T>::t_min);
                     bool bl = ok && !stop;
-                    T w = bl ? alpha * Tr[j] : T(0);
-                    C[j][0] += rc.x * w;
-                    C[j][1] += rc.y * w;
-                    C[j][2] += rc.z * w;
-                    Tr[j] = bl ? Tn : Tr[j];
+                    T w = bl ? alpha * Tj : T(0);
+                    C[j][0] = fma(rc.x, w, C[j][0]);
+                    C[j][1] = fma(rc.y, w, C[j][1]);
+                    C[j][2] = fma(rc.z, w, C[j][2]);
+                    Tr[j] = bl ? Tn : (stop ? -Tj : Tj);
                     lastp[j] = bl ? pos1 : lastp[j];
-                    done[j] = done[j] || stop;
                     if (STATS) {
-                        n_eval += was_done ? 0u : 1u;
+                        n_eval += live ? 1u : 0u;
                         n_blend += bl ? 1u : 0u;
                     }
                 }
-                alldone &= done[j];
+            }
+            if ((q & 3) == 3) {   // wave-uniform exit once every pixel of the wavefront is finished
+                alldone = true;
+                for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);
+                if (__ballot(!alldone) == 0) break;
             }
         }
+        alldone = true;
+        for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);
         walked += cnt;
         if (!__syncthreads_or(!alldone)) break;
     }
@@ -278,10 +287,11 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         int64_t pix = vt.pix_base[v] + (int64_t)py * W + px;
         int64_t plane = (int64_t)W * H;
         T *rgb = A.rgb + 3 * vt.pix_base[v] + (int64_t)py * W + px;
-        rgb[0] = C[j][0] + Tr[j] * A.bg[0];
-        rgb[plane] = C[j][1] + Tr[j] * A.bg[1];
-        rgb[2 * plane] = C[j][2] + Tr[j] * A.bg[2];
-        A.finalT[pix] = Tr[j];
+        T Tf = fabs(Tr[j]);
+        rgb[0] = C[j][0] + Tf * A.bg[0];
+        rgb[plane] = C[j][1] + Tf * A.bg[1];
+        rgb[2 * plane] = C[j][2] + Tf * A.bg[2];
+        A.finalT[pix] = Tf;
         A.last[pix] = lastp[j];
         mylast = max(mylast, lastp[j]);
     }
@@ -307,9 +317,11 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     int TX = vt.tiles_x[v];
     int tx = local % TX, ty = local / TX;
     int W = vt.width[v], H = vt.height[v];
-    int lane = threadIdx.x & 63;
-    const int wave_id = threadIdx.x >> 6;
-    T pxc[PX], pyc[PX], Tr[PX], gr[PX][3], Bc[PX][3];
+    const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const T pxc = (T)(tx * TILE + (threadIdx.x & 15)) + T(0.5);   // one column per thread
+    // Sg: the colour composited behind the current Gaussian, dotted with the
+    // pixel's colour gradient (only that product enters the gradients)
+    T pyc[PX], Tr[PX], gr[PX][3], Sg[PX];
     uint32_t L[PX];
     uint32_t mymax = 0;
     int64_t plane = (int64_t)W * H;
@@ -317,20 +329,17 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         int p = threadIdx.x + j * NT;
         int px = tx * TILE + (p & 15), py = ty * TILE + (p >> 4);
         bool in = px < W && py < H;
-        pxc[j] = (T)px + T(0.5);
         pyc[j] = (T)py + T(0.5);
         int64_t pix = vt.pix_base[v] + (int64_t)py * W + px;
         const T *dl = A.dL + 3 * vt.pix_base[v] + (int64_t)py * W + px;
         Tr[j] = in ? A.finalT[pix] : T(1);
         L[j] = in ? A.last[pix] : 0u;
-        for (int ch = 0; ch < 3; ch++) {
-            gr[j][ch] = in ? dl[ch * plane] : T(0);
-            Bc[j][ch] = A.bg[ch];
-        }
+        for (int ch = 0; ch < 3; ch++) gr[j][ch] = in ? dl[ch * plane] : T(0);
+        Sg[j] = fma(gr[j][0], A.bg[0], fma(gr[j][1], A.bg[1], gr[j][2] * A.bg[2]));
         mymax = max(mymax, L[j]);
     }
     uint32_t Lband[PX];     // per band (one wavefront's pixels): the largest last
-    for (int j = 0; j < PX; j++) Lband[j] = wave_max(L[j]);
+    for (int j = 0; j < PX; j++) Lband[j] = __builtin_amdgcn_readfirstlane(wave_max(L[j]));
     if (threadIdx.x == 0) *s_red = 0;
     __syncthreads();
     atomicMax(s_red, mymax);
@@ -354,40 +363,41 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, (int64_t)s + lo2, (int)(lo - lo2), (uint32_t)lo2);
         }
         for (int q = kept - 1; q >= 0; q--) {
-            uint32_t k = st.pos[q];
+            uint32_t k = __builtin_amdgcn_readfirstlane(st.pos[q]);                  // wave-uniform
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
-            uint32_t bm = st.band[q] >> wave_id;
+            uint32_t bm = __builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id;
             T acc[9];
             for (int c = 0; c < 9; c++) acc[c] = T(0);
             bool any = false;
+            ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
+            const T dx = col.dx;
             for (int j = 0; j < PX; j++) {
                 if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
                 if (k >= Lband[j]) continue;                         // past every last contributor of the band
-                T dx, dy, G, og, alpha;
-                bool ok = eval_alpha(pxc[j], pyc[j], ra.x, ra.y, ra.z, rd.x, rd.y, rd.z, ra.w, dx, dy, G, og, alpha);
+                T dy, G, og, alpha;
+                bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
                 if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian
                     any = true;
-                    T Tk = Tr[j] / (T(1) - alpha);
+                    T om = T(1) - alpha;
+                    T Tk = Tr[j] * rcp_t(om);          // transmittance in front of this Gaussian
                     T w = alpha * Tk;
                     T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
-                    acc[6] += w * gx;
-                    acc[7] += w * gy;
-                    acc[8] += w * gz;
-                    T dalpha = ((rc.x - Bc[j][0]) * gx + (rc.y - Bc[j][1]) * gy + (rc.z - Bc[j][2]) * gz) * Tk;
-                    T om = T(1) - alpha;
-                    Bc[j][0] = alpha * rc.x + om * Bc[j][0];
-                    Bc[j][1] = alpha * rc.y + om * Bc[j][1];
-                    Bc[j][2] = alpha * rc.z + om * Bc[j][2];
+                    acc[6] = fma(w, gx, acc[6]);
+                    acc[7] = fma(w, gy, acc[7]);
+                    acc[8] = fma(w, gz, acc[8]);
+                    T cg = fma(rc.x, gx, fma(rc.y, gy, rc.z * gz));
+                    T dalpha = (cg - Sg[j]) * Tk;
+                    Sg[j] = fma(alpha, cg, om * Sg[j]);
                     Tr[j] = Tk;
-                    if (og <= K<T>::alpha_max) {   // the 0.99 clamp has no gradient
-                        T dpow = dalpha * og;
-                        acc[5] += dalpha * G;
-                        acc[0] += dpow * (rb.x * dx + rb.y * dy);
-                        acc[1] += dpow * (rb.y * dx + rb.z * dy);
-                        acc[2] += T(-0.5) * dpow * dx * dx;
-                        acc[3] += -dpow * dx * dy;
-                        acc[4] += T(-0.5) * dpow * dy * dy;
-                    }
+                    T live = og <= K<T>::alpha_max ? dalpha : T(0);   // the 0.99 clamp has no gradient
+                    T dpow = live * og;
+                    T hx = dpow * dx, hy = dpow * dy;
+                    acc[5] = fma(live, G, acc[5]);
+                    acc[0] = fma(rb.x, hx, fma(rb.y, hy, acc[0]));
+                    acc[1] = fma(rb.y, hx, fma(rb.z, hy, acc[1]));
+                    acc[2] = fma(T(-0.5) * hx, dx, acc[2]);
+                    acc[3] = fma(-hx, dy, acc[3]);
+                    acc[4] = fma(T(-0.5) * hy, dy, acc[4]);
                 }
             }
             if (__ballot(any) == 0) continue;

@@ -56,6 +56,12 @@ def test_host_side_sizes_and_argument_checks():
     assert L.gs_project(_lib.GS_F32, None, 10, None, p, 1, None, None) == _lib.GS_ERR_ARG
     assert b"null" in L.gs_last_error()
     assert L.gs_adam_step(_lib.GS_F32, None, None, None, None, 5, None, None, None, None, None) == _lib.GS_ERR_ARG
+    cams[1].width, cams[1].height = 32768, 32768          # 2^22 tiles: the largest accepted view
+    assert L.gs_total_tiles(p, 2) == 120 * 68 + 2048 * 2048
+    cams[1].height = 32769                                  # one tile row more
+    assert L.gs_total_tiles(p, 2) == -1
+    assert b"2^22 tiles" in L.gs_last_error()
+    cams[1].width, cams[1].height = 70, 45
     cams[1].fx = -1.0
     assert L.gs_total_tiles(p, 2) == -1
 

@@ -218,10 +218,18 @@ __device__ __forceinline__ float fold16(float a, float b)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Adds the wavefront sums of the 9 per-lane values v[0..8] to dst[0..8] with
-// three global atomics (8 values through a transposed permlane/DPP reduction,
-// the ninth through a plain one).
-__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst)
+// Adds the wavefront sums of the per-lane values v[0..8] to dst[0..8], each
+// times a factor, with three global atomics (8 values through a transposed
+// permlane/DPP reduction, the ninth through a plain one). The factors are
+// per lane (see sum9_lane_factors): sc0 for the lane that adds component
+// comp(lane) of v[0..3], sc1 for comp(lane) + 4, sc8 for v[8].
+__device__ __forceinline__ int sum9_comp(int lane)
+{
+    int row = (lane & 63) >> 4;
+    return (row & 1) * 2 + (row >> 1);   // row 0 -> 0, 1 -> 2, 2 -> 1, 3 -> 3
+}
+
+__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst, float sc0, float sc1, float sc8)
 {
     int lane = threadIdx.x & 63;
     // after fold32, rows 0-1 hold the first value of a pair, rows 2-3 the second
@@ -232,15 +240,15 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst
     float z1 = row_sum16(fold16(x45, x67));
     float s8 = wave_sum(v[8]);
     if ((lane & 15) == 15) {
-        int row = lane >> 4;
-        int comp = (row & 1) * 2 + (row >> 1);   // row 0 -> 0, 1 -> 2, 2 -> 1, 3 -> 3
-        unsafeAtomicAdd(dst + comp, z0);
-        unsafeAtomicAdd(dst + 4 + comp, z1);
+        int comp = sum9_comp(lane);
+        unsafeAtomicAdd(dst + comp, z0 * sc0);
+        unsafeAtomicAdd(dst + 4 + comp, z1 * sc1);
     }
-    if (lane == 0) unsafeAtomicAdd(dst + 8, s8);
+    if (lane == 0) unsafeAtomicAdd(dst + 8, s8 * sc8);
 }
 
-__device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *dst)
+// FP64: lane c (c < 9) adds component c, times sc0 (sc1 and sc8 unused).
+__device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *dst, double sc0, double, double)
 {
     int lane = threadIdx.x & 63;
     double r = v[0];
@@ -248,7 +256,7 @@ __device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *d
         double t = wave_sum(v[c]);
         r = lane == c ? t : r;
     }
-    if (lane < 9) unsafeAtomicAdd(dst + lane, r);
+    if (lane < 9) unsafeAtomicAdd(dst + lane, r * sc0);
 }
 
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }

@@ -64,44 +64,67 @@ template <typename T, int CHUNK> struct Stage {
     uint32_t wcnt[4];
 };
 
+// Per-record constants of the culling tests below.
+template <typename T> struct CullRec {
+    T u, v, a, b, c;
+    T ia, ic;      // 1/a, 1/c
+    T r2c;         // radius^2 with a relative and an absolute slack
+    T lim;         // log(255 opacity) + 0.01: the exponent bound where alpha reaches 1/255
+};
+
+__device__ __forceinline__ float log_t(float x) { return __logf(x); }
+__device__ __forceinline__ double log_t(double x) { return log(x); }
+
+template <typename T> __device__ __forceinline__ CullRec<T> cull_rec(T u, T v, T r2, T a, T b, T c, T o)
+{
+    CullRec<T> k;
+    k.u = u; k.v = v; k.a = a; k.b = b; k.c = c;
+    k.ia = rcp_t(a);
+    k.ic = rcp_t(c);
+    k.r2c = r2 * T(1.001) + T(0.01);
+    k.lim = log_t(o * T(255)) + T(0.01);
+    return k;
+}
+
 // Minimum over the box [lx, hx] x [ly, hy] of the quadratic form
 // a dx^2 + 2 b dx dy + c dy^2 (positive definite), with (dx, dy) measured from
-// the centre (u, v); 0 if the centre is inside the box.
+// the centre (u, v); 0 if the centre is inside the box. On each edge the
+// minimiser along the free coordinate is clamped into the edge; an inexact
+// minimiser only raises the value by a second-order amount.
 template <typename T>
-__device__ __forceinline__ T box_min_quadratic(T lx, T hx, T ly, T hy, T a, T b, T c)
+__device__ __forceinline__ T box_min_quadratic(T lx, T hx, T ly, T hy, const CullRec<T> &k)
 {
     if (lx <= T(0) && hx >= T(0) && ly <= T(0) && hy >= T(0)) return T(0);
     auto edge_x = [&](T dx) {        // dx fixed, dy free in [ly, hy]
-        T dy = fmin(fmax(-b * dx / c, ly), hy);
-        return a * dx * dx + T(2) * b * dx * dy + c * dy * dy;
+        T dy = fmin(fmax(-k.b * dx * k.ic, ly), hy);
+        return fma(k.a * dx, dx, fma(T(2) * k.b * dx, dy, k.c * dy * dy));
     };
     auto edge_y = [&](T dy) {        // dy fixed, dx free in [lx, hx]
-        T dx = fmin(fmax(-b * dy / a, lx), hx);
-        return a * dx * dx + T(2) * b * dx * dy + c * dy * dy;
+        T dx = fmin(fmax(-k.b * dy * k.ia, lx), hx);
+        return fma(k.a * dx, dx, fma(T(2) * k.b * dx, dy, k.c * dy * dy));
     };
     return fmin(fmin(edge_x(lx), edge_x(hx)), fmin(edge_y(ly), edge_y(hy)));
 }
 
 // Conservative test that a record cannot reach alpha >= 1/255 inside its
-// footprint circle at any pixel centre of the tile whose centres span
-// [bx0, bx1] x [by0, by1]. A pixel keeps a Gaussian only if its centre is
-// within the radius and o exp(-q/2) >= 1/255 with q the conic's quadratic
-// form; the test culls when the circle misses the whole box, or when the
-// box minimum of q already gives alpha below 1/255 by a margin that bounds
-// the rounding of the per-pixel evaluation (16 FP32 ulps of the largest
-// term a dx^2 + c dy^2 over the box, plus 0.01). A culled record is thus
-// skipped at every pixel anyway and the image is unchanged.
+// footprint circle at any pixel centre in [bx0, bx1] x [by0, by1]. A pixel
+// keeps a Gaussian only if its centre is within the radius and
+// o exp(-q/2) >= 1/255 with q the conic's quadratic form; the test culls when
+// the circle misses the whole box, or when the box minimum of q already gives
+// alpha below 1/255 by a margin that bounds the rounding of the per-pixel
+// evaluation (16 FP32 ulps of the largest term a dx^2 + c dy^2 over the box,
+// plus 0.01). A culled record is thus skipped at every pixel anyway and the
+// image is unchanged.
 template <typename T>
-__device__ __forceinline__ bool tile_culls(T bx0, T bx1, T by0, T by1, T u, T v, T r2, T a, T b, T c, T o)
+__device__ __forceinline__ bool box_culls(const CullRec<T> &k, T bx0, T bx1, T by0, T by1)
 {
-    if (o < K<T>::alpha_min) return true;                        // alpha <= opacity everywhere
-    T lx = bx0 - u, hx = bx1 - u, ly = by0 - v, hy = by1 - v;
+    T lx = bx0 - k.u, hx = bx1 - k.u, ly = by0 - k.v, hy = by1 - k.v;
     T ex = fmax(fmax(lx, -hx), T(0)), ey = fmax(fmax(ly, -hy), T(0));
-    if (ex * ex + ey * ey > r2 * T(1.001) + T(0.01)) return true;  // circle misses every centre
-    T qmin = box_min_quadratic(lx, hx, ly, hy, a, b, c);
+    if (ex * ex + ey * ey > k.r2c) return true;                   // circle misses every centre
+    T qmin = box_min_quadratic(lx, hx, ly, hy, k);
     T dmax2 = fmax(lx * lx, hx * hx) + fmax(ly * ly, hy * hy);
-    T margin = T(0.01) + T(1e-6) * (a + c) * dmax2;
-    return T(0.5) * qmin > log(o * T(255)) + margin;
+    T margin = T(1e-6) * (k.a + k.c) * dmax2;
+    return T(0.5) * qmin > k.lim + margin;
 }
 
 // Records of one chunk held in registers between the gather and the LDS
@@ -157,11 +180,12 @@ __device__ __forceinline__ int commit_records(Stage<T, CHUNK> &st, const Fetched
             sa = V4<T>{r0v.x, r0v.y, rad * rad, r1.y};
             sb = V4<T>{r0v.z, r0v.w, r1.x, T(0)};
             sc = V4<T>{r1.z, r1.w, r2.x, T(0)};
-            if (!tile_culls(bx0, bx0 + T(15), by0, by0 + T(15), sa.x, sa.y, sa.z, sb.x, sb.y, sb.z, sa.w))
-                for (int k = 0; k < 4; k++)
-                    if (!tile_culls(bx0, bx0 + T(15), by0 + T(4 * k), by0 + T(4 * k + 3), sa.x, sa.y, sa.z, sb.x, sb.y,
-                                    sb.z, sa.w))
-                        bands |= 1u << k;
+            if (sa.w >= K<T>::alpha_min) {   // alpha <= opacity everywhere
+                CullRec<T> k = cull_rec(sa.x, sa.y, sa.z, sb.x, sb.y, sb.z, sa.w);
+                for (int band = 0; band < 4; band++)
+                    if (!box_culls(k, bx0, bx0 + T(15), by0 + T(4 * band), by0 + T(4 * band + 3)))
+                        bands |= 1u << band;
+            }
         }
         bool keep = bands != 0;
         uint64_t m = __ballot(keep);
@@ -244,7 +268,7 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         for (int q = 0; q < kept; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
             uint32_t bm = __builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id;   // wave-uniform
-            uint32_t pos1 = __builtin_amdgcn_readfirstlane(st.pos[q]) + 1;
+            uint32_t pos1 = st.pos[q] + 1;
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             for (int j = 0; j < PX; j++) {
                 if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
@@ -254,8 +278,8 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
                     bool live = Tj > T(0);
                     ok = ok && live;
                     T Tn = Tj * (T(1) - alpha);
-                    bool stop = ok && (Tn < K<T>::t_min);
-                    bool bl = ok && !stop;
+                    bool bl = ok && (Tn >= K<T>::t_min);   // (Tn is finite wherever ok holds)
+                    bool stop = ok && !bl;
                     T w = bl ? alpha * Tj : T(0);
                     C[j][0] = fma(rc.x, w, C[j][0]);
                     C[j][1] = fma(rc.y, w, C[j][1]);
@@ -338,6 +362,18 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         Sg[j] = fma(gr[j][0], A.bg[0], fma(gr[j][1], A.bg[1], gr[j][2] * A.bg[2]));
         mymax = max(mymax, L[j]);
     }
+    // factors of the summed components: d/d(a, b, c) of the exponent
+    // -(a dx^2 + c dy^2)/2 - b dx dy are -1/2, -1, -1/2 times the sums kept
+    T sc0, sc1;
+    if (sizeof(T) == 4) {
+        int comp = sum9_comp(threadIdx.x);                  // components comp and comp + 4
+        sc0 = comp == 2 ? T(-0.5) : comp == 3 ? T(-1) : T(1);
+        sc1 = comp == 0 ? T(-0.5) : T(1);
+    } else {
+        int lane = threadIdx.x & 63;                        // component lane
+        sc0 = (lane == 2 || lane == 4) ? T(-0.5) : lane == 3 ? T(-1) : T(1);
+        sc1 = T(1);
+    }
     uint32_t Lband[PX];     // per band (one wavefront's pixels): the largest last
     for (int j = 0; j < PX; j++) Lband[j] = __builtin_amdgcn_readfirstlane(wave_max(L[j]));
     if (threadIdx.x == 0) *s_red = 0;
@@ -395,13 +431,13 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
                     acc[5] = fma(live, G, acc[5]);
                     acc[0] = fma(rb.x, hx, fma(rb.y, hy, acc[0]));
                     acc[1] = fma(rb.y, hx, fma(rb.z, hy, acc[1]));
-                    acc[2] = fma(T(-0.5) * hx, dx, acc[2]);
-                    acc[3] = fma(-hx, dy, acc[3]);
-                    acc[4] = fma(T(-0.5) * hy, dy, acc[4]);
+                    acc[2] = fma(hx, dx, acc[2]);   // times -1/2, -1, -1/2 after the reduction
+                    acc[3] = fma(hx, dy, acc[3]);
+                    acc[4] = fma(hy, dy, acc[4]);
                 }
             }
             if (__ballot(any) == 0) continue;
-            wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC);
+            wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC, sc0, sc1, T(1));
         }
     }
 }

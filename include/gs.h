@@ -132,7 +132,8 @@ gs_status gs_init(int32_t device);
 
 /* ------------------------------------------------------------------ sizes */
 /* Bytes of a projected buffer: views * n records of GS_REC scalars, then two
- * planar uint32 side arrays [views][n]: tiles touched and FP32 depth bits. */
+ * planar uint32 side arrays [views][n] (tiles touched, FP32 depth bits) and
+ * one planar uint64 array [views][n] (tile rectangle). */
 size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views);
 /* Sum over the views of ceil(W/16) * ceil(H/16) [host cameras]; -1 (with
  * gs_last_error set) when a camera is rejected. */
@@ -156,9 +157,11 @@ size_t gs_loss_workspace_bytes(const gs_camera *cams_host, int32_t views);
  * ceil(3 sqrt(largest eigenvalue)); rgb = max(0, SH(direction) + 1/2).
  * A record with radius 0 is culled (behind znear or non-finite); then only
  * radius and tiles touched (0) are defined; rgb is computed only for records
- * with tiles touched > 0. After the records the buffer holds tiles touched
- * and the FP32 bits of depth of every (view, Gaussian) as planar uint32
- * arrays (see gs_projected_bytes).
+ * with tiles touched > 0. After the records the buffer holds, for every
+ * (view, Gaussian), tiles touched and the FP32 bits of depth as planar
+ * uint32 arrays, then the touched tile rectangle as a planar uint64 array
+ * (tile columns x0, x1 and rows y0, y1, inclusive, in 16-bit fields from the
+ * low end; 0 when no tile is touched) (see gs_projected_bytes).
  * params: [59][n]. cams_dev: [views] cameras in device memory (read by the
  * kernel, so a captured graph sees updated poses); cams_host: the same
  * cameras [host] (image sizes). Requires 1 <= views <= GS_MAX_VIEWS,

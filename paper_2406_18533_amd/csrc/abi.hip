@@ -135,7 +135,7 @@ gs_status gs_init(int32_t device)
 size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views)
 {
     if (n < 0 || views < 0 || !dtype_ok(dtype)) return 0;
-    return (size_t)n * (size_t)views * (GS_REC * (dtype == GS_F64 ? 8 : 4) + 8);
+    return (size_t)n * (size_t)views * (GS_REC * (dtype == GS_F64 ? 8 : 4) + 16);
 }
 
 int64_t gs_total_tiles(const gs_camera *cams, int32_t views)

@@ -229,7 +229,6 @@ __global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restr
     int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
     __syncthreads();
-    uint64_t lt = (1ull << lane) - 1ull;
     for (int64_t t = t0; t < t1; t++) {
         int64_t base = t * STILE + (int64_t)w * (SITEMS * 64) + lane;
         uint32_t kk[SITEMS];
@@ -237,11 +236,8 @@ __global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restr
             int64_t idx = base + it * 64;
             kk[it] = idx < n ? kin[idx] : 0u;
         }
-        for (int it = 0; it < SITEMS; it++) {
-            bool valid = base + it * 64 < n;
-            uint32_t d = (kk[it] >> shift) & (RADIX - 1);
-            uint64_t peers = match_digit<BITS>(d, valid);
-            if (valid && (peers & lt) == 0) s_cnt[w][d] += (uint32_t)__popcll(peers);
+        for (int it = 0; it < SITEMS; it++) {       // counts only: LDS atomics, no ranks needed
+            if (base + it * 64 < n) atomicAdd(&s_cnt[w][(kk[it] >> shift) & (RADIX - 1)], 1u);
         }
     }
     __syncthreads();
@@ -380,7 +376,9 @@ static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uin
     uint32_t *kin = keys, *vin = vals, *ko = kalt, *vo = valt;
     for (int p = 0; p < passes; p++) {
         int shift = p * digit;
-        switch (digit) {
+        int width = bits - shift < digit ? bits - shift : digit;   // the last pass may be narrower
+        if (width < 1) width = 1;
+        switch (width) {
         case 1: radix_pass<1>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
         case 2: radix_pass<2>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
         case 3: radix_pass<3>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
@@ -410,8 +408,7 @@ static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uin
 // exact because a view has at most 2^22 tiles, so local + 1/2 < 2^22 keeps
 // the rounding error (below (local + 1/2) 2^-23 / width) under the
 // 1/(2 width) distance of the quotient from an integer.
-template <typename T>
-__global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, int64_t n, ViewTable vt,
+__global__ void __launch_bounds__(256) emit_kernel(const uint64_t *__restrict__ rects, int64_t n, ViewTable vt,
                                                    const uint32_t *__restrict__ flat, const uint64_t *__restrict__ off,
                                                    const int64_t *m_dev, int64_t m_max, const int64_t *k_dev,
                                                    uint32_t *__restrict__ tile_out, uint32_t *__restrict__ id_out,
@@ -431,13 +428,12 @@ __global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, i
         uint32_t f = flat[j];
         uint32_t v = f / (uint32_t)n;
         uint32_t i = f - v * (uint32_t)n;
-        const T *rec = proj + (int64_t)f * REC;
-        TileRect r;
-        if (!tile_rect((float)rec[R_U], (float)rec[R_V], (float)rec[R_RADIUS], vt.width[v], vt.height[v], r))
-            r.x0 = r.x1 = r.y0 = r.y1 = 0;   // not reached: compacted pairs touch at least one tile
-        uint32_t w = (uint32_t)(r.x1 - r.x0 + 1);
+        uint64_t r = rects[j];                       // x0, x1, y0, y1 in 16-bit fields
+        uint32_t x0 = (uint32_t)(r & 0xffffu), x1 = (uint32_t)((r >> 16) & 0xffffu);
+        uint32_t y0 = (uint32_t)((r >> 32) & 0xffffu);
+        uint32_t w = x1 - x0 + 1;
         s_off[threadIdx.x] = (uint32_t)(off[j] - e_beg);
-        s_xy[threadIdx.x] = (uint32_t)r.x0 | ((uint32_t)r.y0 << 16);
+        s_xy[threadIdx.x] = x0 | (y0 << 16);
         s_w[threadIdx.x] = w;
         s_rw[threadIdx.x] = 1.0f / (float)w;
         s_base[threadIdx.x] = (uint32_t)vt.tile_base[v];
@@ -488,13 +484,19 @@ __global__ void __launch_bounds__(256) emit_kernel(const T *__restrict__ proj, i
     }
 }
 
-// Tile counts of the visible pairs in depth order (one gather, so the two
-// passes of the offsets scan read them coalesced).
-__global__ void gather_counts_kernel(const uint32_t *__restrict__ tiles, const uint32_t *__restrict__ flat,
-                                     const int64_t *m_dev, int64_t m_max, uint32_t *__restrict__ out)
+// Tile rectangles and tile counts of the visible pairs in depth order (one
+// gather, so the offsets scan and the emission read them coalesced).
+__global__ void gather_rects_kernel(const uint64_t *__restrict__ rects, const uint32_t *__restrict__ flat,
+                                    const int64_t *m_dev, int64_t m_max, uint32_t *__restrict__ count_out,
+                                    uint64_t *__restrict__ rect_out)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < count_of(m_dev, m_max)) out[j] = tiles[flat[j]];
+    if (j >= count_of(m_dev, m_max)) return;
+    uint64_t r = rects[flat[j]];
+    uint32_t x0 = (uint32_t)(r & 0xffffu), x1 = (uint32_t)((r >> 16) & 0xffffu);
+    uint32_t y0 = (uint32_t)((r >> 32) & 0xffffu), y1 = (uint32_t)(r >> 48);
+    count_out[j] = (x1 - x0 + 1) * (y1 - y0 + 1);
+    rect_out[j] = r;
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
@@ -553,6 +555,7 @@ __global__ void keys64_kernel(const T *__restrict__ proj, int64_t n, ViewTable v
 struct BinWS {
     uint32_t *k1, *v1, *k1b, *v1b;   // [VN] depth keys / flat indices and alternates
     uint64_t *off;                   // [VN] instance offsets
+    uint64_t *rect;                  // [VN] tile rectangles of the visible pairs in depth order
     uint32_t *talt, *ialt;           // [cap] alternate tile keys / ids
     uint32_t *hist;                  // [512 * nbmax]
     uint64_t *partial;               // scan partials
@@ -575,6 +578,7 @@ size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws)
     w.k1b = (uint32_t *)take(4 * vn);
     w.v1b = (uint32_t *)take(4 * vn);
     w.off = (uint64_t *)take(8 * vn);
+    w.rect = (uint64_t *)take(8 * vn);
     w.talt = (uint32_t *)take(4 * cap);
     w.ialt = (uint32_t *)take(4 * cap);
     w.hist = (uint32_t *)take(4 * hist_n);
@@ -610,8 +614,9 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
     // 3. instance offsets in depth order (the sorted depth keys are dead now:
     // their buffer holds the gathered tile counts)
     if (vn > 0)
-        hipLaunchKernelGGL(gather_counts_kernel, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, tiles,
-                           (const uint32_t *)ws.v1, (const int64_t *)ws.m_dev, vn, ws.k1);
+        hipLaunchKernelGGL(gather_rects_kernel, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s,
+                           (const uint64_t *)side_rect<T>(proj, vn), (const uint32_t *)ws.v1,
+                           (const int64_t *)ws.m_dev, vn, ws.k1, ws.rect);
     e = device_scan<uint64_t>(U32AsU64Load{ws.k1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap, b->overflow);
@@ -628,7 +633,8 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
     }
     // 4. emission
     if (vn > 0)
-        hipLaunchKernelGGL(emit_kernel<T>, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s, proj, n, vt,
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s,
+                           (const uint64_t *)ws.rect, n, vt,
                            (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
                            (const int64_t *)b->n_instances, b->tile_keys, b->ids, cap);
     // 5. stable sort by global tile id

@@ -17,10 +17,12 @@ enum : int { R_U = 0, R_V = 1, R_A = 2, R_B = 3, R_C = 4, R_OPAC = 5, R_RGB = 6,
 // Slots of a projected-gradient entry.
 enum : int { D_U = 0, D_V = 1, D_A = 2, D_B = 3, D_C = 4, D_OPAC = 5, D_RGB = 6 };
 
-// The projected buffer holds the [views][n][REC] records followed by two
+// The projected buffer holds the [views][n][REC] records followed by three
 // planar side arrays over the same (view, Gaussian) index: tiles touched
-// (uint32) and the FP32 bits of depth (uint32). Binning and the backward
-// read these 4-byte fields contiguously instead of one field per record.
+// (uint32), the FP32 bits of depth (uint32) and the touched tile rectangle
+// (uint64: x0, x1, y0, y1 in 16-bit fields from the low end; 0 when no tile
+// is touched). Binning and the backward read these fields contiguously
+// instead of one field per record.
 template <typename T> __host__ __device__ inline uint32_t *side_tiles(const void *proj, int64_t vn)
 {
     return (uint32_t *)((char *)proj + vn * (int64_t)REC * (int64_t)sizeof(T));
@@ -28,6 +30,15 @@ template <typename T> __host__ __device__ inline uint32_t *side_tiles(const void
 template <typename T> __host__ __device__ inline uint32_t *side_depth(const void *proj, int64_t vn)
 {
     return side_tiles<T>(proj, vn) + vn;
+}
+template <typename T> __host__ __device__ inline uint64_t *side_rect(const void *proj, int64_t vn)
+{
+    return (uint64_t *)(side_tiles<T>(proj, vn) + 2 * vn);   // 8-byte aligned: records and two uint32 arrays
+}
+__host__ __device__ inline uint64_t pack_rect(int x0, int x1, int y0, int y1)
+{
+    return (uint64_t)(uint16_t)x0 | ((uint64_t)(uint16_t)x1 << 16) | ((uint64_t)(uint16_t)y0 << 32) |
+           ((uint64_t)(uint16_t)y1 << 48);
 }
 
 // Per-view image geometry, passed by value as a kernel argument.

@@ -214,6 +214,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
     uint64_t need_colour = 0;
     const int64_t vn = (int64_t)views * n;
     uint32_t *tiles_out = side_tiles<T>(out, vn), *depth_out = side_depth<T>(out, vn);
+    uint64_t *rect_out = side_rect<T>(out, vn);
     for (int v = 0; v < views; v++) {
         V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
         Camera<T> k = load_camera<T>(cams + v);
@@ -221,6 +222,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
         make_geo(x, S, k, g);
         tiles_out[(int64_t)v * n + i] = g.visible ? (uint32_t)g.tiles : 0u;
         depth_out[(int64_t)v * n + i] = g.visible ? __float_as_uint((float)g.y[2]) : 0u;
+        rect_out[(int64_t)v * n + i] =
+            g.visible && g.tiles > 0 ? pack_rect(g.rect.x0, g.rect.x1, g.rect.y0, g.rect.y1) : 0ull;
         if (!g.visible) {
             rec[2] = V4<T>{T(0), T(0), T(0), T(0)};
             continue;

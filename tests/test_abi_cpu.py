@@ -45,9 +45,9 @@ def test_host_side_sizes_and_argument_checks():
     p = C.cast(cams, C.POINTER(GsCamera))
     assert L.gs_total_tiles(p, 2) == 120 * 68 + 5 * 3
     assert L.gs_total_pixels(p, 2) == 1920 * 1080 + 70 * 45
-    # records plus two uint32 side arrays per (view, Gaussian)
-    assert L.gs_projected_bytes(_lib.GS_F32, 1000, 2) == 1000 * 2 * (12 * 4 + 8)
-    assert L.gs_projected_bytes(_lib.GS_F64, 1000, 2) == 1000 * 2 * (12 * 8 + 8)
+    # records plus two uint32 and one uint64 side arrays per (view, Gaussian)
+    assert L.gs_projected_bytes(_lib.GS_F32, 1000, 2) == 1000 * 2 * (12 * 4 + 16)
+    assert L.gs_projected_bytes(_lib.GS_F64, 1000, 2) == 1000 * 2 * (12 * 8 + 16)
     assert L.gs_bin_workspace_bytes(1000, 2, 5000, 135) > 0
     # rejected before any device call
     assert L.gs_project(_lib.GS_F32, None, 10, None, p, 0, None, None) == _lib.GS_ERR_ARG

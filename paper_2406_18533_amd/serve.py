@@ -20,6 +20,7 @@ from __future__ import annotations
 import collections
 import threading
 import time
+import weakref
 from concurrent.futures import Future
 from dataclasses import dataclass, field
 
@@ -57,10 +58,42 @@ class InstanceEstimator:
         self.rate[key] = new if old is None else max(new, 0.8 * old + 0.2 * new)
 
 
+class PinnedPool:
+    """Page-locked host buffers for finished images, reused by size. A result
+    image is a NumPy view of one buffer (no host copy); the buffer goes back
+    to the pool when the caller drops the image."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.free = collections.defaultdict(list)
+        self.lock = threading.Lock()
+        self.allocated = 0
+
+    def take(self, numel: int):
+        with self.lock:
+            lst = self.free.get(numel)
+            if lst:
+                return lst.pop()
+            self.allocated += 1
+        return self.torch.empty(numel, dtype=self.torch.float32, pin_memory=True)
+
+    def give(self, buf):
+        with self.lock:
+            self.free[buf.numel()].append(buf)
+
+    def lend(self, buf, shape):
+        """NumPy view of buf with the given shape; buf returns to the pool
+        once the view (and everything derived from it) is gone."""
+        arr = buf.view(*shape).numpy()
+        weakref.finalize(arr, self.give, buf)
+        return arr
+
+
 class GPUBackend:
     """Render slots on separate streams over one device-resident model. Each
     slot owns a projected buffer sized for max_views views; a smaller batch
-    uses its front (records, then the side arrays right after them)."""
+    uses its front (records, then the side arrays right after them). Images
+    come back to the host in pooled page-locked buffers (see PinnedPool)."""
 
     def __init__(self, params, slots: int = 2, max_views: int = 8, bg=(0.0, 0.0, 0.0)):
         import torch
@@ -72,6 +105,8 @@ class GPUBackend:
         self.max_views = max_views
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.flat = [R.alloc_projected(self.n, max_views, torch.float32, self.P.device) for _ in range(slots)]
+        self.counts = [torch.empty(2, dtype=torch.int64, pin_memory=True) for _ in range(slots)]
+        self.pool = PinnedPool(torch)
         self.inflight = {}
 
     @property
@@ -95,9 +130,14 @@ class GPUBackend:
             bins = R.Bins(self.n, cams, capacity)
             R.gs_bin_sort(view, self.n, cams, bins, check_capacity=False)
             rgb, _, _ = R.gs_render_fwd(view, self.n, bins, cams, self.bg)
-            host = torch.empty(rgb.shape, dtype=rgb.dtype, pin_memory=True)
-            host.copy_(rgb, non_blocking=True)
-            k_host = torch.empty(2, dtype=torch.int64, pin_memory=True)
+            host, o = [], 0
+            for c in cams_list:
+                k = 3 * c["width"] * c["height"]
+                buf = self.pool.take(k)
+                buf.copy_(rgb[o:o + k], non_blocking=True)
+                host.append(buf)
+                o += k
+            k_host = self.counts[slot]
             k_host[0:1].copy_(bins.n_instances, non_blocking=True)
             k_host[1:2].copy_(bins.overflow.to(torch.int64), non_blocking=True)
             ev = torch.cuda.Event()
@@ -110,11 +150,7 @@ class GPUBackend:
         if not ev.query():
             return None
         del self.inflight[slot]
-        out, o = [], 0
-        for c in cams_list:
-            k = 3 * c["width"] * c["height"]
-            out.append(host[o:o + k].view(3, c["height"], c["width"]).numpy().copy())
-            o += k
+        out = [self.pool.lend(buf, (3, c["height"], c["width"])) for buf, c in zip(host, cams_list)]
         return out, int(k_host[0]), bool(k_host[1])
 
     def render_now(self, slot: int, cams_list: list, capacity: int):
@@ -228,12 +264,13 @@ class RenderServer:
             for r, img in zip(batch, images):
                 self.est.observe(r.cam, int(per * r.cam["width"] * r.cam["height"]))
                 r.done = now
-                self.completed.append(r)
+                self.completed.append((r.arrival, r.start, r.done))   # timestamps only, not the image
                 r.future.set_result(img)
+            del images, batch
 
     # -- statistics -------------------------------------------------------------------------
     def latencies_ms(self):
-        return sorted((r.done - r.arrival) * 1e3 for r in self.completed)
+        return sorted((done - arrival) * 1e3 for arrival, _, done in self.completed)
 
 
 def percentile(xs, q):

@@ -224,6 +224,17 @@ def test_server_result_alone_equals_result_in_the_mix():
         assert np.array_equal(alone[0], img)
     lat = srv.latencies_ms()
     assert len(lat) == len(reqs)
+    # result images borrow pooled page-locked buffers: held images were never
+    # overwritten above (each alone render took a fresh buffer); once released,
+    # a buffer is reused instead of allocating another
+    import gc
+    keep = mixed[0].copy()
+    del futs, mixed, img, alone
+    gc.collect()
+    n_alloc = be.pool.allocated
+    again, _, _ = be.render_now(0, [reqs[0]], 4 << 20)
+    assert be.pool.allocated == n_alloc
+    assert np.array_equal(again[0], keep)
 
 
 def test_checkpoint_resume_continues_the_trajectory(tmp_path):

@@ -262,12 +262,14 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         __syncthreads();
         uint32_t nb = base + CHUNK;
         if (nb < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, nb, (int)min((uint32_t)CHUNK, e - nb), nb - s);
-        bool alldone = true;
-        for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);
-        if (__ballot(!alldone) == 0) kept = 0;   // this wavefront's pixels are all finished
+        // bit j (NT/64): slot j of this wavefront still has an unfinished pixel
+        uint32_t live_bands = 0;
+        for (int j = 0; j < PX; j++)
+            live_bands |= (__ballot(Tr[j] > T(0)) != 0 ? 1u : 0u) << (j * (NT / 64));
+        if (live_bands == 0) kept = 0;            // this wavefront's pixels are all finished
         for (int q = 0; q < kept; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
-            uint32_t bm = __builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id;   // wave-uniform
+            uint32_t bm = (__builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id) & live_bands;   // wave-uniform
             uint32_t pos1 = st.pos[q] + 1;
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             for (int j = 0; j < PX; j++) {
@@ -292,13 +294,14 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
                     }
                 }
             }
-            if ((q & 3) == 3) {   // wave-uniform exit once every pixel of the wavefront is finished
-                alldone = true;
-                for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);
-                if (__ballot(!alldone) == 0) break;
+            if ((q & 3) == 3) {   // drop finished bands; leave once every pixel of the wavefront is finished
+                live_bands = 0;
+                for (int j = 0; j < PX; j++)
+                    live_bands |= (__ballot(Tr[j] > T(0)) != 0 ? 1u : 0u) << (j * (NT / 64));
+                if (live_bands == 0) break;
             }
         }
-        alldone = true;
+        bool alldone = true;
         for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);
         walked += cnt;
         if (!__syncthreads_or(!alldone)) break;

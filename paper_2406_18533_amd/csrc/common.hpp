@@ -201,17 +201,6 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x)
     return x;
 }
 
-// Row-local inclusive scan over rows of 16 lanes: lane 15 of each row ends
-// with the row's sum.
-__device__ __forceinline__ float row_sum16(float x)
-{
-    x += dpp_move<0x111, 0xf>(x);  // row_shr:1
-    x += dpp_move<0x112, 0xf>(x);  // row_shr:2
-    x += dpp_move<0x114, 0xf>(x);  // row_shr:4
-    x += dpp_move<0x118, 0xf>(x);  // row_shr:8
-    return x;
-}
-
 // One butterfly step of a transposed reduction: permlane32_swap exchanges
 // the upper 32 lanes of `a` with the lower 32 lanes of `b`, so the sum holds
 // a's pairwise half-sums in lanes 0-31 and b's in lanes 32-63.
@@ -230,36 +219,40 @@ __device__ __forceinline__ float fold16(float a, float b)
 }
 
 // Adds the wavefront sums of the per-lane values v[0..8] to dst[0..8], each
-// times a factor, with three global atomics (8 values through a transposed
-// permlane/DPP reduction, the ninth through a plain one). The factors are
-// per lane (see sum9_lane_factors): sc0 for the lane that adds component
-// comp(lane) of v[0..3], sc1 for comp(lane) + 4, sc8 for v[8].
+// times a factor, with two global atomic instructions: v[0..7] go through a
+// transposed reduction (permlane32 and permlane16 swaps, a swap of row
+// halves, a three-step row scan) that leaves component sum9_comp(lane) in
+// every lane l with l % 8 == 7; v[8] goes through a plain DPP reduction.
+// sc is the factor for the component of the calling lane, sc8 the one of v[8].
 __device__ __forceinline__ int sum9_comp(int lane)
 {
     int row = (lane & 63) >> 4;
-    return (row & 1) * 2 + (row >> 1);   // row 0 -> 0, 1 -> 2, 2 -> 1, 3 -> 3
+    int base = (row & 1) * 2 + (row >> 1);   // row 0 -> 0, 1 -> 2, 2 -> 1, 3 -> 3
+    return base + ((lane & 8) ? 4 : 0);      // low half of a row: v[0..3], high half: v[4..7]
 }
 
-__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst, float sc0, float sc1, float sc8)
+__device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst, float sc, float sc8)
 {
     int lane = threadIdx.x & 63;
     // after fold32, rows 0-1 hold the first value of a pair, rows 2-3 the second
     float x01 = fold32(v[0], v[1]), x23 = fold32(v[2], v[3]);
     float x45 = fold32(v[4], v[5]), x67 = fold32(v[6], v[7]);
     // after fold16, rows 0..3 hold values (0, 2, 1, 3) and (4, 6, 5, 7)
-    float z0 = row_sum16(fold16(x01, x23));
-    float z1 = row_sum16(fold16(x45, x67));
+    float z0 = fold16(x01, x23), z1 = fold16(x45, x67);
+    // fold the row halves: lanes 0-7 of a row keep z0, lanes 8-15 z1
+    bool hi = (lane & 8) != 0;
+    float c = hi ? z1 : z0, d = hi ? z0 : z1;
+    float r = c + dpp_move<0x128, 0xf>(d);          // row_ror:8: the other half of the row
+    r += dpp_move<0x111, 0xf>(r);                   // row_shr:1
+    r += dpp_move<0x112, 0xf>(r);                   // row_shr:2
+    r += dpp_move<0x114, 0xf>(r);                   // row_shr:4: lane 8k+7 holds its 8 lanes' sum
     float s8 = wave_sum(v[8]);
-    if ((lane & 15) == 15) {
-        int comp = sum9_comp(lane);
-        unsafeAtomicAdd(dst + comp, z0 * sc0);
-        unsafeAtomicAdd(dst + 4 + comp, z1 * sc1);
-    }
+    if ((lane & 7) == 7) unsafeAtomicAdd(dst + sum9_comp(lane), r * sc);
     if (lane == 0) unsafeAtomicAdd(dst + 8, s8 * sc8);
 }
 
-// FP64: lane c (c < 9) adds component c, times sc0 (sc1 and sc8 unused).
-__device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *dst, double sc0, double, double)
+// FP64: lane c (c < 9) adds component c, times sc (sc8 unused).
+__device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *dst, double sc0, double)
 {
     int lane = threadIdx.x & 63;
     double r = v[0];

@@ -367,16 +367,8 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     }
     // factors of the summed components: d/d(a, b, c) of the exponent
     // -(a dx^2 + c dy^2)/2 - b dx dy are -1/2, -1, -1/2 times the sums kept
-    T sc0, sc1;
-    if (sizeof(T) == 4) {
-        int comp = sum9_comp(threadIdx.x);                  // components comp and comp + 4
-        sc0 = comp == 2 ? T(-0.5) : comp == 3 ? T(-1) : T(1);
-        sc1 = comp == 0 ? T(-0.5) : T(1);
-    } else {
-        int lane = threadIdx.x & 63;                        // component lane
-        sc0 = (lane == 2 || lane == 4) ? T(-0.5) : lane == 3 ? T(-1) : T(1);
-        sc1 = T(1);
-    }
+    const int comp = sizeof(T) == 4 ? sum9_comp(threadIdx.x) : (int)(threadIdx.x & 63);   // component this lane adds
+    const T sc = (comp == 2 || comp == 4) ? T(-0.5) : comp == 3 ? T(-1) : T(1);
     uint32_t Lband[PX];     // per band (one wavefront's pixels): the largest last
     for (int j = 0; j < PX; j++) Lband[j] = __builtin_amdgcn_readfirstlane(wave_max(L[j]));
     if (threadIdx.x == 0) *s_red = 0;
@@ -440,7 +432,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
                 }
             }
             if (__ballot(any) == 0) continue;
-            wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC, sc0, sc1, T(1));
+            wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC, sc, T(1));
         }
     }
 }

@@ -62,8 +62,9 @@ def entry_timings(tr, reps: int):
     the stream the kernels run on (eager steps, same kernels as the graph)."""
     import torch
     from paper_2406_18533_amd import raster as R
-    names = ["gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss_l1", "gs_render_bwd_pixels", "gs_project_bwd",
-             "gs_adam_step"]
+    fused = tr.cfg.fused_adam
+    names = ["gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss_l1", "gs_render_bwd_pixels"]
+    names += ["gs_project_bwd_adam"] if fused else ["gs_project_bwd", "gs_adam_step"]
     acc = {k: 0.0 for k in names}
     c = tr.cfg
     for _ in range(reps):
@@ -81,10 +82,14 @@ def entry_timings(tr, reps: int):
         R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, tr.dproj, c.bg,
                                tr.sched_bwd)
         ev[5].record()
-        R.gs_project_bwd(tr.P, tr.cams, tr.proj, tr.dproj, tr.grad, clear=True)
-        ev[6].record()
-        R.gs_adam_step(tr.P, tr.grad, tr.m, tr.v, tr.hp, tr.step_dev, tr.scratch, skip_flag=tr.bins.overflow)
-        ev[7].record()
+        if fused:
+            R.gs_project_bwd_adam(tr.P, tr.cams, tr.proj, tr.dproj, tr.grad, tr.m, tr.v, tr.hp, tr.step_dev,
+                                  tr.scratch, skip_flag=tr.bins.overflow)
+        else:
+            R.gs_project_bwd(tr.P, tr.cams, tr.proj, tr.dproj, tr.grad, clear=True)
+            ev[6].record()
+            R.gs_adam_step(tr.P, tr.grad, tr.m, tr.v, tr.hp, tr.step_dev, tr.scratch, skip_flag=tr.bins.overflow)
+        ev[len(names)].record()
         torch.cuda.synchronize()
         for j, k in enumerate(names):
             acc[k] += ev[j].elapsed_time(ev[j + 1])
@@ -140,6 +145,10 @@ def algorithmic(c: dict) -> dict:
         "gs_project_bwd": ("hbm", 708 * Ns + 4 * VN + 72 * M),
         # read p, g, m, v and write p, m, v (+ g cleared): 32 B per parameter float, 59 per Gaussian
         "gs_adam_step": ("hbm", 32 * 59 * N),
+        # both in one pass: read p, m, v and write p, m, v for every parameter float (24 B), the position
+        # gradient handed between the two kernels (36 B per on-screen Gaussian), tiles field of every
+        # record, the record gradient read and cleared per on-screen record
+        "gs_project_bwd_adam": ("hbm", 24 * 59 * N + 36 * Ns + 4 * VN + 72 * M),
     }
 
 
@@ -193,6 +202,8 @@ def roofline(timings: dict, counts: dict):
     out["ms"] = round(timings[dom], 4)
     per = {}
     for k, (b, a) in work.items():
+        if k not in timings:
+            continue
         t = timings[k] / 1e3
         per[k] = {"bound": b, "ms": round(timings[k], 4),
                   "achieved": round(a / t / (1e9 if b == "hbm" else 1e12), 2 if b == "alu" else 1),

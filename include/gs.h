@@ -267,6 +267,22 @@ gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *
                        const gs_adam_hparams *h, int64_t *step_dev, double *scratch,
                        const int32_t *skip_flag, void *stream);
 
+/* Transformation backward fused with the Adam step: the parameter gradient
+ * that gs_project_bwd (clear = 1) would add into an all-zero grad is applied
+ * to params/m/v exactly as gs_adam_step applies it (same arithmetic in the
+ * same order, so params, m and v equal the two calls bit for bit), without
+ * writing the gradient out: the Gaussian-wise gradient (appendix A.3) and the
+ * dense optimizer update (section 4) become one pass over the parameters.
+ * dprojected is consumed and left all zero, as with clear = 1. grad [59][n]
+ * is scratch that must be all zero on entry and is all zero again on return
+ * (rows 0-2 carry part of the position gradient between the two kernels).
+ * step_dev, scratch, skip_flag and h as for gs_adam_step; a skipped step
+ * still consumes dprojected. */
+gs_status gs_project_bwd_adam(gs_dtype dtype, void *params, int64_t n, const gs_camera *cams_dev,
+                              const gs_camera *cams_host, int32_t views, const void *projected,
+                              void *dprojected, void *grad, void *m, void *v, const gs_adam_hparams *h,
+                              int64_t *step_dev, double *scratch, const int32_t *skip_flag, void *stream);
+
 /* ------------------------------------------------------------------ scheduler */
 /* Algorithm 1 ("Calculation of Division Points") on the device with G =
  * Q = sched->queues: CT = cumsum(ET) with ET_j = tile_cost[j] + 1,

@@ -14,6 +14,9 @@ template <typename T>
 hipError_t launch_project_bwd(const void *, int64_t, const gs_camera *, int32_t, const void *, void *, int, void *,
                               hipStream_t);
 template <typename T>
+hipError_t launch_project_bwd_adam(void *, int64_t, const gs_camera *, int32_t, const void *, void *, void *, void *,
+                                   void *, const gs_adam_hparams *, int64_t *, double *, const int32_t *, hipStream_t);
+template <typename T>
 hipError_t launch_bin_sort(const void *, int64_t, const ViewTable &, gs_bins *, bool, int *, hipStream_t);
 template <typename T>
 hipError_t launch_keys64(const void *, int64_t, const ViewTable &, const gs_bins *, uint64_t *, hipStream_t);
@@ -416,6 +419,28 @@ gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *
     hipError_t e = dtype == GS_F32 ? launch_adam<float>(params, grad, m, v, n, h, step_dev, scratch, skip_flag, s)
                                    : launch_adam<double>(params, grad, m, v, n, h, step_dev, scratch, skip_flag, s);
     return hip_status(e, "gs_adam_step");
+}
+
+gs_status gs_project_bwd_adam(gs_dtype dtype, void *params, int64_t n, const gs_camera *cams_dev,
+                              const gs_camera *cams_host, int32_t views, const void *projected, void *dprojected,
+                              void *grad, void *m, void *v, const gs_adam_hparams *h, int64_t *step_dev,
+                              double *scratch, const int32_t *skip_flag, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(n >= 0 && (uint64_t)n * (uint64_t)views < (uint64_t(1) << 32), "n * views must be < 2^32");
+    CHECK_ARG(h && step_dev && scratch, "null pointer");
+    CHECK_ARG(n == 0 || (params && cams_dev && projected && dprojected && grad && m && v), "null pointer");
+    CHECK_ARG(h->batch_size >= 1, "batch_size must be >= 1");
+    CHECK_ARG(h->beta1 >= 0 && h->beta1 < 1 && h->beta2 >= 0 && h->beta2 < 1 && h->eps >= 0, "bad betas / eps");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32
+                       ? launch_project_bwd_adam<float>(params, n, cams_dev, views, projected, dprojected, grad, m, v,
+                                                        h, step_dev, scratch, skip_flag, s)
+                       : launch_project_bwd_adam<double>(params, n, cams_dev, views, projected, dprojected, grad, m,
+                                                         v, h, step_dev, scratch, skip_flag, s);
+    return hip_status(e, "gs_project_bwd_adam");
 }
 
 }  // extern "C"

@@ -266,4 +266,79 @@ __device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *d
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// ------------------------------------------------------------------ Adam
+// Hyper-parameters of one Adam step after the batch scaling rules of paper
+// section 4: lr already times sqrt(batch), betas already to the power batch.
+struct AdamConst {
+    double lr[6];      // per parameter group (row_group)
+    double b1, b2;
+    double eps;
+    int32_t zero_grad;
+};
+
+// Parameter group of a row of the [59][n] parameter layout: position,
+// log-scale, rotation, opacity logit, SH DC, SH rest.
+__host__ __device__ __forceinline__ int row_group(int row)
+{
+    return row < 3 ? 0 : row < 6 ? 1 : row < 10 ? 2 : row < 11 ? 3 : row < 14 ? 4 : 5;
+}
+
+// One Adam update (torch.optim.Adam semantics) with step = lr / (1 - b1^t)
+// and bc2s = sqrt(1 - b2^t).
+template <typename T>
+__device__ __forceinline__ void adam_one(T &p, T g, T &m, T &v, T b1, T b2, T step, T bc2s, T eps)
+{
+    m = b1 * m + (T(1) - b1) * g;
+    v = b2 * v + (T(1) - b2) * g * g;
+    T denom = sqrt(v) / bc2s + eps;
+    p = p - step * (m / denom);
+}
+
+// Moments, constants and the bias corrections of the current step (written
+// by the prepare kernel: scratch[0] = 1 - b1^t, 0 for a skipped step;
+// scratch[1] = sqrt(1 - b2^t)).
+template <typename T> struct AdamRef {
+    T *M, *V;
+    AdamConst c;
+    const double *scratch;
+};
+
+// Adam on up to 4 rows of Gaussian i at once: rows row0 + r * stride for
+// r < cnt, gradients g[r]. All loads are issued before any store (the
+// moment and parameter arrays never alias), so the memory latency of the
+// rows overlaps.
+template <typename T>
+__device__ __forceinline__ void adam_rows(T *__restrict__ P, const AdamRef<T> &a, int row0, int stride, int cnt,
+                                          int64_t n, int64_t i, const T *g)
+{
+    double bc1 = a.scratch[0];
+    if (bc1 == 0.0) return;                       // skipped step
+    T *__restrict__ M = a.M;
+    T *__restrict__ V = a.V;
+    T p[4], m[4], v[4];
+    for (int r = 0; r < 4; r++) {
+        if (r >= cnt) break;
+        int64_t k = (int64_t)(row0 + r * stride) * n + i;
+        p[r] = P[k];
+        m[r] = M[k];
+        v[r] = V[k];
+    }
+    T b1 = (T)a.c.b1, b2 = (T)a.c.b2, eps = (T)a.c.eps, bc2s = (T)a.scratch[1];
+    for (int r = 0; r < 4; r++) {
+        if (r >= cnt) break;
+        T step = (T)a.c.lr[row_group(row0 + r * stride)] / (T)bc1;
+        adam_one(p[r], g[r], m[r], v[r], b1, b2, step, bc2s, eps);
+    }
+    for (int r = 0; r < 4; r++) {
+        if (r >= cnt) break;
+        int64_t k = (int64_t)(row0 + r * stride) * n + i;
+        P[k] = p[r];
+        M[k] = m[r];
+        V[k] = v[r];
+    }
+}
+
+AdamConst make_adam_const(const gs_adam_hparams *h);
+hipError_t launch_adam_prepare(int64_t *step, const AdamConst &c, double *scratch, const int32_t *skip, hipStream_t s);
+
 }  // namespace gs

@@ -8,13 +8,6 @@
 
 namespace gs {
 
-struct AdamConst {
-    double lr[6];      // already multiplied by sqrt(batch)
-    double b1, b2;     // already raised to the power batch
-    double eps;
-    int32_t zero_grad;
-};
-
 // scratch[0] = 1 - b1^t, scratch[1] = sqrt(1 - b2^t); 0 in scratch[0] marks a skipped step.
 __global__ void adam_prepare_kernel(int64_t *step, double b1, double b2, double *scratch, const int32_t *skip)
 {
@@ -28,18 +21,22 @@ __global__ void adam_prepare_kernel(int64_t *step, double b1, double b2, double 
     scratch[1] = sqrt(1.0 - pow(b2, (double)t));
 }
 
-__device__ __forceinline__ int row_group(int row)
+AdamConst make_adam_const(const gs_adam_hparams *h)
 {
-    return row < 3 ? 0 : row < 6 ? 1 : row < 10 ? 2 : row < 11 ? 3 : row < 14 ? 4 : 5;
+    AdamConst c;
+    double sb = sqrt((double)h->batch_size);
+    for (int j = 0; j < 6; j++) c.lr[j] = h->lr[j] * sb;
+    c.b1 = pow(h->beta1, (double)h->batch_size);
+    c.b2 = pow(h->beta2, (double)h->batch_size);
+    c.eps = h->eps;
+    c.zero_grad = h->zero_grad;
+    return c;
 }
 
-template <typename T>
-__device__ __forceinline__ void adam_one(T &p, T &g, T &m, T &v, T b1, T b2, T step, T bc2s, T eps)
+hipError_t launch_adam_prepare(int64_t *step, const AdamConst &c, double *scratch, const int32_t *skip, hipStream_t s)
 {
-    m = b1 * m + (T(1) - b1) * g;
-    v = b2 * v + (T(1) - b2) * g * g;
-    T denom = sqrt(v) / bc2s + eps;
-    p = p - step * (m / denom);
+    hipLaunchKernelGGL(adam_prepare_kernel, dim3(1), dim3(1), 0, s, step, c.b1, c.b2, scratch, skip);
+    return hipGetLastError();
 }
 
 template <typename T, bool VEC>
@@ -93,15 +90,9 @@ template <typename T>
 hipError_t launch_adam(void *p, void *g, void *m, void *v, int64_t n, const gs_adam_hparams *h, int64_t *step,
                        double *scratch, const int32_t *skip, hipStream_t s)
 {
-    AdamConst c;
-    double sb = sqrt((double)h->batch_size);
-    for (int j = 0; j < 6; j++) c.lr[j] = h->lr[j] * sb;
-    c.b1 = pow(h->beta1, (double)h->batch_size);
-    c.b2 = pow(h->beta2, (double)h->batch_size);
-    c.eps = h->eps;
-    c.zero_grad = h->zero_grad;
-    hipLaunchKernelGGL(adam_prepare_kernel, dim3(1), dim3(1), 0, s, step, c.b1, c.b2, scratch, skip);
-    if (n == 0) return hipGetLastError();
+    AdamConst c = make_adam_const(h);
+    hipError_t e = launch_adam_prepare(step, c, scratch, skip, s);
+    if (n == 0 || e != hipSuccess) return e;
     bool vec = (n % 4 == 0) && ((uintptr_t)p % 32 == 0) && ((uintptr_t)g % 32 == 0) && ((uintptr_t)m % 32 == 0) &&
                ((uintptr_t)v % 32 == 0);
     int64_t per_row = vec ? n / 4 : n;

@@ -269,11 +269,21 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
 // position (through u, v and the perspective Jacobian), scale, rotation and
 // opacity; the colour kernel covers the SH coefficients and the position
 // gradient through the viewing direction, one colour channel at a time.
-template <typename T>
-__global__ void __launch_bounds__(256) project_bwd_geom_kernel(const T *__restrict__ P, int64_t n,
+//
+// With ADAM the kernels apply the Adam step to the parameters instead of
+// adding into grad (the gradient is the same expression, summed in the same
+// order, so the result equals the two separate calls bit for bit): the
+// geometry kernel updates rows 3-10 and leaves its part of the position
+// gradient in grad rows 0-2 (all-zero on entry); the colour kernel adds the
+// viewing-direction part, updates rows 0-2 and 11-58 and zeroes grad rows
+// 0-2 again. Each kernel reads only parameters that it alone updates, or
+// that nothing updates before it reads them. Gaussians seen by no view get
+// the Adam step with a zero gradient.
+template <typename T, bool ADAM>
+__global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P, int64_t n,
                                                                const gs_camera *__restrict__ cams, int32_t views,
                                                                const T *__restrict__ proj, const T *__restrict__ dproj,
-                                                               T *__restrict__ grad)
+                                                               T *__restrict__ grad, AdamRef<T> ad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -281,7 +291,14 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(const T *__restri
     const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
     for (int v = 0; v < views; v++)
         if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
-    if (!vis) return;
+    if (!vis) {
+        if (ADAM) {
+            const T zero[4] = {0, 0, 0, 0};
+            adam_rows(P, ad, 3, 1, 4, n, i, zero);
+            adam_rows(P, ad, 7, 1, 4, n, i, zero);
+        }
+        return;
+    }
     T x[3] = {P[i], P[n + i], P[2 * n + i]};
     Shape<T> S;
     make_shape(P, n, i, S);
@@ -351,17 +368,27 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(const T *__restri
                     qy * dRq[5] + qx * dRq[6] + qy * dRq[7]);
     T dot = dq[0] * S.q[0] + dq[1] * S.q[1] + dq[2] * S.q[2] + dq[3] * S.q[3];
     T iqn = T(1) / S.qn;
-    for (int c = 0; c < 3; c++) grad[c * n + i] += gmean[c];
-    for (int c = 0; c < 3; c++) grad[(3 + c) * n + i] += gls[c];
-    for (int j = 0; j < 4; j++) grad[(6 + j) * n + i] += (dq[j] - S.q[j] * dot) * iqn;
-    grad[10 * n + i] += gop * S.opac * (T(1) - S.opac);
+    if (!ADAM) {
+        for (int c = 0; c < 3; c++) grad[c * n + i] += gmean[c];
+        for (int c = 0; c < 3; c++) grad[(3 + c) * n + i] += gls[c];
+        for (int j = 0; j < 4; j++) grad[(6 + j) * n + i] += (dq[j] - S.q[j] * dot) * iqn;
+        grad[10 * n + i] += gop * S.opac * (T(1) - S.opac);
+    } else {
+        for (int c = 0; c < 3; c++) grad[c * n + i] = T(0) + gmean[c];   // as += into a zero gradient
+        T g8[8];
+        for (int c = 0; c < 3; c++) g8[c] = T(0) + gls[c];
+        for (int j = 0; j < 4; j++) g8[3 + j] = T(0) + (dq[j] - S.q[j] * dot) * iqn;
+        g8[7] = T(0) + gop * S.opac * (T(1) - S.opac);
+        adam_rows(P, ad, 3, 1, 4, n, i, g8);      // rows 3-10
+        adam_rows(P, ad, 7, 1, 4, n, i, g8 + 4);
+    }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) project_bwd_colour_kernel(const T *__restrict__ P, int64_t n,
+template <typename T, bool ADAM>
+__global__ void __launch_bounds__(256) project_bwd_colour_kernel(T *__restrict__ P, int64_t n,
                                                                  const gs_camera *__restrict__ cams, int32_t views,
                                                                  const T *__restrict__ proj, T *__restrict__ dproj,
-                                                                 int clear, T *__restrict__ grad)
+                                                                 int clear, T *__restrict__ grad, AdamRef<T> ad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -369,7 +396,15 @@ __global__ void __launch_bounds__(256) project_bwd_colour_kernel(const T *__rest
     const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
     for (int v = 0; v < views; v++)
         if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
-    if (!vis) return;
+    if (!vis) {
+        if (ADAM) {
+            const T zero[4] = {0, 0, 0, 0};
+            adam_rows(P, ad, 0, 1, 3, n, i, zero);
+            for (int row = 11; row < GS_PARAM_ROWS; row += 4)
+                adam_rows(P, ad, row, 1, GS_PARAM_ROWS - row < 4 ? GS_PARAM_ROWS - row : 4, n, i, zero);
+        }
+        return;
+    }
     T x[3] = {P[i], P[n + i], P[2 * n + i]};
     T gmean[3] = {0, 0, 0};
     for (int ch = 0; ch < 3; ch++) {
@@ -405,9 +440,26 @@ __global__ void __launch_bounds__(256) project_bwd_colour_kernel(const T *__rest
             T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
             for (int j = 0; j < 3; j++) gmean[j] += (gd[j] - dir[j] * dd) * idn;
         }
-        for (int k2 = 0; k2 < 16; k2++) grad[(11 + 3 * k2 + ch) * n + i] += gsh[k2];
+        if (!ADAM)
+            for (int k2 = 0; k2 < 16; k2++) grad[(11 + 3 * k2 + ch) * n + i] += gsh[k2];
+        else {
+            T g4[4];
+            for (int q4 = 0; q4 < 4; q4++) {           // SH rows 11 + 3 k + ch, 4 at a time
+                for (int r = 0; r < 4; r++) g4[r] = T(0) + gsh[4 * q4 + r];
+                adam_rows(P, ad, 11 + 3 * 4 * q4 + ch, 3, 4, n, i, g4);
+            }
+        }
     }
-    for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
+    if (!ADAM) {
+        for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
+    } else {
+        T g3[3];
+        for (int j = 0; j < 3; j++) {
+            g3[j] = grad[j * n + i] + gmean[j];
+            grad[j * n + i] = T(0);
+        }
+        adam_rows(P, ad, 0, 1, 3, n, i, g3);
+    }
     if (clear) {
         const V4<T> zero{T(0), T(0), T(0), T(0)};
         for (int v = 0; v < views; v++) {
@@ -437,10 +489,29 @@ hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, i
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(project_bwd_geom_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams,
-                       views, (const T *)proj, (const T *)dproj, (T *)grad);
-    hipLaunchKernelGGL(project_bwd_colour_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams,
-                       views, (const T *)proj, (T *)dproj, clear, (T *)grad);
+    AdamRef<T> none{};
+    hipLaunchKernelGGL((project_bwd_geom_kernel<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (const T *)dproj, (T *)grad,
+                       none);
+    hipLaunchKernelGGL((project_bwd_colour_kernel<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (T *)dproj, clear, (T *)grad,
+                       none);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_bwd_adam(void *P, int64_t n, const gs_camera *cams, int32_t views, const void *proj,
+                                   void *dproj, void *grad, void *m, void *v, const gs_adam_hparams *h,
+                                   int64_t *step, double *scratch, const int32_t *skip, hipStream_t s)
+{
+    AdamRef<T> ad{(T *)m, (T *)v, make_adam_const(h), scratch};
+    hipError_t e = launch_adam_prepare(step, ad.c, scratch, skip, s);
+    if (n == 0 || e != hipSuccess) return e;
+    int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL((project_bwd_geom_kernel<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, (T *)P, n, cams,
+                       views, (const T *)proj, (const T *)dproj, (T *)grad, ad);
+    hipLaunchKernelGGL((project_bwd_colour_kernel<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, (T *)P, n,
+                       cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
     return hipGetLastError();
 }
 
@@ -450,5 +521,11 @@ template hipError_t launch_project_bwd<float>(const void *, int64_t, const gs_ca
                                               int, void *, hipStream_t);
 template hipError_t launch_project_bwd<double>(const void *, int64_t, const gs_camera *, int32_t, const void *, void *,
                                                int, void *, hipStream_t);
+template hipError_t launch_project_bwd_adam<float>(void *, int64_t, const gs_camera *, int32_t, const void *, void *,
+                                                   void *, void *, void *, const gs_adam_hparams *, int64_t *,
+                                                   double *, const int32_t *, hipStream_t);
+template hipError_t launch_project_bwd_adam<double>(void *, int64_t, const gs_camera *, int32_t, const void *, void *,
+                                                    void *, void *, void *, const gs_adam_hparams *, int64_t *,
+                                                    double *, const int32_t *, hipStream_t);
 
 }  // namespace gs

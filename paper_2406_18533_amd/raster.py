@@ -288,5 +288,16 @@ def gs_adam_step(params, grad, m, v, h: GsAdamHparams, step: torch.Tensor, scrat
                                    C.byref(h), _ptr(step), _ptr(scratch), _ptr(skip_flag), _stream(stream)))
 
 
+def gs_project_bwd_adam(params, cams: Cameras, projected: torch.Tensor, dprojected: torch.Tensor, grad, m, v,
+                        h: GsAdamHparams, step: torch.Tensor, scratch: torch.Tensor,
+                        skip_flag: torch.Tensor | None = None, stream=None):
+    """Transformation backward + Adam in one pass (grad: all-zero scratch)."""
+    n = params.shape[1]
+    check(_lib.load().gs_project_bwd_adam(_dtype_code(params.dtype), _ptr(params), n, cams.dev_ptr, cams.host_ptr,
+                                          cams.n, _ptr(projected), _ptr(dprojected), _ptr(grad), _ptr(m), _ptr(v),
+                                          C.byref(h), _ptr(step), _ptr(scratch), _ptr(skip_flag),
+                                          _stream(stream)))
+
+
 def gs_sched_plan(sched: Sched, cams: Cameras, dp_out: torch.Tensor | None = None, stream=None):
     check(_lib.load().gs_sched_plan(C.byref(sched.struct), cams.host_ptr, cams.n, _ptr(dp_out), _stream(stream)))

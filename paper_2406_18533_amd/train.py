@@ -38,6 +38,7 @@ class TrainConfig:
     queues: int = 64
     workers: int = 0
     graph: bool = True
+    fused_adam: bool = True         # transformation backward and Adam in one pass (gs_project_bwd_adam)
     extra: dict = field(default_factory=dict)
 
 
@@ -105,9 +106,16 @@ class BatchedTrainer:
         R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
         R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
                                self.dproj, self.cfg.bg, self.sched_bwd)
-        R.gs_project_bwd(self.P, self.cams, self.proj, self.dproj, self.grad, clear=True)
-        R.gs_adam_step(self.P, self.grad, self.m, self.v, self.hp, self.step_dev, self.scratch,
-                       skip_flag=self.bins.overflow)
+        self._update(self.bins.overflow)
+
+    def _update(self, skip_flag):
+        if self.cfg.fused_adam:
+            R.gs_project_bwd_adam(self.P, self.cams, self.proj, self.dproj, self.grad, self.m, self.v, self.hp,
+                                  self.step_dev, self.scratch, skip_flag=skip_flag)
+        else:
+            R.gs_project_bwd(self.P, self.cams, self.proj, self.dproj, self.grad, clear=True)
+            R.gs_adam_step(self.P, self.grad, self.m, self.v, self.hp, self.step_dev, self.scratch,
+                           skip_flag=skip_flag)
 
     def _body(self, check: bool):
         self.forward(check)
@@ -154,9 +162,7 @@ class BatchedTrainer:
         R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
         R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
                                self.dproj, self.cfg.bg, self.sched_bwd)
-        R.gs_project_bwd(self.P, self.cams, self.proj, self.dproj, self.grad, clear=True)
-        R.gs_adam_step(self.P, self.grad, self.m, self.v, self.hp, self.step_dev, self.scratch,
-                       skip_flag=self._skip_flag)
+        self._update(self._skip_flag)
 
     def capture(self):
         """Captures one whole step as a HIP graph (after a state-preserving

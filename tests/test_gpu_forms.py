@@ -142,6 +142,46 @@ def test_batched_step_equals_plain_per_view_step():
     assert (bt.P - pt.P).norm().item() < 0.05 * moved
 
 
+def test_fused_backward_adam_equals_separate_calls():
+    """gs_project_bwd_adam == gs_project_bwd (clear) + gs_adam_step bit for
+    bit on params, m, v and the step counter, from identical copies of the
+    same record gradients, over two steps and a skipped one; it consumes
+    dprojected and leaves its gradient scratch all zero."""
+    from paper_2406_18533_amd import raster as R
+    from paper_2406_18533_amd import train
+    P, cams, tgt = _small_batch()
+    tr = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=False))
+    tr.forward(check=True)
+    R.gs_loss_l1(tr.rgb, tr.targets, tr.cams, tr.loss_buf)
+    R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, tr.dproj, tr.cfg.bg,
+                           tr.sched_bwd)
+    dproj = tr.dproj.clone()
+    assert dproj.abs().sum().item() > 0
+    state = {}
+    for name in ("sep", "fused"):
+        state[name] = dict(P=P.cuda().clone(), m=torch.zeros_like(tr.m), v=torch.zeros_like(tr.v),
+                           g=torch.zeros_like(tr.grad), t=torch.zeros(1, dtype=torch.int64, device="cuda"),
+                           sc=torch.zeros(2, dtype=torch.float64, device="cuda"))
+    skip = torch.ones(1, dtype=torch.int32, device="cuda")
+    for it, sk in enumerate((None, None, skip)):
+        for name, st in state.items():
+            d = dproj.clone()
+            if name == "sep":
+                R.gs_project_bwd(st["P"], tr.cams, tr.proj, d, st["g"], clear=True)
+                R.gs_adam_step(st["P"], st["g"], st["m"], st["v"], tr.hp, st["t"], st["sc"], skip_flag=sk)
+            else:
+                R.gs_project_bwd_adam(st["P"], tr.cams, tr.proj, d, st["g"], st["m"], st["v"], tr.hp, st["t"],
+                                      st["sc"], skip_flag=sk)
+            torch.cuda.synchronize()
+            assert d.abs().max().item() == 0, (name, it)
+            assert st["g"].abs().max().item() == 0, (name, it)
+        a, b = state["sep"], state["fused"]
+        for key in ("P", "m", "v", "t"):
+            assert torch.equal(a[key], b[key]), (key, it)
+    assert int(state["fused"]["t"].item()) == 2
+    assert not torch.equal(state["fused"]["P"], P.cuda())
+
+
 def test_graph_replay_equals_eager_steps():
     """Whole-step graph replays, with eager work and synchronisations in
     between, track eager steps from the same start."""

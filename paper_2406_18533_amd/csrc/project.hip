@@ -384,30 +384,35 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P
     }
 }
 
+// Colour part, one wavefront per colour channel: a block holds 64 Gaussians
+// (one per lane) and its three wavefronts are the channels. Each wavefront
+// walks the views its Gaussians are seen from and accumulates the SH
+// gradients of its channel (coalesced rows 11 + 3 k + ch) and its channel's
+// share of the position gradient through the viewing direction; the three
+// shares meet in LDS, wavefront c finishes position row c, and after the
+// barrier wavefront c clears 16-byte slice c of every record it consumed.
+constexpr int COLOUR_G = 64;   // Gaussians per block (one per lane); 3 wavefronts = channels
+
 template <typename T, bool ADAM>
-__global__ void __launch_bounds__(256) project_bwd_colour_kernel(T *__restrict__ P, int64_t n,
-                                                                 const gs_camera *__restrict__ cams, int32_t views,
-                                                                 const T *__restrict__ proj, T *__restrict__ dproj,
-                                                                 int clear, T *__restrict__ grad, AdamRef<T> ad)
+__global__ void __launch_bounds__(3 * COLOUR_G) project_bwd_colour_kernel(T *__restrict__ P, int64_t n,
+                                                                          const gs_camera *__restrict__ cams,
+                                                                          int32_t views, const T *__restrict__ proj,
+                                                                          T *__restrict__ dproj, int clear,
+                                                                          T *__restrict__ grad, AdamRef<T> ad)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ T s_gd[3][3][COLOUR_G];   // [channel][position component][Gaussian]
+    const int ch = threadIdx.x / COLOUR_G, lane = threadIdx.x % COLOUR_G;
+    const int64_t i = (int64_t)blockIdx.x * COLOUR_G + lane;
+    const bool valid = i < n;
     uint64_t vis = 0;
-    const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
-    for (int v = 0; v < views; v++)
-        if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
-    if (!vis) {
-        if (ADAM) {
-            const T zero[4] = {0, 0, 0, 0};
-            adam_rows(P, ad, 0, 1, 3, n, i, zero);
-            for (int row = 11; row < GS_PARAM_ROWS; row += 4)
-                adam_rows(P, ad, row, 1, GS_PARAM_ROWS - row < 4 ? GS_PARAM_ROWS - row : 4, n, i, zero);
-        }
-        return;
+    if (valid) {
+        const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
+        for (int v = 0; v < views; v++)
+            if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
     }
-    T x[3] = {P[i], P[n + i], P[2 * n + i]};
     T gmean[3] = {0, 0, 0};
-    for (int ch = 0; ch < 3; ch++) {
+    if (valid && vis) {
+        T x[3] = {P[i], P[n + i], P[2 * n + i]};
         T sh[16], gsh[16];
         for (int k2 = 0; k2 < 16; k2++) {
             sh[k2] = P[(11 + 3 * k2 + ch) * n + i];
@@ -449,26 +454,31 @@ __global__ void __launch_bounds__(256) project_bwd_colour_kernel(T *__restrict__
                 adam_rows(P, ad, 11 + 3 * 4 * q4 + ch, 3, 4, n, i, g4);
             }
         }
+    } else if (valid && ADAM) {                       // seen by no view: Adam with a zero gradient
+        const T zero[4] = {0, 0, 0, 0};
+        for (int q4 = 0; q4 < 4; q4++) adam_rows(P, ad, 11 + 3 * 4 * q4 + ch, 3, 4, n, i, zero);
     }
-    if (!ADAM) {
-        for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
-    } else {
-        T g3[3];
-        for (int j = 0; j < 3; j++) {
-            g3[j] = grad[j * n + i] + gmean[j];
+    for (int j = 0; j < 3; j++) s_gd[ch][j][lane] = gmean[j];
+    __syncthreads();                                  // every channel has read its record gradients
+    if (!valid) return;
+    const int j = ch;                                 // position row finished by this wavefront
+    if (vis) {
+        T gj = (s_gd[0][j][lane] + s_gd[1][j][lane]) + s_gd[2][j][lane];
+        if (!ADAM) {
+            grad[j * n + i] += gj;
+        } else {
+            T g = grad[j * n + i] + gj;
             grad[j * n + i] = T(0);
+            adam_rows(P, ad, j, 1, 1, n, i, &g);
         }
-        adam_rows(P, ad, 0, 1, 3, n, i, g3);
-    }
-    if (clear) {
-        const V4<T> zero{T(0), T(0), T(0), T(0)};
-        for (int v = 0; v < views; v++) {
-            if (!((vis >> v) & 1ull)) continue;
-            V4<T> *dr = reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
-            dr[0] = zero;
-            dr[1] = zero;
-            dr[2] = zero;
+        if (clear) {
+            const V4<T> zero{T(0), T(0), T(0), T(0)};
+            for (int v = 0; v < views; v++)
+                if ((vis >> v) & 1ull) reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC)[ch] = zero;
         }
+    } else if (ADAM) {
+        const T zero = T(0);
+        adam_rows(P, ad, j, 1, 1, n, i, &zero);
     }
 }
 
@@ -493,9 +503,9 @@ hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, i
     hipLaunchKernelGGL((project_bwd_geom_kernel<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
                        const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (const T *)dproj, (T *)grad,
                        none);
-    hipLaunchKernelGGL((project_bwd_colour_kernel<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (T *)dproj, clear, (T *)grad,
-                       none);
+    hipLaunchKernelGGL((project_bwd_colour_kernel<T, false>), dim3((unsigned)((n + COLOUR_G - 1) / COLOUR_G)),
+                       dim3(3 * COLOUR_G), 0, s, const_cast<T *>((const T *)P), n, cams, views, (const T *)proj,
+                       (T *)dproj, clear, (T *)grad, none);
     return hipGetLastError();
 }
 
@@ -510,8 +520,8 @@ hipError_t launch_project_bwd_adam(void *P, int64_t n, const gs_camera *cams, in
     int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL((project_bwd_geom_kernel<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, (T *)P, n, cams,
                        views, (const T *)proj, (const T *)dproj, (T *)grad, ad);
-    hipLaunchKernelGGL((project_bwd_colour_kernel<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, (T *)P, n,
-                       cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
+    hipLaunchKernelGGL((project_bwd_colour_kernel<T, true>), dim3((unsigned)((n + COLOUR_G - 1) / COLOUR_G)),
+                       dim3(3 * COLOUR_G), 0, s, (T *)P, n, cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
     return hipGetLastError();
 }
 

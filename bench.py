@@ -63,7 +63,10 @@ def entry_timings(tr, reps: int):
     import torch
     from paper_2406_18533_amd import raster as R
     fused = tr.cfg.fused_adam
-    names = ["gs_project", "gs_bin_sort", "gs_render_fwd", "gs_loss_l1", "gs_render_bwd_pixels"]
+    fused_loss = tr.cfg.fused_loss
+    names = ["gs_project", "gs_bin_sort"]
+    names += ["gs_render_fwd_l1"] if fused_loss else ["gs_render_fwd", "gs_loss_l1"]
+    names += ["gs_render_bwd_pixels"]
     names += ["gs_project_bwd_adam"] if fused else ["gs_project_bwd", "gs_adam_step"]
     acc = {k: 0.0 for k in names}
     c = tr.cfg
@@ -74,20 +77,27 @@ def entry_timings(tr, reps: int):
         ev[1].record()
         R.gs_bin_sort(tr.proj, tr.n, tr.cams, tr.bins, check_capacity=False)
         ev[2].record()
-        R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, c.bg, tr.sched_fwd, tr.rgb, tr.T, tr.last, tr.work_fwd,
-                        tr.work_bwd)
-        ev[3].record()
-        R.gs_loss_l1(tr.rgb, tr.targets, tr.cams, tr.loss_buf)
-        ev[4].record()
+        e = 3
+        if fused_loss:
+            R.gs_render_fwd_l1(tr.proj, tr.n, tr.bins, tr.cams, tr.targets, tr.loss_buf, c.bg, tr.sched_fwd, tr.rgb,
+                               tr.T, tr.last, tr.work_fwd, tr.work_bwd)
+        else:
+            R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, c.bg, tr.sched_fwd, tr.rgb, tr.T, tr.last,
+                            tr.work_fwd, tr.work_bwd)
+            ev[e].record()
+            e += 1
+            R.gs_loss_l1(tr.rgb, tr.targets, tr.cams, tr.loss_buf)
+        ev[e].record()
+        e += 1
         R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, tr.dproj, c.bg,
                                tr.sched_bwd)
-        ev[5].record()
+        ev[e].record()
         if fused:
             R.gs_project_bwd_adam(tr.P, tr.cams, tr.proj, tr.dproj, tr.grad, tr.m, tr.v, tr.hp, tr.step_dev,
                                   tr.scratch, skip_flag=tr.bins.overflow)
         else:
             R.gs_project_bwd(tr.P, tr.cams, tr.proj, tr.dproj, tr.grad, clear=True)
-            ev[6].record()
+            ev[e + 1].record()
             R.gs_adam_step(tr.P, tr.grad, tr.m, tr.v, tr.hp, tr.step_dev, tr.scratch, skip_flag=tr.bins.overflow)
         ev[len(names)].record()
         torch.cuda.synchronize()
@@ -137,6 +147,8 @@ def algorithmic(c: dict) -> dict:
                         + radix_passes_tile * 20 * K + 4 * K + 8 * T),
         # 17 flops to evaluate a pair (offset, circle, quadratic form, exp, opacity), 9 more to blend it
         "gs_render_fwd": ("alu", 17 * c["pairs_evaluated_fwd"] + 9 * c["pairs_blended"]),
+        # the same, with the L1 loss and its gradient (a few flops per pixel channel) in the output stage
+        "gs_render_fwd_l1": ("alu", 17 * c["pairs_evaluated_fwd"] + 9 * c["pairs_blended"] + 12 * c["pixels"]),
         "gs_loss_l1": ("hbm", 36 * Pn),
         # re-evaluate every pair up to `last` (17 flops), 53 more for each blended pair's gradients
         "gs_render_bwd_pixels": ("alu", 17 * c["pairs_evaluated_bwd"] + 53 * c["pairs_blended"]),
@@ -154,7 +166,8 @@ def algorithmic(c: dict) -> dict:
 
 # Kernel sources whose HBM traffic per launch was measured with hardware counters.
 TRAFFIC_SOURCES = {"gs_render_bwd_pixels": ["render.hip", "common.hpp"],
-                   "gs_render_fwd": ["render.hip", "common.hpp"]}
+                   "gs_render_fwd": ["render.hip", "common.hpp"],
+                   "gs_render_fwd_l1": ["render.hip", "common.hpp"]}
 
 
 def source_digest(entry: str):

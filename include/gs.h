@@ -251,6 +251,20 @@ gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const 
                      int32_t views, double scale, void *dL_drgb, double *loss_dev, void *workspace,
                      size_t workspace_bytes, void *stream);
 
+/* Render forward with the L1 loss fused into its output stage: everything
+ * gs_render_fwd writes (without pair_stats), plus dL_drgb exactly as
+ * gs_loss_l1 writes it for the same rgb (bit for bit: the gradient at a
+ * pixel depends only on its final colour, so it is written as the pixel
+ * finishes) and *loss_dev, the same loss summed per tile and then over the
+ * tiles in a fixed order (deterministic; equal to gs_loss_l1's value up to
+ * the order of the double-precision sum). target/dL_drgb: like rgb.
+ * workspace: gs_loss_workspace_bytes (one double per tile). */
+gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                           const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
+                           void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd,
+                           uint32_t *tile_work_bwd, const void *target, double scale, void *dL_drgb,
+                           double *loss_dev, void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------ optimizer */
 /* Adam with the batch scaling rules of section 4: learning rate
  * lr * sqrt(batch_size) (eq. "lambda") and beta1^b, beta2^b (eq. "beta").

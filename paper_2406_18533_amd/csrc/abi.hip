@@ -24,7 +24,7 @@ size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws);
 template <typename T>
 hipError_t launch_render_fwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                              const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *, uint64_t *,
-                             hipStream_t);
+                             const void *, double, void *, double *, double *, hipStream_t);
 template <typename T>
 hipError_t launch_render_bwd(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                              const LaunchShape &, const void *, const uint32_t *, const void *, void *, hipStream_t);
@@ -188,9 +188,11 @@ size_t gs_sched_workspace_bytes(int64_t total_tiles, int32_t queues)
 
 size_t gs_loss_workspace_bytes(const gs_camera *cams, int32_t views)
 {
-    (void)cams;
-    if (views < 1) return 0;
-    return loss_ws_bytes(views);
+    std::string why;
+    if (!cams_ok(cams, views, why)) return 0;
+    size_t tiles = (size_t)make_view_table(cams, views).total_tiles * sizeof(double);   // gs_render_fwd_l1
+    size_t ws = loss_ws_bytes(views);
+    return ws > tiles ? ws : tiles;
 }
 
 gs_status gs_project(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
@@ -329,10 +331,44 @@ gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const 
     }
     hipError_t e = dtype == GS_F32
                        ? launch_render_fwd<float>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
-                                                  tile_work_bwd, pair_stats, s)
+                                                  tile_work_bwd, pair_stats, nullptr, 0.0, nullptr, nullptr, nullptr,
+                                                  s)
                        : launch_render_fwd<double>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
-                                                   tile_work_bwd, pair_stats, s);
+                                                   tile_work_bwd, pair_stats, nullptr, 0.0, nullptr, nullptr, nullptr,
+                                                   s);
     return hip_status(e, "gs_render_fwd");
+}
+
+gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                           const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
+                           void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd, uint32_t *tile_work_bwd,
+                           const void *target, double scale, void *dL_drgb, double *loss_dev, void *workspace,
+                           size_t workspace_bytes, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(bins_ok(bins, n, views, why), why);
+    CHECK_ARG(bg && rgb && final_T && last && projected, "null pointer");
+    CHECK_ARG(target && dL_drgb && loss_dev && workspace, "null pointer");
+    CHECK_ARG(isfinite(scale), "bad scale");
+    ViewTable vt = make_view_table(cams_host, views);
+    CHECK_ARG(workspace_bytes >= (size_t)vt.total_tiles * sizeof(double), "loss workspace too small");
+    LaunchShape sh;
+    CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
+    hipStream_t s = (hipStream_t)stream;
+    if (sh.mode == GS_SCHED_PERSISTENT) {
+        hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
+        if (e != hipSuccess) return hip_status(e, "gs_render_fwd_l1 plan");
+    }
+    hipError_t e = dtype == GS_F32
+                       ? launch_render_fwd<float>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
+                                                  tile_work_bwd, nullptr, target, scale, dL_drgb, loss_dev,
+                                                  (double *)workspace, s)
+                       : launch_render_fwd<double>(vt, projected, n, bins, bg, sh, rgb, final_T, last, tile_work_fwd,
+                                                   tile_work_bwd, nullptr, target, scale, dL_drgb, loss_dev,
+                                                   (double *)workspace, s);
+    return hip_status(e, "gs_render_fwd_l1");
 }
 
 gs_status gs_render_bwd_pixels(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,

@@ -39,6 +39,11 @@ template <typename T> struct FwdArgs {
     uint32_t *work_fwd;
     uint32_t *work_bwd;
     unsigned long long *stats;   // [2]: pairs evaluated, pairs blended (STATS variants only)
+    // L1 loss fused into the output stage (target null: no loss)
+    const T *target;             // like rgb
+    T *dL;                       // like rgb: scale sign(rgb - target) / (3 H W views)
+    double *loss_tile;           // [total tiles]: the tile's share of the loss
+    double loss_scale;
 };
 
 template <typename T> struct BwdArgs {
@@ -307,20 +312,48 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         if (!__syncthreads_or(!alldone)) break;
     }
     uint32_t mylast = 0;
+    const int64_t plane = (int64_t)W * H;
+    // per-element L1 weight, computed exactly as the standalone loss does
+    const double wd = A.target ? A.loss_scale / ((double)(3 * plane) * (double)vt.nviews) : 0.0;
+    double labs = 0.0;
     for (int j = 0; j < PX; j++) {
         if (!inside[j]) continue;
         int p = threadIdx.x + j * NT;
         int px = tx * TILE + (p & 15), py = ty * TILE + (p >> 4);
         int64_t pix = vt.pix_base[v] + (int64_t)py * W + px;
-        int64_t plane = (int64_t)W * H;
-        T *rgb = A.rgb + 3 * vt.pix_base[v] + (int64_t)py * W + px;
+        int64_t o = 3 * vt.pix_base[v] + (int64_t)py * W + px;
         T Tf = fabs(Tr[j]);
-        rgb[0] = C[j][0] + Tf * A.bg[0];
-        rgb[plane] = C[j][1] + Tf * A.bg[1];
-        rgb[2 * plane] = C[j][2] + Tf * A.bg[2];
+        T out[3];
+        for (int ch = 0; ch < 3; ch++) {
+            out[ch] = C[j][ch] + Tf * A.bg[ch];
+            A.rgb[o + ch * plane] = out[ch];
+        }
+        if (A.target) {                     // L1: gradient now, loss summed per tile
+            T w = (T)wd;
+            for (int ch = 0; ch < 3; ch++) {
+                T d = out[ch] - A.target[o + ch * plane];
+                A.dL[o + ch * plane] = d > T(0) ? w : (d < T(0) ? -w : T(0));
+                labs += (double)(d < T(0) ? -d : d);
+            }
+        }
         A.finalT[pix] = Tf;
         A.last[pix] = lastp[j];
         mylast = max(mylast, lastp[j]);
+    }
+    if (A.target) {                         // the tile's share of the loss (no atomics: deterministic)
+        for (int off = 32; off > 0; off >>= 1) labs += __shfl_xor(labs, off, 64);
+        if (NT == 64) {
+            if (threadIdx.x == 0) A.loss_tile[g] = labs * wd;
+        } else {
+            __shared__ double s_l[NT / 64];
+            if ((threadIdx.x & 63) == 0) s_l[threadIdx.x >> 6] = labs;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int k = 0; k < NT / 64; k++) t += s_l[k];
+                A.loss_tile[g] = t * wd;
+            }
+        }
     }
     if (A.work_bwd) atomicMax(s_red, mylast);
     if (STATS) {
@@ -541,12 +574,34 @@ __global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, 
         else { CALL(T, 4, 256); }                                                                            \
     } while (0)
 
+// Sum of the per-tile loss shares in a fixed order (deterministic): each
+// thread adds a fixed strided subset, then a fixed tree over the threads.
+__global__ void __launch_bounds__(1024) loss_tiles_sum_kernel(const double *__restrict__ part, int64_t n,
+                                                              double *__restrict__ loss)
+{
+    __shared__ double s[1024];
+    double a = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 1024) a += part[j];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = s[0];
+}
+
 template <typename T>
 hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, const gs_bins *b, const float *bg,
                              const LaunchShape &sh, void *rgb, void *finalT, uint32_t *last, uint32_t *wf,
-                             uint32_t *wb, uint64_t *stats, hipStream_t s)
+                             uint32_t *wb, uint64_t *stats, const void *target, double loss_scale, void *dL,
+                             double *loss, double *loss_tiles, hipStream_t s)
 {
     FwdArgs<T> A;
+    A.target = (const T *)target;
+    A.dL = (T *)dL;
+    A.loss_tile = loss_tiles;
+    A.loss_scale = loss_scale;
     A.proj = (const T *)proj;
     A.n = n;
     A.ids = b->ids;
@@ -575,6 +630,9 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     }
 #undef GS_FWD
 #undef GS_FWD_S
+    if (target)
+        hipLaunchKernelGGL(loss_tiles_sum_kernel, dim3(1), dim3(1024), 0, s, (const double *)loss_tiles,
+                           (int64_t)vt.total_tiles, loss);
     return hipGetLastError();
 }
 
@@ -611,10 +669,12 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
 
 template hipError_t launch_render_fwd<float>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                                              const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *,
-                                             uint64_t *, hipStream_t);
+                                             uint64_t *, const void *, double, void *, double *, double *,
+                                             hipStream_t);
 template hipError_t launch_render_fwd<double>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                                               const LaunchShape &, void *, void *, uint32_t *, uint32_t *, uint32_t *,
-                                              uint64_t *, hipStream_t);
+                                              uint64_t *, const void *, double, void *, double *, double *,
+                                              hipStream_t);
 template hipError_t launch_render_bwd<float>(const ViewTable &, const void *, int64_t, const gs_bins *, const float *,
                                              const LaunchShape &, const void *, const uint32_t *, const void *, void *,
                                              hipStream_t);

@@ -222,6 +222,26 @@ def gs_render_fwd(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras, bg
     return rgb, final_T, last
 
 
+def gs_render_fwd_l1(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras, target: torch.Tensor,
+                     buf: "LossBuffers", bg=(0.0, 0.0, 0.0), sched: Sched | None = None, rgb=None, final_T=None,
+                     last=None, tile_work_fwd=None, tile_work_bwd=None, scale: float = 1.0, stream=None):
+    """Render forward with the L1 loss fused in: also writes buf.dL and buf.loss."""
+    P = cams.total_pixels()
+    dev = projected.device
+    if rgb is None:
+        rgb = torch.empty(3 * P, dtype=projected.dtype, device=dev)
+    if final_T is None:
+        final_T = torch.empty(P, dtype=projected.dtype, device=dev)
+    if last is None:
+        last = torch.empty(P, dtype=torch.int32, device=dev)
+    check(_lib.load().gs_render_fwd_l1(_dtype_code(projected.dtype), _ptr(projected), n, C.byref(bins.struct),
+                                       cams.host_ptr, cams.n, _bg(bg), C.byref(sched.struct) if sched else None,
+                                       _ptr(rgb), _ptr(final_T), _ptr(last), _ptr(tile_work_fwd),
+                                       _ptr(tile_work_bwd), _ptr(target), float(scale), _ptr(buf.dL),
+                                       _ptr(buf.loss), _ptr(buf.workspace), buf.workspace.numel(), _stream(stream)))
+    return rgb, final_T, last
+
+
 def gs_render_bwd(params: torch.Tensor, projected: torch.Tensor, bins: Bins, cams: Cameras, final_T, last, dL_drgb,
                   grad: torch.Tensor, bg=(0.0, 0.0, 0.0), sched: Sched | None = None, dprojected=None, stream=None):
     """Both backward halves; accumulates (+=) into ``grad``. ``dprojected``

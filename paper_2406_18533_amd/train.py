@@ -39,6 +39,7 @@ class TrainConfig:
     workers: int = 0
     graph: bool = True
     fused_adam: bool = True         # transformation backward and Adam in one pass (gs_project_bwd_adam)
+    fused_loss: bool = True         # L1 loss in the render forward's output stage (gs_render_fwd_l1)
     extra: dict = field(default_factory=dict)
 
 
@@ -99,11 +100,19 @@ class BatchedTrainer:
     def forward(self, check: bool = False):
         R.gs_project(self.P, self.cams, self.proj)
         R.gs_bin_sort(self.proj, self.n, self.cams, self.bins, check_capacity=check)
-        R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
-                        self.last, self.work_fwd, self.work_bwd)
+        self._render()
+
+    def _render(self):
+        """Render forward, and the loss with its gradient (fused or after)."""
+        if self.cfg.fused_loss:
+            R.gs_render_fwd_l1(self.proj, self.n, self.bins, self.cams, self.targets, self.loss_buf, self.cfg.bg,
+                               self.sched_fwd, self.rgb, self.T, self.last, self.work_fwd, self.work_bwd)
+        else:
+            R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
+                            self.last, self.work_fwd, self.work_bwd)
+            R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
 
     def backward_and_update(self):
-        R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
         R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
                                self.dproj, self.cfg.bg, self.sched_bwd)
         self._update(self.bins.overflow)
@@ -138,8 +147,7 @@ class BatchedTrainer:
                     raise
                 self.overflows += 1
                 self._grow()
-        R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
-                        self.last, self.work_fwd, self.work_bwd)
+        self._render()
         self.backward_and_update()
 
     def warmup(self):
@@ -157,9 +165,7 @@ class BatchedTrainer:
                     raise
                 self.overflows += 1
                 self._grow()
-        R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
-                        self.last, self.work_fwd, self.work_bwd)
-        R.gs_loss_l1(self.rgb, self.targets, self.cams, self.loss_buf)
+        self._render()
         R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
                                self.dproj, self.cfg.bg, self.sched_bwd)
         self._update(self._skip_flag)

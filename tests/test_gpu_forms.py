@@ -142,6 +142,33 @@ def test_batched_step_equals_plain_per_view_step():
     assert (bt.P - pt.P).norm().item() < 0.05 * moved
 
 
+@pytest.mark.parametrize("px,mode", [(1, 0), (2, 1), (4, 0)])
+def test_fused_forward_loss_equals_separate_calls(px, mode):
+    """gs_render_fwd_l1 == gs_render_fwd + gs_loss_l1: rgb, T, last and the
+    image gradient bit for bit, the loss to double rounding; ragged view
+    sizes, one, two and four pixels per thread, both schedulers."""
+    from paper_2406_18533_amd import raster as R
+    P = scenes.clustered_gaussians(60_000, 3).cuda()
+    cams_list = scenes.sphere_cameras(3, 21, 200, 136) + [scenes.orbit_camera(97, 61, 8.0, 1.0, 0.4)]
+    cams = R.Cameras(cams_list)
+    tgt = scenes.random_images(cams_list, 4).cuda()
+    proj = R.gs_project(P, cams)
+    K = int(R.projected_side_arrays(proj)[0].sum().item())
+    bins = R.Bins(P.shape[1], cams, K + 16)
+    R.gs_bin_sort(proj, P.shape[1], cams, bins)
+    sched = R.Sched(cams, mode=mode, px_per_thread=px, chunk=64)
+    rgb, T, last = R.gs_render_fwd(proj, P.shape[1], bins, cams, (0.1, 0.2, 0.3), sched)
+    lb = R.LossBuffers(cams)
+    R.gs_loss_l1(rgb, tgt, cams, lb, scale=0.7)
+    lb2 = R.LossBuffers(cams)
+    rgb2, T2, last2 = R.gs_render_fwd_l1(proj, P.shape[1], bins, cams, tgt, lb2, (0.1, 0.2, 0.3), sched, scale=0.7)
+    torch.cuda.synchronize()
+    assert torch.equal(rgb, rgb2) and torch.equal(T, T2) and torch.equal(last, last2)
+    assert torch.equal(lb.dL, lb2.dL)
+    a, b = lb.loss.item(), lb2.loss.item()
+    assert a > 0 and abs(a - b) <= 1e-12 * a, (a, b)
+
+
 def test_fused_backward_adam_equals_separate_calls():
     """gs_project_bwd_adam == gs_project_bwd (clear) + gs_adam_step bit for
     bit on params, m, v and the step counter, from identical copies of the

@@ -380,7 +380,7 @@ def main():
                     help="end with a fill and a copy of this many MiB (calibration for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (a multi-GPU run would "
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 (a multi-GPU run would "
                                    "shard Gaussians and tiles across GPUs, which is not built)"}))
         sys.exit(2)
     import torch

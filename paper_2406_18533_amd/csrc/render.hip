@@ -430,8 +430,11 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             uint32_t k = __builtin_amdgcn_readfirstlane(st.pos[q]);                  // wave-uniform
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
             uint32_t bm = __builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id;
-            T acc[9];
-            for (int c = 0; c < 9; c++) acc[c] = T(0);
+            // dL/d(exponent) moments over this thread's pixels: they share the column
+            // (one dx), so the position and conic sums factor through
+            // D0 = sum d, D1 = sum d dy, D2 = sum d dy^2 (d = dL/d exponent)
+            T D0 = T(0), D1 = T(0), D2 = T(0), acc[9];
+            for (int c = 5; c < 9; c++) acc[c] = T(0);
             bool any = false;
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             const T dx = col.dx;
@@ -455,15 +458,20 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
                     Tr[j] = Tk;
                     T live = og <= K<T>::alpha_max ? dalpha : T(0);   // the 0.99 clamp has no gradient
                     T dpow = live * og;
-                    T hx = dpow * dx, hy = dpow * dy;
+                    T hy = dpow * dy;
                     acc[5] = fma(live, G, acc[5]);
-                    acc[0] = fma(rb.x, hx, fma(rb.y, hy, acc[0]));
-                    acc[1] = fma(rb.y, hx, fma(rb.z, hy, acc[1]));
-                    acc[2] = fma(hx, dx, acc[2]);   // times -1/2, -1, -1/2 after the reduction
-                    acc[3] = fma(hx, dy, acc[3]);
-                    acc[4] = fma(hy, dy, acc[4]);
+                    D0 += dpow;
+                    D1 += hy;
+                    D2 = fma(hy, dy, D2);
                 }
             }
+            // d/du, d/dv through (dx, dy) and d/d(a, b, c) (times -1/2, -1, -1/2 after the reduction)
+            T hx = dx * D0;
+            acc[0] = fma(rb.x, hx, rb.y * D1);
+            acc[1] = fma(rb.y, hx, rb.z * D1);
+            acc[2] = dx * hx;
+            acc[3] = dx * D1;
+            acc[4] = D2;
             if (__ballot(any) == 0) continue;
             wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC, sc, T(1));
         }

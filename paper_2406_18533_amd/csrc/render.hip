@@ -542,7 +542,8 @@ __global__ void __launch_bounds__(256 / PX) render_fwd_persistent(ViewTable vt, 
 }
 
 template <typename T, int PX, int CHUNK>
-__global__ void __launch_bounds__(256 / PX) render_bwd_kernel(ViewTable vt, BwdArgs<T> A)
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(6)))
+render_bwd_kernel(ViewTable vt, BwdArgs<T> A)
 {
     __shared__ Stage<T, CHUNK> st;
     __shared__ uint32_t s_red;

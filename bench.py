@@ -299,6 +299,8 @@ def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, ma
     t_fixed = time.perf_counter() - t0
     lat = srv.latencies_ms()
     p50, p99 = percentile(lat, 50), percentile(lat, 99)
+    waits = [(st - arr) * 1e3 for arr, st, _ in srv.completed]        # queue: arrival to launch
+    service = [(dn - st) * 1e3 for _, st, dn in srv.completed]        # launch to result on the host
     mean_batch = sum(srv.batches) / max(len(srv.batches), 1)
     # saturation: everything queued at once
     srv.completed.clear()
@@ -313,6 +315,8 @@ def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, ma
     torch.cuda.synchronize()
     return {"workload": f"serving_{n_gaussians // 1_000_000}M_mixed_res", "qps": round(qps, 2),
             "requests": requests, "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+            "queue_wait_p50_p99_ms": [round(percentile(waits, 50), 3), round(percentile(waits, 99), 3)],
+            "service_p50_p99_ms": [round(percentile(service, 50), 3), round(percentile(service, 99), 3)],
             "views_per_s_at_qps": round(requests / t_fixed, 2), "saturation_views_per_s": round(sat, 2),
             "one_at_a_time_views_per_s": round(1.0 / single, 2), "mean_batch": round(mean_batch, 2),
             "pinned_image_buffers": be.pool.allocated,

@@ -1,0 +1,134 @@
+"""Parity at the full batched-training size: 1,000,000 clustered Gaussians,
+16 views of 1920x1080, in the launch configuration the benchmark times on
+MI355X (the batched trainer with the L1 loss fused into the forward, four
+pixels per thread, 64-record chunks, one workgroup per tile). The oracle
+checks sampled outputs it can compute one view at a time from the GPU's own
+FP32 projection: bit-exact bins and images of two views, the image gradient
+of those views, and the record gradients of one view; whole-batch properties
+cover the rest."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import scenes
+from tests.test_gpu_parity import oracle_proj_from_gpu
+
+pytestmark = pytest.mark.gpu
+
+SAMPLED_VIEWS = (0, 11)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_18533_amd import _lib, train
+    from paper_2406_18533_amd import raster as R
+    R.init(0)
+    w = scenes.batched_1080p()
+    tgt = scenes.random_images(w.cameras, 17)
+    cfg = train.TrainConfig(graph=False, mode=_lib.GS_SCHED_PER_TILE, fwd_shape=(4, 64), bwd_shape=(4, 64))
+    tr = train.BatchedTrainer(w.params.cuda(), w.cameras, tgt.cuda(), cfg)
+    tr.forward(check=True)
+    torch.cuda.synchronize()
+    return w, tr
+
+
+def _view_slices(cams, channels):
+    out, o = [], 0
+    for c in cams:
+        k = channels * c["width"] * c["height"]
+        out.append((o, o + k))
+        o += k
+    return out
+
+
+def _oracle_bins(pf, v, cam):
+    r = np.where(pf["radius"][v] > 0, pf["radius"][v], 0).astype(np.float32)
+    return oracle.bin_sort(pf["u"][v:v + 1], pf["v"][v:v + 1], r[None], pf["depth"][v:v + 1], [cam])
+
+
+def test_fullsize_bins_and_images_of_sampled_views(batch):
+    from tests import gpu_pipeline as gp
+    w, tr = batch
+    cams = w.cameras
+    pf = gp.proj_fields(tr.proj)
+    base = oracle.tile_base(cams)
+    ranges_g = tr.bins.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    ids_g = tr.bins.ids.cpu().numpy().view(np.uint32)
+    sl3 = _view_slices(cams, 3)
+    sl1 = _view_slices(cams, 1)
+    rgb = tr.rgb.cpu().numpy()
+    T = tr.T.cpu().numpy()
+    last = tr.last.cpu().numpy().view(np.uint32)
+    dL = tr.loss_buf.dL.cpu().numpy()
+    tgt = tr.targets.cpu().numpy()
+    for v in SAMPLED_VIEWS:
+        cam = cams[v]
+        H, W = cam["height"], cam["width"]
+        keys_o, ids_o, ranges_o = _oracle_bins(pf, v, cam)
+        # this view's tiles: the same lists, offset by where the view starts in the batch
+        rv = ranges_g[base[v]:base[v + 1]].astype(np.int64)
+        start = rv[rv[:, 1] > rv[:, 0], 0].min()
+        nonempty = ranges_o[:, 1] > ranges_o[:, 0]
+        assert (rv[nonempty] - start == ranges_o[nonempty]).all()
+        assert (rv[~nonempty, 1] == rv[~nonempty, 0]).all()
+        assert (ids_g[start:start + ids_o.size] == ids_o).all()
+        # image at the pixels the oracle does not flag as a threshold near-tie
+        o = oracle.render(oracle_proj_from_gpu(pf, v), cam, ids_o, ranges_o, tr.cfg.bg)
+        ok = o["amb"] == 0
+        img = rgb[sl3[v][0]:sl3[v][1]].reshape(3, H, W)
+        assert np.max(np.abs(img - o["rgb"])[:, ok]) <= 1e-5
+        assert np.max(np.abs(T[sl1[v][0]:sl1[v][1]].reshape(H, W) - o["T"])[ok]) <= 1e-5
+        assert (last[sl1[v][0]:sl1[v][1]].reshape(H, W)[ok] == o["last"][ok]).all()
+        assert (~ok).sum() <= max(4, 2e-3 * ok.size), (~ok).sum()
+        # image gradient of the fused loss: sign(rgb - target) / (3 H W views), in FP32
+        wgt = np.float32(1.0 / (3.0 * H * W * len(cams)))
+        d = img.reshape(-1) - tgt[sl3[v][0]:sl3[v][1]]
+        expect = np.where(d > 0, wgt, np.where(d < 0, -wgt, np.float32(0)))
+        assert (dL[sl3[v][0]:sl3[v][1]] == expect).all()
+
+
+def test_fullsize_record_gradients_of_a_sampled_view(batch):
+    from tests import gpu_pipeline as gp
+    from paper_2406_18533_amd import raster as R
+    w, tr = batch
+    cams = w.cameras
+    dproj = torch.zeros_like(tr.dproj)
+    R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, dproj, tr.cfg.bg,
+                           tr.sched_bwd)
+    torch.cuda.synchronize()
+    pf = gp.proj_fields(tr.proj)
+    v = SAMPLED_VIEWS[0]
+    cam = cams[v]
+    _, ids_o, ranges_o = _oracle_bins(pf, v, cam)
+    sl3 = _view_slices(cams, 3)
+    dLv = tr.loss_buf.dL[sl3[v][0]:sl3[v][1]].cpu().numpy().reshape(3, cam["height"], cam["width"])
+    do = oracle.render_bwd(oracle_proj_from_gpu(pf, v), cam, ids_o, ranges_o, dLv.astype(np.float64), tr.cfg.bg)
+    dg = dproj[v].cpu().numpy()
+    for comp in [slice(0, 2), slice(2, 5), slice(5, 6), slice(6, 9)]:
+        a = dg[:, comp].T.astype(np.float64)
+        b = do[comp]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert err <= 1e-3, (comp, err)
+
+
+def test_fullsize_batch_properties(batch):
+    """Every view: instance count equals the tiles touched, T in [0, 1] and
+    non-increasing from 1 only where something blended, the loss equals the
+    mean of the per-view mean absolute errors."""
+    w, tr = batch
+    tiles = tr.proj[..., 11]
+    assert int(tr.bins.n_instances.item()) == int(tiles.double().sum().item())
+    T = tr.T
+    assert float(T.min()) >= 0.0 and float(T.max()) <= 1.0
+    assert bool(((tr.last == 0) == (T == 1.0)).all())
+    rgb, tgt = tr.rgb.double(), tr.targets.double()
+    per_view, o = [], 0
+    for c in w.cameras:
+        k = 3 * c["width"] * c["height"]
+        per_view.append((rgb[o:o + k] - tgt[o:o + k]).abs().mean().item())
+        o += k
+    loss = tr.loss_buf.loss.item()
+    assert abs(loss - sum(per_view) / len(per_view)) <= 1e-9 * loss

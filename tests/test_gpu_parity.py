@@ -5,7 +5,8 @@ Tolerances (FP32 kernels against the FP64 oracle):
     the oracle binning the GPU's own FP32 (u, v, radius, depth);
   - images: max |difference| <= 1e-5 over pixels the oracle does not flag as
     ambiguous (a threshold decision within rounding distance), flagged pixels
-    < 1e-4 of all;
+    at most 2e-3 of all with the GPU's own projection (render-only), 4% end
+    to end (10% for the needle scene);
   - gradients: ||g - g_oracle|| / ||g_oracle|| <= 1e-3 per parameter group.
 """
 import math

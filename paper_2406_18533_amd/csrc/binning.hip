@@ -2,17 +2,21 @@
 //
 // The order is lexicographic in (global tile, FP32 depth bits, Gaussian
 // index). It is produced as a least-significant-digit-first radix sort whose
-// low digits (depth) are sorted BEFORE the instances are duplicated per tile:
+// low digits (depth) are sorted BEFORE the instances are duplicated per tile,
+// and whose most significant digit, the view, is never sorted at all: every
+// step keeps the views in their own contiguous segments.
 //   1. compact the (view, Gaussian) pairs that touch at least one tile,
 //      keeping (view-major, index) order;
-//   2. stable radix sort of those pairs by FP32 depth bits (4 passes);
+//   2. stable radix sort of each view's pairs by FP32 depth bits (4 passes);
 //   3. exclusive scan of their tile counts in that order -> instance offsets;
-//   4. emit (global tile id, Gaussian index) per tile of each pair's rectangle;
-//   5. stable radix sort of the instances by global tile id (2-3 passes).
-// Stability of step 5 keeps step 2's (depth, index) order inside each tile,
-// and a tile id already names its view. Only step 5 runs over the duplicated
-// instances, so the wide depth digits cost passes over the pairs, not over
-// the (typically 5-10x larger) instance set.
+//   4. emit (global tile id, Gaussian index) per tile of each pair's rectangle
+//      (grouped by view, since the pairs are);
+//   5. stable radix sort of each view's instances by tile within the view
+//      (13 bits, two passes, for a 1920x1080 view).
+// Stability of step 5 keeps step 2's (depth, index) order inside each tile.
+// Only step 5 runs over the duplicated instances, so the wide depth digits
+// cost passes over the pairs, not over the (typically 5-10x larger)
+// instance set, and its key is the tile within the view, not the global tile.
 #include "common.hpp"
 
 namespace gs {
@@ -187,11 +191,84 @@ struct U32Store {
 };
 
 // ---------------------------------------------------------------- radix sort
-// One stable LSD pass over 32-bit keys with 32-bit values, BITS-wide digits.
-// A block owns STILE consecutive elements; wave w owns the w-th quarter and
-// walks it in rounds of 64. Lanes with equal digits find each other with
-// BITS ballots; their order inside the wave and the wave's running per-digit
-// count give each element its rank among equal digits, in input order.
+// View-segmented stable LSD radix sort of 32-bit keys with 32-bit values.
+// The items of view v occupy [start[v], start[v + 1]) and a pass orders each
+// view's items among themselves, by a digit of (key - base[v]): the views
+// stay where they are. A block owns one 4096-item tile of one view (view v
+// has tiles b0[v] .. b0[v + 1] - 1). A pass's histogram is laid out view
+// first, then digit, then tile (entry RADIX b0[v] + d ntiles_v + t), so one
+// exclusive scan over it gives every (view, digit, tile) its output offset.
+struct SegPlan {
+    int64_t start[MAXV + 1];
+    int64_t b0[MAXV + 1];
+    int64_t hist_n[10];   // histogram length RADIX b0[views] for RADIX = 2^bits
+    uint32_t base[MAXV];
+};
+
+__device__ __forceinline__ void plan_finish(SegPlan *p, int views)
+{
+    int64_t b = 0;
+    for (int v = 0; v < views; v++) {
+        p->b0[v] = b;
+        b += (p->start[v + 1] - p->start[v] + STILE - 1) / STILE;
+    }
+    p->b0[views] = b;
+    for (int k = 0; k < 10; k++) p->hist_n[k] = b << k;
+}
+
+// Pair segments: the compacted pairs are in flat (view-major) order, so view
+// v starts at the first flat index >= v n.
+__global__ void pair_plan_kernel(const uint32_t *__restrict__ flat, const int64_t *m_dev, int64_t m_max, int64_t n,
+                                 int views, SegPlan *plan)
+{
+    const int v = threadIdx.x;
+    const int64_t m = count_of(m_dev, m_max);
+    if (v < views) {
+        int64_t lo = 0, hi = m;                       // first j with flat[j] >= v n
+        const uint64_t key = (uint64_t)v * (uint64_t)n;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)flat[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        plan->start[v] = lo;
+        plan->base[v] = 0u;
+    }
+    if (v == 0) plan->start[views] = m;
+    __syncthreads();
+    if (v == 0) plan_finish(plan, views);
+}
+
+// Instance segments: view v's instances start at the offset of its first
+// pair (the emission keeps the pairs' view grouping); clipped to capacity.
+__global__ void instance_plan_kernel(const SegPlan *__restrict__ pairs, const uint64_t *__restrict__ off,
+                                     const int64_t *k_dev, int64_t cap, ViewTable vt, SegPlan *plan)
+{
+    const int v = threadIdx.x, views = vt.nviews;
+    int64_t K = *k_dev < cap ? *k_dev : cap;
+    const int64_t m = pairs->start[views];
+    if (v < views) {
+        int64_t j = pairs->start[v];
+        int64_t st = j < m ? (int64_t)off[j] : K;
+        plan->start[v] = st < K ? st : K;
+        plan->base[v] = (uint32_t)vt.tile_base[v];
+    }
+    if (v == 0) plan->start[views] = K;
+    __syncthreads();
+    if (v == 0) plan_finish(plan, views);
+}
+
+// View and tile of block b (views are few: a uniform linear walk).
+__device__ __forceinline__ int plan_view(const SegPlan *plan, int views, int64_t b)
+{
+    int v = 0;
+    while (v + 1 < views && b >= plan->b0[v + 1]) v++;
+    return v;
+}
+
+// Lanes with equal digits find each other with BITS ballots; their order
+// inside the wave and the wave's running per-digit count give each element
+// its rank among equal digits, in input order.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
 {
@@ -204,56 +281,45 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
     return peers;
 }
 
-// Each block owns a contiguous run of 4096-key tiles (tiles_per_block of
-// them, computed from the device-side count so both kernels agree) and
-// writes one histogram column; the grid is bounded, so the histogram and its
-// scan stay small whatever the key count.
-__device__ __forceinline__ void block_tiles(int64_t n, int64_t grid, int64_t &t0, int64_t &t1)
-{
-    int64_t ntiles = (n + STILE - 1) / STILE;
-    int64_t per = (ntiles + grid - 1) / grid;
-    t0 = (int64_t)blockIdx.x * per;
-    t1 = t0 + per < ntiles ? t0 + per : ntiles;
-}
-
 template <int BITS>
-__global__ void __launch_bounds__(SB) radix_count_kernel(const uint32_t *__restrict__ kin, const int64_t *n_dev,
-                                                         int64_t n_max, int shift, uint32_t *__restrict__ hist,
-                                                         int64_t nblocks)
+__global__ void __launch_bounds__(SB) seg_count_kernel(const uint32_t *__restrict__ kin,
+                                                       const SegPlan *__restrict__ plan, int views, int shift,
+                                                       uint32_t *__restrict__ hist)
 {
     constexpr int RADIX = 1 << BITS;
     __shared__ uint32_t s_cnt[SB / 64][RADIX];
-    int64_t n = count_of(n_dev, n_max);
-    int64_t t0, t1;
-    block_tiles(n, nblocks, t0, t1);
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t b = blockIdx.x;
+    if (b >= plan->b0[views]) return;
+    const int v = plan_view(plan, views, b);
+    const int64_t t = b - plan->b0[v], nt = plan->b0[v + 1] - plan->b0[v];
+    const int64_t beg = plan->start[v] + t * STILE;
+    const int64_t end = plan->start[v + 1] < beg + STILE ? plan->start[v + 1] : beg + STILE;
+    const uint32_t kb = plan->base[v];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
     __syncthreads();
-    for (int64_t t = t0; t < t1; t++) {
-        int64_t base = t * STILE + (int64_t)w * (SITEMS * 64) + lane;
-        uint32_t kk[SITEMS];
-        for (int it = 0; it < SITEMS; it++) {      // all loads of the tile in flight at once
-            int64_t idx = base + it * 64;
-            kk[it] = idx < n ? kin[idx] : 0u;
-        }
-        for (int it = 0; it < SITEMS; it++) {       // counts only: LDS atomics, no ranks needed
-            if (base + it * 64 < n) atomicAdd(&s_cnt[w][(kk[it] >> shift) & (RADIX - 1)], 1u);
-        }
+    const int64_t i0 = beg + (int64_t)w * (SITEMS * 64) + lane;
+    uint32_t kk[SITEMS];
+    for (int it = 0; it < SITEMS; it++) {          // all loads of the tile in flight at once
+        int64_t idx = i0 + it * 64;
+        kk[it] = idx < end ? kin[idx] : 0u;
     }
+    for (int it = 0; it < SITEMS; it++)             // counts only: LDS atomics, no ranks needed
+        if (i0 + it * 64 < end) atomicAdd(&s_cnt[w][((kk[it] - kb) >> shift) & (RADIX - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < RADIX; d += SB) {
         uint32_t c = 0;
         for (int j = 0; j < SB / 64; j++) c += s_cnt[j][d];
-        hist[(int64_t)d * nblocks + blockIdx.x] = c;
+        hist[RADIX * plan->b0[v] + d * nt + t] = c;
     }
 }
 
 template <int BITS>
-__global__ void __launch_bounds__(SB) radix_scatter_kernel(const uint32_t *__restrict__ kin,
-                                                           const uint32_t *__restrict__ vin,
-                                                           uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                           const int64_t *n_dev, int64_t n_max, int shift,
-                                                           const uint32_t *__restrict__ offs, int64_t nblocks)
+__global__ void __launch_bounds__(SB) seg_scatter_kernel(const uint32_t *__restrict__ kin,
+                                                         const uint32_t *__restrict__ vin,
+                                                         uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                         const SegPlan *__restrict__ plan, int views, int shift,
+                                                         const uint32_t *__restrict__ offs)
 {
     constexpr int RADIX = 1 << BITS;
     constexpr int PER = (RADIX + SB - 1) / SB;
@@ -262,132 +328,120 @@ __global__ void __launch_bounds__(SB) radix_scatter_kernel(const uint32_t *__res
     __shared__ uint32_t s_cnt[SB / 64][RADIX];
     __shared__ uint32_t s_start[RADIX];
     __shared__ uint32_t s_goff[RADIX];
-    int64_t n = count_of(n_dev, n_max);
-    int64_t t0, t1;
-    block_tiles(n, nblocks, t0, t1);
-    if (t0 >= t1) return;
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int d = threadIdx.x; d < RADIX; d += SB) s_goff[d] = offs[(int64_t)d * nblocks + blockIdx.x];
-    uint64_t lt = (1ull << lane) - 1ull;
-    for (int64_t t = t0; t < t1; t++) {
-        int64_t base = t * STILE;
-        for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
-        __syncthreads();
-        uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
-        for (int it = 0; it < SITEMS; it++) {      // all loads of the tile in flight at once
-            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
-            key[it] = idx < n ? kin[idx] : 0u;
-            val[it] = idx < n ? vin[idx] : 0u;
-        }
-        for (int it = 0; it < SITEMS; it++) {
-            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
-            bool valid = idx < n;
-            uint32_t k = key[it];
-            uint32_t v = val[it];
-            uint32_t d = (k >> shift) & (RADIX - 1);
-            uint64_t peers = match_digit<BITS>(d, valid);
-            uint32_t before = s_cnt[w][d];
-            if (valid && (peers & lt) == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
-            rank[it] = before + (uint32_t)__popcll(peers & lt);
-            key[it] = k;
-            val[it] = v;
-        }
-        __syncthreads();
-        // wave prefixes per digit, then tile-local digit starts
-        uint32_t tot[PER];
-        uint32_t mysum = 0;
-        for (int j = 0; j < PER; j++) {
-            int d = threadIdx.x * PER + j;
-            uint32_t tt = 0;
-            if (d < RADIX) {
-                uint32_t run = 0;
-                for (int q = 0; q < SB / 64; q++) {
-                    uint32_t c = s_cnt[q][d];
-                    s_cnt[q][d] = run;
-                    run += c;
-                }
-                tt = run;
+    const int64_t b = blockIdx.x;
+    if (b >= plan->b0[views]) return;
+    const int v = plan_view(plan, views, b);
+    const int64_t t = b - plan->b0[v], nt = plan->b0[v + 1] - plan->b0[v];
+    const int64_t beg = plan->start[v] + t * STILE;
+    const int64_t end = plan->start[v + 1] < beg + STILE ? plan->start[v + 1] : beg + STILE;
+    const uint32_t kb = plan->base[v];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int d = threadIdx.x; d < RADIX; d += SB) s_goff[d] = offs[RADIX * plan->b0[v] + d * nt + t];
+    for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t i0 = beg + (int64_t)w * (SITEMS * 64) + lane;
+    uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
+    for (int it = 0; it < SITEMS; it++) {          // all loads of the tile in flight at once
+        int64_t idx = i0 + it * 64;
+        key[it] = idx < end ? kin[idx] : 0u;
+        val[it] = idx < end ? vin[idx] : 0u;
+    }
+    __syncthreads();
+    for (int it = 0; it < SITEMS; it++) {
+        bool valid = i0 + it * 64 < end;
+        uint32_t d = ((key[it] - kb) >> shift) & (RADIX - 1);
+        uint64_t peers = match_digit<BITS>(d, valid);
+        uint32_t before = s_cnt[w][d];
+        if (valid && (peers & lt) == 0) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
+        rank[it] = before + (uint32_t)__popcll(peers & lt);
+    }
+    __syncthreads();
+    // wave prefixes per digit, then tile-local digit starts
+    uint32_t tot[PER];
+    uint32_t mysum = 0;
+    for (int j = 0; j < PER; j++) {
+        int d = threadIdx.x * PER + j;
+        uint32_t tt = 0;
+        if (d < RADIX) {
+            uint32_t run = 0;
+            for (int q = 0; q < SB / 64; q++) {
+                uint32_t c = s_cnt[q][d];
+                s_cnt[q][d] = run;
+                run += c;
             }
-            tot[j] = tt;
-            mysum += tt;
+            tt = run;
         }
-        uint32_t total;
-        uint32_t run = block_excl_scan(mysum, total);
-        for (int j = 0; j < PER; j++) {
-            int d = threadIdx.x * PER + j;
-            if (d < RADIX) s_start[d] = run;
-            run += tot[j];
+        tot[j] = tt;
+        mysum += tt;
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(mysum, total);
+    for (int j = 0; j < PER; j++) {
+        int d = threadIdx.x * PER + j;
+        if (d < RADIX) s_start[d] = run;
+        run += tot[j];
+    }
+    __syncthreads();
+    for (int it = 0; it < SITEMS; it++) {
+        if (i0 + it * 64 < end) {
+            uint32_t d = ((key[it] - kb) >> shift) & (RADIX - 1);
+            uint32_t pos = s_start[d] + s_cnt[w][d] + rank[it];
+            s_key[pos] = key[it];
+            s_val[pos] = val[it];
         }
-        __syncthreads();
-        for (int it = 0; it < SITEMS; it++) {
-            int64_t idx = base + (int64_t)w * (SITEMS * 64) + it * 64 + lane;
-            if (idx < n) {
-                uint32_t d = (key[it] >> shift) & (RADIX - 1);
-                uint32_t pos = s_start[d] + s_cnt[w][d] + rank[it];
-                s_key[pos] = key[it];
-                s_val[pos] = val[it];
-            }
-        }
-        __syncthreads();
-        int64_t cnt = n - base < STILE ? n - base : STILE;
-        for (int p = threadIdx.x; p < cnt; p += SB) {
-            uint32_t k = s_key[p];
-            uint32_t d = (k >> shift) & (RADIX - 1);
-            int64_t g = (int64_t)s_goff[d] + (p - (int64_t)s_start[d]);
-            kout[g] = k;
-            vout[g] = s_val[p];
-        }
-        __syncthreads();
-        // this tile's counts advance the block's running digit offsets
-        for (int j = 0; j < PER; j++) {
-            int d = threadIdx.x * PER + j;
-            if (d < RADIX) s_goff[d] += tot[j];
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    const int cnt = (int)(end - beg);
+    for (int q = threadIdx.x; q < cnt; q += SB) {
+        uint32_t k = s_key[q];
+        uint32_t d = ((k - kb) >> shift) & (RADIX - 1);
+        int64_t g = (int64_t)s_goff[d] + (q - (int64_t)s_start[d]);
+        kout[g] = k;
+        vout[g] = s_val[q];
     }
 }
 
-constexpr int64_t RADIX_GRID = 2048;   // blocks per radix pass (upper bound)
-
 template <int BITS>
-static void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *ko, uint32_t *vo, const int64_t *n_dev,
-                       int64_t n_max, int shift, uint32_t *hist, uint32_t *partial, int64_t nblocks, hipStream_t s)
+static void seg_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *ko, uint32_t *vo, const SegPlan *plan,
+                     int views, int64_t nbmax, int shift, uint32_t *hist, uint32_t *partial, hipStream_t s)
 {
-    int64_t hn = (int64_t)(1 << BITS) * nblocks;
-    hipLaunchKernelGGL(radix_count_kernel<BITS>, dim3((unsigned)nblocks), dim3(SB), 0, s, kin, n_dev, n_max, shift,
-                       hist, nblocks);
-    (void)device_scan<uint32_t>(U32Load{hist}, U32Store{hist}, nullptr, hn, partial, nullptr, s);
-    hipLaunchKernelGGL(radix_scatter_kernel<BITS>, dim3((unsigned)nblocks), dim3(SB), 0, s, kin, vin, ko, vo, n_dev,
-                       n_max, shift, (const uint32_t *)hist, nblocks);
+    constexpr int RADIX = 1 << BITS;
+    hipLaunchKernelGGL(seg_count_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, plan, views, shift, hist);
+    (void)device_scan<uint32_t>(U32Load{hist}, U32Store{hist}, &plan->hist_n[BITS], (int64_t)RADIX * nbmax, partial,
+                                nullptr, s);
+    hipLaunchKernelGGL(seg_scatter_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, vin, ko, vo, plan, views,
+                       shift, (const uint32_t *)hist);
 }
 
-// Sorts (keys, vals) over their lowest `bits` key bits; the result lands back
-// in keys/vals (an even number of passes through the alternate buffers). The
-// element count is min(*n_dev, n_max).
-static hipError_t radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uint32_t *valt, const int64_t *n_dev,
-                             int64_t n_max, int bits, uint32_t *hist, uint32_t *partial, hipStream_t s)
+// Passes of a sort over the lowest `bits` key bits: digits of at most 8 bits,
+// as even in width as possible.
+static int seg_passes(int bits) { return bits < 1 ? 1 : (bits + 7) / 8; }
+
+// Sorts (keys, vals) within each view segment over the lowest `bits` bits of
+// key - base[v]. The result lands in keys/vals after an even number of
+// passes and in kalt/valt after an odd one. n_max bounds the item count.
+static hipError_t seg_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt, uint32_t *valt,
+                                 const SegPlan *plan, int views, int64_t n_max, int bits, uint32_t *hist,
+                                 uint32_t *partial, hipStream_t s)
 {
-    int64_t nbmax = (n_max + STILE - 1) / STILE;
-    if (nbmax == 0) return hipSuccess;
-    if (nbmax > RADIX_GRID) nbmax = RADIX_GRID;
-    int passes = (bits + 8) / 9;
-    if (passes & 1) passes++;
-    int digit = (bits + passes - 1) / passes;
+    if (n_max == 0) return hipSuccess;
+    const int64_t nbmax = (n_max + STILE - 1) / STILE + views;   // sum over views of ceil(count / STILE)
+    if (bits < 1) bits = 1;
+    const int passes = seg_passes(bits);
+    const int digit = (bits + passes - 1) / passes;
     uint32_t *kin = keys, *vin = vals, *ko = kalt, *vo = valt;
     for (int p = 0; p < passes; p++) {
         int shift = p * digit;
         int width = bits - shift < digit ? bits - shift : digit;   // the last pass may be narrower
-        if (width < 1) width = 1;
         switch (width) {
-        case 1: radix_pass<1>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 2: radix_pass<2>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 3: radix_pass<3>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 4: radix_pass<4>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 5: radix_pass<5>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 6: radix_pass<6>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 7: radix_pass<7>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        case 8: radix_pass<8>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
-        default: radix_pass<9>(kin, vin, ko, vo, n_dev, n_max, shift, hist, partial, nbmax, s); break;
+        case 1: seg_pass<1>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        case 2: seg_pass<2>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        case 3: seg_pass<3>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        case 4: seg_pass<4>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        case 5: seg_pass<5>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        case 6: seg_pass<6>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        case 7: seg_pass<7>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+        default: seg_pass<8>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
         }
         uint32_t *tk = kin, *tv = vin;
         kin = ko; vin = vo; ko = tk; vo = tv;
@@ -557,9 +611,10 @@ struct BinWS {
     uint64_t *off;                   // [VN] instance offsets
     uint64_t *rect;                  // [VN] tile rectangles of the visible pairs in depth order
     uint32_t *talt, *ialt;           // [cap] alternate tile keys / ids
-    uint32_t *hist;                  // [512 * nbmax]
+    uint32_t *hist;                  // [256 * nbmax] radix histograms
     uint64_t *partial;               // scan partials
     int64_t *m_dev;                  // visible pair count
+    SegPlan *pplan, *iplan;          // view segments of the pairs and of the instances
 };
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -567,8 +622,8 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws)
 {
     int64_t big = vn > cap ? vn : cap;
-    int64_t nbmax = (big + STILE - 1) / STILE + 1;
-    int64_t hist_n = 512 * nbmax;
+    int64_t nbmax = (big + STILE - 1) / STILE + MAXV;
+    int64_t hist_n = 256 * nbmax;
     int64_t part_n = (hist_n + STILE - 1) / STILE + (big + STILE - 1) / STILE + 8;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return base ? (void *)(base + at) : nullptr; };
@@ -584,6 +639,8 @@ size_t bin_ws_layout(int64_t vn, int64_t cap, char *base, BinWS *ws)
     w.hist = (uint32_t *)take(4 * hist_n);
     w.partial = (uint64_t *)take(8 * part_n);
     w.m_dev = (int64_t *)take(64);
+    w.pplan = (SegPlan *)take(sizeof(SegPlan));
+    w.iplan = (SegPlan *)take(sizeof(SegPlan));
     if (ws) *ws = w;
     return o;
 }
@@ -608,8 +665,12 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
     e = device_scan<uint32_t>(FlagLoad{tiles}, CompactStore{depth, ws.k1, ws.v1}, nullptr, vn,
                               (uint32_t *)ws.partial, ws.m_dev, s);
     if (e != hipSuccess) return e;
-    // 2. stable sort by FP32 depth bits (positive depths: 31 significant bits)
-    e = radix_sort(ws.k1, ws.v1, ws.k1b, ws.v1b, ws.m_dev, vn, 32, ws.hist, (uint32_t *)ws.partial, s);
+    if (vn > 0)
+        hipLaunchKernelGGL(pair_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const uint32_t *)ws.v1,
+                           (const int64_t *)ws.m_dev, vn, n, vt.nviews, ws.pplan);
+    // 2. stable sort by FP32 depth bits within each view (4 passes: an even
+    // count, so the result is back in k1 / v1)
+    e = seg_radix_sort(ws.k1, ws.v1, ws.k1b, ws.v1b, ws.pplan, vt.nviews, vn, 32, ws.hist, (uint32_t *)ws.partial, s);
     if (e != hipSuccess) return e;
     // 3. instance offsets in depth order (the sorted depth keys are dead now:
     // their buffer holds the gathered tile counts)
@@ -631,18 +692,28 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
             return hipSuccess;
         }
     }
-    // 4. emission
-    if (vn > 0)
+    // 4. emission, grouped by view like the pairs; an odd number of tile
+    // passes starts from the alternate buffers so the result lands in the
+    // caller's
+    int bits = 1;                                   // tile id within its view
+    for (int v = 0; v < vt.nviews; v++)
+        while ((int64_t(1) << bits) < (int64_t)(vt.tile_base[v + 1] - vt.tile_base[v])) bits++;
+    const bool odd = seg_passes(bits) & 1;
+    uint32_t *ek = odd ? ws.talt : b->tile_keys, *ei = odd ? ws.ialt : b->ids;
+    uint32_t *ak = odd ? b->tile_keys : ws.talt, *ai = odd ? b->ids : ws.ialt;
+    if (vn > 0) {
         hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s,
                            (const uint64_t *)ws.rect, n, vt,
                            (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
-                           (const int64_t *)b->n_instances, b->tile_keys, b->ids, cap);
-    // 5. stable sort by global tile id
-    int bits = 1;
-    while ((int64_t(1) << bits) < T_all) bits++;
-    e = radix_sort(b->tile_keys, b->ids, ws.talt, ws.ialt, b->n_instances, cap, bits, ws.hist, (uint32_t *)ws.partial,
-                   s);
-    if (e != hipSuccess) return e;
+                           (const int64_t *)b->n_instances, ek, ei, cap);
+        hipLaunchKernelGGL(instance_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const SegPlan *)ws.pplan,
+                           (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan);
+    }
+    // 5. stable sort by tile within each view
+    if (vn > 0) {
+        e = seg_radix_sort(ek, ei, ak, ai, ws.iplan, vt.nviews, cap, bits, ws.hist, (uint32_t *)ws.partial, s);
+        if (e != hipSuccess) return e;
+    }
     if (cap > 0)
         hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((cap + 1023) / 1024)), dim3(256), 0, s,
                            (const uint32_t *)b->tile_keys, (const int64_t *)b->n_instances, cap, T_all, b->ranges);

@@ -169,16 +169,23 @@ def test_fused_forward_loss_equals_separate_calls(px, mode):
     assert a > 0 and abs(a - b) <= 1e-12 * a, (a, b)
 
 
-def test_fused_backward_adam_equals_separate_calls():
+@pytest.mark.parametrize("n", [60_000, 59_997])
+def test_fused_backward_adam_equals_separate_calls(n):
     """gs_project_bwd_adam == gs_project_bwd (clear) + gs_adam_step bit for
     bit on params, m, v and the step counter, from identical copies of the
     same record gradients, over two steps and a skipped one; it consumes
-    dprojected and leaves its gradient scratch all zero."""
+    dprojected and leaves its gradient scratch all zero. The batch holds
+    Gaussians seen by no view (zero-gradient update) beside seen ones, and
+    a count that is not a multiple of the 64-Gaussian block."""
     from paper_2406_18533_amd import raster as R
     from paper_2406_18533_amd import train
     P, cams, tgt = _small_batch()
+    P = P[:, :n].contiguous()
     tr = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=False))
     tr.forward(check=True)
+    tiles, _ = R.projected_side_arrays(tr.proj)
+    seen = (tiles > 0).any(dim=0)
+    assert 0 < int(seen.sum().item()) < n
     R.gs_loss_l1(tr.rgb, tr.targets, tr.cams, tr.loss_buf)
     R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, tr.dproj, tr.cfg.bg,
                            tr.sched_bwd)

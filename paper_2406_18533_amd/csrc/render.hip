@@ -402,8 +402,14 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     // -(a dx^2 + c dy^2)/2 - b dx dy are -1/2, -1, -1/2 times the sums kept
     const int comp = sizeof(T) == 4 ? sum9_comp(threadIdx.x) : (int)(threadIdx.x & 63);   // component this lane adds
     const T sc = (comp == 2 || comp == 4) ? T(-0.5) : comp == 3 ? T(-1) : T(1);
-    uint32_t Lband[PX];     // per band (one wavefront's pixels): the largest last
-    for (int j = 0; j < PX; j++) Lband[j] = __builtin_amdgcn_readfirstlane(wave_max(L[j]));
+    // per band (one wavefront's pixels) the largest last, held by lane
+    // j (NT/64) of the wavefront: one compare and ballot per record then give
+    // the bands that still have a contributor behind the record
+    uint32_t Lv = 0;
+    for (int j = 0; j < PX; j++) {
+        uint32_t lb = __builtin_amdgcn_readfirstlane(wave_max(L[j]));
+        Lv = (int)(threadIdx.x & 63) == j * (NT / 64) ? lb : Lv;
+    }
     if (threadIdx.x == 0) *s_red = 0;
     __syncthreads();
     atomicMax(s_red, mymax);
@@ -429,7 +435,8 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         for (int q = kept - 1; q >= 0; q--) {
             uint32_t k = __builtin_amdgcn_readfirstlane(st.pos[q]);                  // wave-uniform
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
-            uint32_t bm = __builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id;
+            const uint32_t act = (uint32_t)__ballot(k < Lv);                          // k < largest last of band j
+            uint32_t bm = (__builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id) & act;
             // dL/d(exponent) moments over this thread's pixels: they share the column
             // (one dx), so the position and conic sums factor through
             // D0 = sum d, D1 = sum d dy, D2 = sum d dy^2 (d = dL/d exponent)
@@ -440,7 +447,6 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             const T dx = col.dx;
             for (int j = 0; j < PX; j++) {
                 if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
-                if (k >= Lband[j]) continue;                         // past every last contributor of the band
                 T dy, G, og, alpha;
                 bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
                 if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian

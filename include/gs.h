@@ -258,7 +258,8 @@ gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const 
  * finishes) and *loss_dev, the same loss summed per tile and then over the
  * tiles in a fixed order (deterministic; equal to gs_loss_l1's value up to
  * the order of the double-precision sum). target/dL_drgb: like rgb.
- * workspace: gs_loss_workspace_bytes (one double per tile). */
+ * workspace: gs_loss_workspace_bytes (one double per tile, plus 64 for the
+ * block sums of the final reduction). */
 gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
                            const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
                            void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd,

@@ -190,7 +190,7 @@ size_t gs_loss_workspace_bytes(const gs_camera *cams, int32_t views)
 {
     std::string why;
     if (!cams_ok(cams, views, why)) return 0;
-    size_t tiles = (size_t)make_view_table(cams, views).total_tiles * sizeof(double);   // gs_render_fwd_l1
+    size_t tiles = ((size_t)make_view_table(cams, views).total_tiles + LOSS_SUM_BLOCKS) * sizeof(double);   // gs_render_fwd_l1
     size_t ws = loss_ws_bytes(views);
     return ws > tiles ? ws : tiles;
 }
@@ -353,7 +353,7 @@ gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, con
     CHECK_ARG(target && dL_drgb && loss_dev && workspace, "null pointer");
     CHECK_ARG(isfinite(scale), "bad scale");
     ViewTable vt = make_view_table(cams_host, views);
-    CHECK_ARG(workspace_bytes >= (size_t)vt.total_tiles * sizeof(double), "loss workspace too small");
+    CHECK_ARG(workspace_bytes >= ((size_t)vt.total_tiles + LOSS_SUM_BLOCKS) * sizeof(double), "loss workspace too small");
     LaunchShape sh;
     CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
     hipStream_t s = (hipStream_t)stream;

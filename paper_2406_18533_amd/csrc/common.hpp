@@ -10,6 +10,7 @@ namespace gs {
 
 constexpr int TILE = GS_TILE;
 constexpr int MAXV = GS_MAX_VIEWS;
+constexpr int LOSS_SUM_BLOCKS = 64;   // blocks of the fused loss's deterministic sum
 constexpr int REC = GS_REC;
 
 // Record slots of a projected (view, Gaussian) entry.

@@ -160,8 +160,8 @@ template <typename T> __device__ __forceinline__ void sh_basis(T x, T y, T z, T 
 }
 
 // sum_k w_k grad Y_k of the polynomial forms above (before projection onto
-// the sphere's tangent plane).
-template <typename T> __device__ __forceinline__ void sh_grad(T x, T y, T z, const T w[16], T g[3])
+// the sphere's tangent plane); w(k) gives the weight of basis function k.
+template <typename T, typename W> __device__ __forceinline__ void sh_grad(T x, T y, T z, W w, T g[3])
 {
     constexpr double PI = 3.14159265358979323846;
     const T c1 = GS_SQRT(3.0 / (4.0 * PI));
@@ -170,21 +170,21 @@ template <typename T> __device__ __forceinline__ void sh_grad(T x, T y, T z, con
     const T c3d = GS_SQRT(7.0 / (16.0 * PI)), c3e = GS_SQRT(105.0 / (16.0 * PI));
     T xx = x * x, yy = y * y, zz = z * z;
     T gx = T(0), gy = T(0), gz = T(0);
-    gy += -c1 * w[1];
-    gz += c1 * w[2];
-    gx += -c1 * w[3];
-    gx += c2a * y * w[4]; gy += c2a * x * w[4];
-    gy += -c2a * z * w[5]; gz += -c2a * y * w[5];
-    gz += c2b * T(6) * z * w[6];
-    gx += -c2a * z * w[7]; gz += -c2a * x * w[7];
-    gx += c2c * T(2) * x * w[8]; gy += -c2c * T(2) * y * w[8];
-    gx += -c3a * T(6) * x * y * w[9]; gy += -c3a * (T(3) * xx - T(3) * yy) * w[9];
-    gx += c3b * y * z * w[10]; gy += c3b * x * z * w[10]; gz += c3b * x * y * w[10];
-    gy += -c3c * (T(5) * zz - T(1)) * w[11]; gz += -c3c * T(10) * y * z * w[11];
-    gz += c3d * (T(15) * zz - T(3)) * w[12];
-    gx += -c3c * (T(5) * zz - T(1)) * w[13]; gz += -c3c * T(10) * x * z * w[13];
-    gx += c3e * T(2) * x * z * w[14]; gy += -c3e * T(2) * y * z * w[14]; gz += c3e * (xx - yy) * w[14];
-    gx += -c3a * (T(3) * xx - T(3) * yy) * w[15]; gy += c3a * T(6) * x * y * w[15];
+    gy += -c1 * w(1);
+    gz += c1 * w(2);
+    gx += -c1 * w(3);
+    gx += c2a * y * w(4); gy += c2a * x * w(4);
+    gy += -c2a * z * w(5); gz += -c2a * y * w(5);
+    gz += c2b * T(6) * z * w(6);
+    gx += -c2a * z * w(7); gz += -c2a * x * w(7);
+    gx += c2c * T(2) * x * w(8); gy += -c2c * T(2) * y * w(8);
+    gx += -c3a * T(6) * x * y * w(9); gy += -c3a * (T(3) * xx - T(3) * yy) * w(9);
+    gx += c3b * y * z * w(10); gy += c3b * x * z * w(10); gz += c3b * x * y * w(10);
+    gy += -c3c * (T(5) * zz - T(1)) * w(11); gz += -c3c * T(10) * y * z * w(11);
+    gz += c3d * (T(15) * zz - T(3)) * w(12);
+    gx += -c3c * (T(5) * zz - T(1)) * w(13); gz += -c3c * T(10) * x * z * w(13);
+    gx += c3e * T(2) * x * z * w(14); gy += -c3e * T(2) * y * z * w(14); gz += c3e * (xx - yy) * w(14);
+    gx += -c3a * (T(3) * xx - T(3) * yy) * w(15); gy += c3a * T(6) * x * y * w(15);
     g[0] = gx; g[1] = gy; g[2] = gz;
 }
 #undef GS_SQRT
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
 // Two kernels keep register pressure low: the geometry kernel covers
 // position (through u, v and the perspective Jacobian), scale, rotation and
 // opacity; the colour kernel covers the SH coefficients and the position
-// gradient through the viewing direction, one colour channel at a time.
+// gradient through the viewing direction.
 //
 // With ADAM the kernels apply the Adam step to the parameters instead of
 // adding into grad (the gradient is the same expression, summed in the same
@@ -384,101 +384,103 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P
     }
 }
 
-// Colour part, one wavefront per colour channel: a block holds 64 Gaussians
-// (one per lane) and its three wavefronts are the channels. Each wavefront
-// walks the views its Gaussians are seen from and accumulates the SH
-// gradients of its channel (coalesced rows 11 + 3 k + ch) and its channel's
-// share of the position gradient through the viewing direction; the three
-// shares meet in LDS, wavefront c finishes position row c, and after the
-// barrier wavefront c clears 16-byte slice c of every record it consumed.
-constexpr int COLOUR_G = 64;   // Gaussians per block (one per lane); 3 wavefronts = channels
+// Colour part, one thread per Gaussian and all three channels: the thread
+// walks the views its Gaussian is seen from; per view it forms the direction
+// and the SH basis once, tests each channel's clamp (the raw colour summed in
+// the forward's order, so the mask agrees), accumulates the SH gradients of
+// the unclamped channels (rows 11 + 3 k + c, coalesced) and the position
+// gradient through the viewing direction, which is linear in the weights:
+// one sh_grad of the clamp-masked sum over channels of dL/drgb_c sh_c.
+// Afterwards it clears every record it consumed.
+constexpr int COLOUR_NT = 256;
 
 template <typename T, bool ADAM>
-__global__ void __launch_bounds__(3 * COLOUR_G) project_bwd_colour_kernel(T *__restrict__ P, int64_t n,
-                                                                          const gs_camera *__restrict__ cams,
-                                                                          int32_t views, const T *__restrict__ proj,
-                                                                          T *__restrict__ dproj, int clear,
-                                                                          T *__restrict__ grad, AdamRef<T> ad)
+__global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__restrict__ P, int64_t n,
+                                                                       const gs_camera *__restrict__ cams,
+                                                                       int32_t views, const T *__restrict__ proj,
+                                                                       T *__restrict__ dproj, int clear,
+                                                                       T *__restrict__ grad, AdamRef<T> ad)
 {
-    __shared__ T s_gd[3][3][COLOUR_G];   // [channel][position component][Gaussian]
-    const int ch = threadIdx.x / COLOUR_G, lane = threadIdx.x % COLOUR_G;
-    const int64_t i = (int64_t)blockIdx.x * COLOUR_G + lane;
-    const bool valid = i < n;
+    const int64_t i = (int64_t)blockIdx.x * COLOUR_NT + threadIdx.x;
+    if (i >= n) return;
     uint64_t vis = 0;
-    if (valid) {
-        const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
-        for (int v = 0; v < views; v++)
-            if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
+    const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
+    for (int v = 0; v < views; v++)
+        if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
+    if (!vis) {
+        if (ADAM) {                                   // seen by no view: Adam with a zero gradient
+            const T zero[4] = {0, 0, 0, 0};
+            adam_rows(P, ad, 0, 1, 3, n, i, zero);
+            for (int q4 = 0; q4 < 12; q4++) adam_rows(P, ad, 11 + 4 * q4, 1, 4, n, i, zero);
+        }
+        return;
     }
+    T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    T sh[3][16], gsh[3][16];
+    for (int k2 = 0; k2 < 16; k2++)
+        for (int c = 0; c < 3; c++) {
+            sh[c][k2] = P[(11 + 3 * k2 + c) * n + i];
+            gsh[c][k2] = T(0);
+        }
     T gmean[3] = {0, 0, 0};
-    if (valid && vis) {
-        T x[3] = {P[i], P[n + i], P[2 * n + i]};
-        T sh[16], gsh[16];
-        for (int k2 = 0; k2 < 16; k2++) {
-            sh[k2] = P[(11 + 3 * k2 + ch) * n + i];
-            gsh[k2] = T(0);
-        }
-        for (int v = 0; v < views; v++) {
-            if (!((vis >> v) & 1ull)) continue;
-            const T *dr = dproj + ((int64_t)v * n + i) * REC;
-            T drgb = dr[D_RGB + ch];
-            const gs_camera *c = cams + v;
-            T cen[3];
-            for (int j = 0; j < 3; j++)
-                cen[j] = (T)(-(c->R[j] * c->t[0] + c->R[3 + j] * c->t[1] + c->R[6 + j] * c->t[2]));
-            T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
-            T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
-            T Y[16];
-            sh_basis(dir[0], dir[1], dir[2], Y);
-            T raw = T(0);   // same summation order as the forward, so the clamp mask agrees
-            for (int k2 = 0; k2 < 16; k2++) raw += sh[k2] * Y[k2];
-            raw += T(0.5);
-            if (!(raw > T(0))) continue;
-            T wk[16];
-            for (int k2 = 0; k2 < 16; k2++) {
-                gsh[k2] += drgb * Y[k2];
-                wk[k2] = drgb * sh[k2];
-            }
-            T gd[3];
-            sh_grad(dir[0], dir[1], dir[2], wk, gd);
-            T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
-            for (int j = 0; j < 3; j++) gmean[j] += (gd[j] - dir[j] * dd) * idn;
-        }
-        if (!ADAM)
-            for (int k2 = 0; k2 < 16; k2++) grad[(11 + 3 * k2 + ch) * n + i] += gsh[k2];
-        else {
-            T g4[4];
-            for (int q4 = 0; q4 < 4; q4++) {           // SH rows 11 + 3 k + ch, 4 at a time
-                for (int r = 0; r < 4; r++) g4[r] = T(0) + gsh[4 * q4 + r];
-                adam_rows(P, ad, 11 + 3 * 4 * q4 + ch, 3, 4, n, i, g4);
-            }
-        }
-    } else if (valid && ADAM) {                       // seen by no view: Adam with a zero gradient
-        const T zero[4] = {0, 0, 0, 0};
-        for (int q4 = 0; q4 < 4; q4++) adam_rows(P, ad, 11 + 3 * 4 * q4 + ch, 3, 4, n, i, zero);
+    for (int v = 0; v < views; v++) {
+        if (!((vis >> v) & 1ull)) continue;
+        const T *dr = dproj + ((int64_t)v * n + i) * REC;
+        T drgb[3] = {dr[D_RGB], dr[D_RGB + 1], dr[D_RGB + 2]};
+        const gs_camera *cm = cams + v;
+        T cen[3];
+        for (int j = 0; j < 3; j++)
+            cen[j] = (T)(-(cm->R[j] * cm->t[0] + cm->R[3 + j] * cm->t[1] + cm->R[6 + j] * cm->t[2]));
+        T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
+        T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
+        T Y[16];
+        sh_basis(dir[0], dir[1], dir[2], Y);
+        T raw[3] = {T(0), T(0), T(0)};   // each summed in the forward's order, so the clamp mask agrees
+        for (int k2 = 0; k2 < 16; k2++)
+            for (int c = 0; c < 3; c++) raw[c] += sh[c][k2] * Y[k2];
+        T a[3];                          // dL/drgb of the unclamped channels, 0 for clamped ones
+        for (int c = 0; c < 3; c++) a[c] = raw[c] + T(0.5) > T(0) ? drgb[c] : T(0);
+        if (!(raw[0] + T(0.5) > T(0)) && !(raw[1] + T(0.5) > T(0)) && !(raw[2] + T(0.5) > T(0))) continue;
+        for (int k2 = 0; k2 < 16; k2++)
+            for (int c = 0; c < 3; c++) gsh[c][k2] = fma(a[c], Y[k2], gsh[c][k2]);
+        T gd[3];
+        sh_grad(dir[0], dir[1], dir[2], [&](int k2) { return fma(a[2], sh[2][k2], fma(a[1], sh[1][k2], a[0] * sh[0][k2])); },
+                gd);
+        T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+        for (int j = 0; j < 3; j++) gmean[j] += (gd[j] - dir[j] * dd) * idn;
     }
-    for (int j = 0; j < 3; j++) s_gd[ch][j][lane] = gmean[j];
-    __syncthreads();                                  // every channel has read its record gradients
-    if (!valid) return;
-    const int j = ch;                                 // position row finished by this wavefront
-    if (vis) {
-        T gj = (s_gd[0][j][lane] + s_gd[1][j][lane]) + s_gd[2][j][lane];
-        if (!ADAM) {
-            grad[j * n + i] += gj;
-        } else {
-            T g = grad[j * n + i] + gj;
+    if (!ADAM) {
+        for (int k2 = 0; k2 < 16; k2++)
+            for (int c = 0; c < 3; c++) grad[(11 + 3 * k2 + c) * n + i] += gsh[c][k2];
+        for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
+    } else {
+        T g4[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 12; q4++) {               // SH rows 11 .. 58, 4 at a time
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = 4 * q4 + r;             // row - 11 = 3 k + c
+                g4[r] = T(0) + gsh[row % 3][row / 3];
+            }
+            adam_rows(P, ad, 11 + 4 * q4, 1, 4, n, i, g4);
+        }
+        T g3[3];                                        // position: the geometry kernel's part is in grad
+        for (int j = 0; j < 3; j++) {
+            g3[j] = grad[j * n + i] + gmean[j];
             grad[j * n + i] = T(0);
-            adam_rows(P, ad, j, 1, 1, n, i, &g);
         }
-        if (clear) {
-            const V4<T> zero{T(0), T(0), T(0), T(0)};
-            for (int v = 0; v < views; v++)
-                if ((vis >> v) & 1ull) reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC)[ch] = zero;
-        }
-    } else if (ADAM) {
-        const T zero = T(0);
-        adam_rows(P, ad, j, 1, 1, n, i, &zero);
+        adam_rows(P, ad, 0, 1, 3, n, i, g3);
+    }
+    if (clear) {
+        const V4<T> zero{T(0), T(0), T(0), T(0)};
+        for (int v = 0; v < views; v++)
+            if ((vis >> v) & 1ull) {
+                V4<T> *rec = reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
+                rec[0] = zero;
+                rec[1] = zero;
+                rec[2] = zero;
+            }
     }
 }
 
@@ -503,8 +505,8 @@ hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, i
     hipLaunchKernelGGL((project_bwd_geom_kernel<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
                        const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (const T *)dproj, (T *)grad,
                        none);
-    hipLaunchKernelGGL((project_bwd_colour_kernel<T, false>), dim3((unsigned)((n + COLOUR_G - 1) / COLOUR_G)),
-                       dim3(3 * COLOUR_G), 0, s, const_cast<T *>((const T *)P), n, cams, views, (const T *)proj,
+    hipLaunchKernelGGL((project_bwd_colour_kernel<T, false>), dim3((unsigned)((n + COLOUR_NT - 1) / COLOUR_NT)),
+                       dim3(COLOUR_NT), 0, s, const_cast<T *>((const T *)P), n, cams, views, (const T *)proj,
                        (T *)dproj, clear, (T *)grad, none);
     return hipGetLastError();
 }
@@ -520,8 +522,8 @@ hipError_t launch_project_bwd_adam(void *P, int64_t n, const gs_camera *cams, in
     int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL((project_bwd_geom_kernel<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, (T *)P, n, cams,
                        views, (const T *)proj, (const T *)dproj, (T *)grad, ad);
-    hipLaunchKernelGGL((project_bwd_colour_kernel<T, true>), dim3((unsigned)((n + COLOUR_G - 1) / COLOUR_G)),
-                       dim3(3 * COLOUR_G), 0, s, (T *)P, n, cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
+    hipLaunchKernelGGL((project_bwd_colour_kernel<T, true>), dim3((unsigned)((n + COLOUR_NT - 1) / COLOUR_NT)),
+                       dim3(COLOUR_NT), 0, s, (T *)P, n, cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
     return hipGetLastError();
 }
 

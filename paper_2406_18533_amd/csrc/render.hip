@@ -589,21 +589,31 @@ __global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, 
         else { CALL(T, 4, 256); }                                                                            \
     } while (0)
 
-// Sum of the per-tile loss shares in a fixed order (deterministic): each
-// thread adds a fixed strided subset, then a fixed tree over the threads.
-__global__ void __launch_bounds__(1024) loss_tiles_sum_kernel(const double *__restrict__ part, int64_t n,
-                                                              double *__restrict__ loss)
+// Sum of the per-tile loss shares in a fixed order (deterministic): block b
+// adds slice b of the tiles (a fixed strided split over its threads, then a
+// fixed tree), and one wavefront adds the block sums with a fixed tree.
+__global__ void __launch_bounds__(256) loss_tiles_part_kernel(const double *__restrict__ part, int64_t n,
+                                                             double *__restrict__ bsum)
 {
-    __shared__ double s[1024];
+    __shared__ double s[256];
+    const int64_t per = (n + LOSS_SUM_BLOCKS - 1) / LOSS_SUM_BLOCKS;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
     double a = 0.0;
-    for (int64_t j = threadIdx.x; j < n; j += 1024) a += part[j];
+    for (int64_t j = b0 + threadIdx.x; j < b1; j += 256) a += part[j];
     s[threadIdx.x] = a;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *loss = s[0];
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(64) loss_tiles_final_kernel(const double *__restrict__ bsum, double *__restrict__ loss)
+{
+    double a = bsum[threadIdx.x];   // LOSS_SUM_BLOCKS == 64: one per lane
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (threadIdx.x == 0) *loss = a;
 }
 
 template <typename T>
@@ -645,9 +655,12 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     }
 #undef GS_FWD
 #undef GS_FWD_S
-    if (target)
-        hipLaunchKernelGGL(loss_tiles_sum_kernel, dim3(1), dim3(1024), 0, s, (const double *)loss_tiles,
-                           (int64_t)vt.total_tiles, loss);
+    if (target) {
+        double *bsum = loss_tiles + vt.total_tiles;
+        hipLaunchKernelGGL(loss_tiles_part_kernel, dim3(LOSS_SUM_BLOCKS), dim3(256), 0, s, (const double *)loss_tiles,
+                           (int64_t)vt.total_tiles, bsum);
+        hipLaunchKernelGGL(loss_tiles_final_kernel, dim3(1), dim3(64), 0, s, (const double *)bsum, loss);
+    }
     return hipGetLastError();
 }
 

@@ -304,35 +304,34 @@ template <typename T> struct AdamRef {
     const double *scratch;
 };
 
-// Adam on up to 4 rows of Gaussian i at once: rows row0 + r * stride for
-// r < cnt, gradients g[r]. All loads are issued before any store (the
-// moment and parameter arrays never alias), so the memory latency of the
-// rows overlaps.
-template <typename T>
-__device__ __forceinline__ void adam_rows(T *__restrict__ P, const AdamRef<T> &a, int row0, int stride, int cnt,
-                                          int64_t n, int64_t i, const T *g)
+// Adam on CNT consecutive rows row0 .. row0 + CNT - 1 of Gaussian i with
+// gradients g[r]: all loads are issued before any update, so the memory
+// latency of the rows overlaps.
+template <typename T, int CNT>
+__device__ __forceinline__ void adam_row_block(T *__restrict__ P, const AdamRef<T> &a, int row0, int64_t n, int64_t i,
+                                               const T *g)
 {
     double bc1 = a.scratch[0];
     if (bc1 == 0.0) return;                       // skipped step
-    T *__restrict__ M = a.M;
-    T *__restrict__ V = a.V;
-    T p[4], m[4], v[4];
-    for (int r = 0; r < 4; r++) {
-        if (r >= cnt) break;
-        int64_t k = (int64_t)(row0 + r * stride) * n + i;
+    T *M = a.M;                                   // (no restrict: a later block's loads stay after this block's stores)
+    T *V = a.V;
+    T p[CNT], m[CNT], v[CNT];
+#pragma unroll
+    for (int r = 0; r < CNT; r++) {
+        int64_t k = (int64_t)(row0 + r) * n + i;
         p[r] = P[k];
         m[r] = M[k];
         v[r] = V[k];
     }
     T b1 = (T)a.c.b1, b2 = (T)a.c.b2, eps = (T)a.c.eps, bc2s = (T)a.scratch[1];
-    for (int r = 0; r < 4; r++) {
-        if (r >= cnt) break;
-        T step = (T)a.c.lr[row_group(row0 + r * stride)] / (T)bc1;
+#pragma unroll
+    for (int r = 0; r < CNT; r++) {
+        T step = (T)a.c.lr[row_group(row0 + r)] / (T)bc1;
         adam_one(p[r], g[r], m[r], v[r], b1, b2, step, bc2s, eps);
     }
-    for (int r = 0; r < 4; r++) {
-        if (r >= cnt) break;
-        int64_t k = (int64_t)(row0 + r * stride) * n + i;
+#pragma unroll
+    for (int r = 0; r < CNT; r++) {
+        int64_t k = (int64_t)(row0 + r) * n + i;
         P[k] = p[r];
         M[k] = m[r];
         V[k] = v[r];

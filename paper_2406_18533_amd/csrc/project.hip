@@ -293,9 +293,8 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P
         if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
     if (!vis) {
         if (ADAM) {
-            const T zero[4] = {0, 0, 0, 0};
-            adam_rows(P, ad, 3, 1, 4, n, i, zero);
-            adam_rows(P, ad, 7, 1, 4, n, i, zero);
+            const T zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            adam_row_block<T, 8>(P, ad, 3, n, i, zero);
         }
         return;
     }
@@ -379,8 +378,7 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P
         for (int c = 0; c < 3; c++) g8[c] = T(0) + gls[c];
         for (int j = 0; j < 4; j++) g8[3 + j] = T(0) + (dq[j] - S.q[j] * dot) * iqn;
         g8[7] = T(0) + gop * S.opac * (T(1) - S.opac);
-        adam_rows(P, ad, 3, 1, 4, n, i, g8);      // rows 3-10
-        adam_rows(P, ad, 7, 1, 4, n, i, g8 + 4);
+        adam_row_block<T, 8>(P, ad, 3, n, i, g8);   // rows 3-10
     }
 }
 
@@ -409,9 +407,13 @@ __global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__rest
         if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
     if (!vis) {
         if (ADAM) {                                   // seen by no view: Adam with a zero gradient
-            const T zero[4] = {0, 0, 0, 0};
-            adam_rows(P, ad, 0, 1, 3, n, i, zero);
-            for (int q4 = 0; q4 < 12; q4++) adam_rows(P, ad, 11 + 4 * q4, 1, 4, n, i, zero);
+            const T zero[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            adam_row_block<T, 3>(P, ad, 0, n, i, zero);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                adam_row_block<T, 12>(P, ad, 11 + 12 * b, n, i, zero);
+                asm volatile("" ::: "memory");
+            }
         }
         return;
     }
@@ -455,22 +457,23 @@ __global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__rest
             for (int c = 0; c < 3; c++) grad[(11 + 3 * k2 + c) * n + i] += gsh[c][k2];
         for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
     } else {
-        T g4[4];
-#pragma unroll
-        for (int q4 = 0; q4 < 12; q4++) {               // SH rows 11 .. 58, 4 at a time
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int row = 4 * q4 + r;             // row - 11 = 3 k + c
-                g4[r] = T(0) + gsh[row % 3][row / 3];
-            }
-            adam_rows(P, ad, 11 + 4 * q4, 1, 4, n, i, g4);
-        }
         T g3[3];                                        // position: the geometry kernel's part is in grad
         for (int j = 0; j < 3; j++) {
             g3[j] = grad[j * n + i] + gmean[j];
             grad[j * n + i] = T(0);
         }
-        adam_rows(P, ad, 0, 1, 3, n, i, g3);
+        adam_row_block<T, 3>(P, ad, 0, n, i, g3);
+#pragma unroll
+        for (int b = 0; b < 6; b++) {                   // SH rows 11 .. 58, 8 at a time; row - 11 = 3 k + c
+            T gb[8];
+#pragma unroll
+            for (int r = 0; r < 8; r++) {
+                const int t = 8 * b + r;
+                gb[r] = T(0) + gsh[t % 3][t / 3];
+            }
+            adam_row_block<T, 8>(P, ad, 11 + 8 * b, n, i, gb);
+            asm volatile("" ::: "memory");              // one block's moments in registers at a time
+        }
     }
     if (clear) {
         const V4<T> zero{T(0), T(0), T(0), T(0)};

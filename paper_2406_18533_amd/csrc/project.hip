@@ -264,41 +264,35 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
 
 // Transformation backward: chain rule from the per-view record gradients
 // d(u, v, a, b, c, opacity, rgb) to the 59 parameters, summed over views in
-// registers; each parameter gradient is added once per kernel (no atomics).
-// Two kernels keep register pressure low: the geometry kernel covers
-// position (through u, v and the perspective Jacobian), scale, rotation and
-// opacity; the colour kernel covers the SH coefficients and the position
-// gradient through the viewing direction.
+// registers; each parameter gradient is added once (no atomics). One thread
+// per Gaussian, in two phases that keep register pressure apart:
+//  - geometry: position (through u, v and the perspective Jacobian), scale,
+//    rotation and opacity;
+//  - colour, all three channels: per seen view the direction and the SH
+//    basis are formed once, each channel's clamp is tested (the raw colour
+//    summed in the forward's order, so the mask agrees), the SH gradients of
+//    the unclamped channels are accumulated (rows 11 + 3 k + c) and so is
+//    the position gradient through the viewing direction, which is linear
+//    in the weights: one sh_grad of the clamp-masked channel sum of
+//    dL/drgb_c sh_c.
+// The records are read once and, with `clear`, zeroed after use.
 //
-// With ADAM the kernels apply the Adam step to the parameters instead of
-// adding into grad (the gradient is the same expression, summed in the same
-// order, so the result equals the two separate calls bit for bit): the
-// geometry kernel updates rows 3-10 and leaves its part of the position
-// gradient in grad rows 0-2 (all-zero on entry); the colour kernel adds the
-// viewing-direction part, updates rows 0-2 and 11-58 and zeroes grad rows
-// 0-2 again. Each kernel reads only parameters that it alone updates, or
-// that nothing updates before it reads them. Gaussians seen by no view get
-// the Adam step with a zero gradient.
-template <typename T, bool ADAM>
-__global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P, int64_t n,
-                                                               const gs_camera *__restrict__ cams, int32_t views,
-                                                               const T *__restrict__ proj, const T *__restrict__ dproj,
-                                                               T *__restrict__ grad, AdamRef<T> ad)
+// With ADAM the Adam step is applied to the parameters instead of adding
+// into grad: the gradient is the same expression, summed in the same order
+// ((0 + geometry part) + colour part for the position), so the result equals
+// the two separate calls bit for bit, and grad is left untouched. Rows 3-10
+// are updated after the geometry phase (nothing reads them later); position
+// and SH rows, read before, are updated at the end. Gaussians seen by no view
+// get the Adam step with a zero gradient on all 59 rows.
+
+// Geometry part for Gaussian i, seen by the views in vis: the position
+// gradient gpos and the gradients g8 of rows 3-10 (log-scales, rotation,
+// opacity logit).
+template <typename T>
+__device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, int64_t i, const T x[3],
+                                           const gs_camera *__restrict__ cams, int32_t views, uint64_t vis,
+                                           const T *__restrict__ dproj, T gpos[3], T g8[8])
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t vis = 0;
-    const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
-    for (int v = 0; v < views; v++)
-        if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
-    if (!vis) {
-        if (ADAM) {
-            const T zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            adam_row_block<T, 8>(P, ad, 3, n, i, zero);
-        }
-        return;
-    }
-    T x[3] = {P[i], P[n + i], P[2 * n + i]};
     Shape<T> S;
     make_shape(P, n, i, S);
     T gmean[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = T(0);
@@ -367,39 +361,21 @@ __global__ void __launch_bounds__(256) project_bwd_geom_kernel(T *__restrict__ P
                     qy * dRq[5] + qx * dRq[6] + qy * dRq[7]);
     T dot = dq[0] * S.q[0] + dq[1] * S.q[1] + dq[2] * S.q[2] + dq[3] * S.q[3];
     T iqn = T(1) / S.qn;
-    if (!ADAM) {
-        for (int c = 0; c < 3; c++) grad[c * n + i] += gmean[c];
-        for (int c = 0; c < 3; c++) grad[(3 + c) * n + i] += gls[c];
-        for (int j = 0; j < 4; j++) grad[(6 + j) * n + i] += (dq[j] - S.q[j] * dot) * iqn;
-        grad[10 * n + i] += gop * S.opac * (T(1) - S.opac);
-    } else {
-        for (int c = 0; c < 3; c++) grad[c * n + i] = T(0) + gmean[c];   // as += into a zero gradient
-        T g8[8];
-        for (int c = 0; c < 3; c++) g8[c] = T(0) + gls[c];
-        for (int j = 0; j < 4; j++) g8[3 + j] = T(0) + (dq[j] - S.q[j] * dot) * iqn;
-        g8[7] = T(0) + gop * S.opac * (T(1) - S.opac);
-        adam_row_block<T, 8>(P, ad, 3, n, i, g8);   // rows 3-10
+    for (int c = 0; c < 3; c++) {
+        gpos[c] = gmean[c];
+        g8[c] = gls[c];
     }
+    for (int j = 0; j < 4; j++) g8[3 + j] = (dq[j] - S.q[j] * dot) * iqn;
+    g8[7] = gop * S.opac * (T(1) - S.opac);
 }
 
-// Colour part, one thread per Gaussian and all three channels: the thread
-// walks the views its Gaussian is seen from; per view it forms the direction
-// and the SH basis once, tests each channel's clamp (the raw colour summed in
-// the forward's order, so the mask agrees), accumulates the SH gradients of
-// the unclamped channels (rows 11 + 3 k + c, coalesced) and the position
-// gradient through the viewing direction, which is linear in the weights:
-// one sh_grad of the clamp-masked sum over channels of dL/drgb_c sh_c.
-// Afterwards it clears every record it consumed.
-constexpr int COLOUR_NT = 256;
-
 template <typename T, bool ADAM>
-__global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__restrict__ P, int64_t n,
-                                                                       const gs_camera *__restrict__ cams,
-                                                                       int32_t views, const T *__restrict__ proj,
-                                                                       T *__restrict__ dproj, int clear,
-                                                                       T *__restrict__ grad, AdamRef<T> ad)
+__global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int64_t n,
+                                                          const gs_camera *__restrict__ cams, int32_t views,
+                                                          const T *__restrict__ proj, T *__restrict__ dproj, int clear,
+                                                          T *__restrict__ grad, AdamRef<T> ad)
 {
-    const int64_t i = (int64_t)blockIdx.x * COLOUR_NT + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint64_t vis = 0;
     const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
@@ -409,6 +385,9 @@ __global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__rest
         if (ADAM) {                                   // seen by no view: Adam with a zero gradient
             const T zero[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
             adam_row_block<T, 3>(P, ad, 0, n, i, zero);
+            asm volatile("" ::: "memory");
+            adam_row_block<T, 8>(P, ad, 3, n, i, zero);
+            asm volatile("" ::: "memory");
 #pragma unroll
             for (int b = 0; b < 4; b++) {
                 adam_row_block<T, 12>(P, ad, 11 + 12 * b, n, i, zero);
@@ -418,6 +397,18 @@ __global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__rest
         return;
     }
     T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    T gpos[3];
+    {
+        T g8[8];
+        geom_grads(P, n, i, x, cams, views, vis, dproj, gpos, g8);
+        if (!ADAM) {
+            for (int r = 0; r < 8; r++) grad[(3 + r) * n + i] += g8[r];
+        } else {
+            for (int r = 0; r < 8; r++) g8[r] = T(0) + g8[r];   // as += into a zero gradient
+            adam_row_block<T, 8>(P, ad, 3, n, i, g8);           // rows 3-10
+        }
+    }
+    asm volatile("" ::: "memory");
     T sh[3][16], gsh[3][16];
     for (int k2 = 0; k2 < 16; k2++)
         for (int c = 0; c < 3; c++) {
@@ -455,13 +446,10 @@ __global__ void __launch_bounds__(COLOUR_NT) project_bwd_colour_kernel(T *__rest
     if (!ADAM) {
         for (int k2 = 0; k2 < 16; k2++)
             for (int c = 0; c < 3; c++) grad[(11 + 3 * k2 + c) * n + i] += gsh[c][k2];
-        for (int j = 0; j < 3; j++) grad[j * n + i] += gmean[j];
+        for (int j = 0; j < 3; j++) grad[j * n + i] = (grad[j * n + i] + gpos[j]) + gmean[j];
     } else {
-        T g3[3];                                        // position: the geometry kernel's part is in grad
-        for (int j = 0; j < 3; j++) {
-            g3[j] = grad[j * n + i] + gmean[j];
-            grad[j * n + i] = T(0);
-        }
+        T g3[3];
+        for (int j = 0; j < 3; j++) g3[j] = (T(0) + gpos[j]) + gmean[j];
         adam_row_block<T, 3>(P, ad, 0, n, i, g3);
 #pragma unroll
         for (int b = 0; b < 6; b++) {                   // SH rows 11 .. 58, 8 at a time; row - 11 = 3 k + c
@@ -503,14 +491,10 @@ hipError_t launch_project_bwd(const void *P, int64_t n, const gs_camera *cams, i
                               void *dproj, int clear, void *grad, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
     AdamRef<T> none{};
-    hipLaunchKernelGGL((project_bwd_geom_kernel<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (const T *)dproj, (T *)grad,
+    hipLaunchKernelGGL((project_bwd_kernel<T, false>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       const_cast<T *>((const T *)P), n, cams, views, (const T *)proj, (T *)dproj, clear, (T *)grad,
                        none);
-    hipLaunchKernelGGL((project_bwd_colour_kernel<T, false>), dim3((unsigned)((n + COLOUR_NT - 1) / COLOUR_NT)),
-                       dim3(COLOUR_NT), 0, s, const_cast<T *>((const T *)P), n, cams, views, (const T *)proj,
-                       (T *)dproj, clear, (T *)grad, none);
     return hipGetLastError();
 }
 
@@ -522,11 +506,8 @@ hipError_t launch_project_bwd_adam(void *P, int64_t n, const gs_camera *cams, in
     AdamRef<T> ad{(T *)m, (T *)v, make_adam_const(h), scratch};
     hipError_t e = launch_adam_prepare(step, ad.c, scratch, skip, s);
     if (n == 0 || e != hipSuccess) return e;
-    int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL((project_bwd_geom_kernel<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, (T *)P, n, cams,
-                       views, (const T *)proj, (const T *)dproj, (T *)grad, ad);
-    hipLaunchKernelGGL((project_bwd_colour_kernel<T, true>), dim3((unsigned)((n + COLOUR_NT - 1) / COLOUR_NT)),
-                       dim3(COLOUR_NT), 0, s, (T *)P, n, cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
+    hipLaunchKernelGGL((project_bwd_kernel<T, true>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (T *)P, n,
+                       cams, views, (const T *)proj, (T *)dproj, 1, (T *)grad, ad);
     return hipGetLastError();
 }
 

@@ -157,10 +157,9 @@ def algorithmic(c: dict) -> dict:
         "gs_project_bwd": ("hbm", 708 * Ns + 4 * VN + 72 * M),
         # read p, g, m, v and write p, m, v (+ g cleared): 32 B per parameter float, 59 per Gaussian
         "gs_adam_step": ("hbm", 32 * 59 * N),
-        # both in one pass: read p, m, v and write p, m, v for every parameter float (24 B), the position
-        # gradient handed between the two kernels (36 B per on-screen Gaussian), tiles field of every
-        # record, the record gradient read and cleared per on-screen record
-        "gs_project_bwd_adam": ("hbm", 24 * 59 * N + 36 * Ns + 4 * VN + 72 * M),
+        # both in one pass: read p, m, v and write p, m, v for every parameter float (24 B), tiles field
+        # of every record, the record gradient read and cleared per on-screen record
+        "gs_project_bwd_adam": ("hbm", 24 * 59 * N + 4 * VN + 72 * M),
     }
 
 

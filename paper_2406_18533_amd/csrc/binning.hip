@@ -281,8 +281,12 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
     return peers;
 }
 
-template <int BITS>
-__global__ void __launch_bounds__(SB) seg_count_kernel(const uint32_t *__restrict__ kin,
+// Keys are uint32 (FP32 depth bits, or global tile ids, whose digits are
+// taken from key - base[v]) or, for the tile sort of views with at most 2^16
+// tiles, uint16 tile ids within the view (LOCAL: base 0); the last pass of
+// such a sort writes global ids (GLOBAL_OUT: key + base[v]).
+template <int BITS, typename KI, bool LOCAL>
+__global__ void __launch_bounds__(SB) seg_count_kernel(const KI *__restrict__ kin,
                                                        const SegPlan *__restrict__ plan, int views, int shift,
                                                        uint32_t *__restrict__ hist)
 {
@@ -294,7 +298,7 @@ __global__ void __launch_bounds__(SB) seg_count_kernel(const uint32_t *__restric
     const int64_t t = b - plan->b0[v], nt = plan->b0[v + 1] - plan->b0[v];
     const int64_t beg = plan->start[v] + t * STILE;
     const int64_t end = plan->start[v + 1] < beg + STILE ? plan->start[v + 1] : beg + STILE;
-    const uint32_t kb = plan->base[v];
+    const uint32_t kb = LOCAL ? 0u : plan->base[v];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
     __syncthreads();
@@ -302,7 +306,7 @@ __global__ void __launch_bounds__(SB) seg_count_kernel(const uint32_t *__restric
     uint32_t kk[SITEMS];
     for (int it = 0; it < SITEMS; it++) {          // all loads of the tile in flight at once
         int64_t idx = i0 + it * 64;
-        kk[it] = idx < end ? kin[idx] : 0u;
+        kk[it] = idx < end ? (uint32_t)kin[idx] : 0u;
     }
     for (int it = 0; it < SITEMS; it++)             // counts only: LDS atomics, no ranks needed
         if (i0 + it * 64 < end) atomicAdd(&s_cnt[w][((kk[it] - kb) >> shift) & (RADIX - 1)], 1u);
@@ -314,10 +318,10 @@ __global__ void __launch_bounds__(SB) seg_count_kernel(const uint32_t *__restric
     }
 }
 
-template <int BITS>
-__global__ void __launch_bounds__(SB) seg_scatter_kernel(const uint32_t *__restrict__ kin,
+template <int BITS, typename KI, typename KO, bool LOCAL, bool GLOBAL_OUT>
+__global__ void __launch_bounds__(SB) seg_scatter_kernel(const KI *__restrict__ kin,
                                                          const uint32_t *__restrict__ vin,
-                                                         uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                         KO *__restrict__ kout, uint32_t *__restrict__ vout,
                                                          const SegPlan *__restrict__ plan, int views, int shift,
                                                          const uint32_t *__restrict__ offs)
 {
@@ -334,7 +338,8 @@ __global__ void __launch_bounds__(SB) seg_scatter_kernel(const uint32_t *__restr
     const int64_t t = b - plan->b0[v], nt = plan->b0[v + 1] - plan->b0[v];
     const int64_t beg = plan->start[v] + t * STILE;
     const int64_t end = plan->start[v + 1] < beg + STILE ? plan->start[v + 1] : beg + STILE;
-    const uint32_t kb = plan->base[v];
+    const uint32_t kb = LOCAL ? 0u : plan->base[v];
+    const uint32_t kout_add = GLOBAL_OUT ? plan->base[v] : 0u;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int d = threadIdx.x; d < RADIX; d += SB) s_goff[d] = offs[RADIX * plan->b0[v] + d * nt + t];
     for (int d = threadIdx.x; d < RADIX * (SB / 64); d += SB) (&s_cnt[0][0])[d] = 0;
@@ -343,7 +348,7 @@ __global__ void __launch_bounds__(SB) seg_scatter_kernel(const uint32_t *__restr
     uint32_t key[SITEMS], val[SITEMS], rank[SITEMS];
     for (int it = 0; it < SITEMS; it++) {          // all loads of the tile in flight at once
         int64_t idx = i0 + it * 64;
-        key[it] = idx < end ? kin[idx] : 0u;
+        key[it] = idx < end ? (uint32_t)kin[idx] : 0u;
         val[it] = idx < end ? vin[idx] : 0u;
     }
     __syncthreads();
@@ -396,21 +401,38 @@ __global__ void __launch_bounds__(SB) seg_scatter_kernel(const uint32_t *__restr
         uint32_t k = s_key[q];
         uint32_t d = ((k - kb) >> shift) & (RADIX - 1);
         int64_t g = (int64_t)s_goff[d] + (q - (int64_t)s_start[d]);
-        kout[g] = k;
+        kout[g] = (KO)(k + kout_add);
         vout[g] = s_val[q];
     }
 }
 
-template <int BITS>
-static void seg_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *ko, uint32_t *vo, const SegPlan *plan,
-                     int views, int64_t nbmax, int shift, uint32_t *hist, uint32_t *partial, hipStream_t s)
+template <int BITS, typename KI, typename KO, bool LOCAL, bool GLOBAL_OUT>
+static void seg_pass(const KI *kin, const uint32_t *vin, KO *ko, uint32_t *vo, const SegPlan *plan, int views,
+                     int64_t nbmax, int shift, uint32_t *hist, uint32_t *partial, hipStream_t s)
 {
     constexpr int RADIX = 1 << BITS;
-    hipLaunchKernelGGL(seg_count_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, plan, views, shift, hist);
+    hipLaunchKernelGGL((seg_count_kernel<BITS, KI, LOCAL>), dim3((unsigned)nbmax), dim3(SB), 0, s, kin, plan, views,
+                       shift, hist);
     (void)device_scan<uint32_t>(U32Load{hist}, U32Store{hist}, &plan->hist_n[BITS], (int64_t)RADIX * nbmax, partial,
                                 nullptr, s);
-    hipLaunchKernelGGL(seg_scatter_kernel<BITS>, dim3((unsigned)nbmax), dim3(SB), 0, s, kin, vin, ko, vo, plan, views,
-                       shift, (const uint32_t *)hist);
+    hipLaunchKernelGGL((seg_scatter_kernel<BITS, KI, KO, LOCAL, GLOBAL_OUT>), dim3((unsigned)nbmax), dim3(SB), 0, s, kin,
+                       vin, ko, vo, plan, views, shift, (const uint32_t *)hist);
+}
+
+template <typename KI, typename KO, bool LOCAL, bool GLOBAL_OUT>
+static void seg_pass_w(int width, const KI *kin, const uint32_t *vin, KO *ko, uint32_t *vo, const SegPlan *plan,
+                       int views, int64_t nbmax, int shift, uint32_t *hist, uint32_t *partial, hipStream_t s)
+{
+    switch (width) {
+    case 1: seg_pass<1, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    case 2: seg_pass<2, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    case 3: seg_pass<3, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    case 4: seg_pass<4, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    case 5: seg_pass<5, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    case 6: seg_pass<6, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    case 7: seg_pass<7, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    default: seg_pass<8, KI, KO, LOCAL, GLOBAL_OUT>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
+    }
 }
 
 // Passes of a sort over the lowest `bits` key bits: digits of at most 8 bits,
@@ -429,26 +451,52 @@ static hipError_t seg_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt,
     if (bits < 1) bits = 1;
     const int passes = seg_passes(bits);
     const int digit = (bits + passes - 1) / passes;
-    uint32_t *kin = keys, *vin = vals, *ko = kalt, *vo = valt;
     // A narrower digit goes first: the later passes read input already
     // ordered by the lower digits, where a block's items fall into long runs
     // per digit and a wide digit costs less (measured on tile sorts).
     const int first = bits - (passes - 1) * digit;
+    uint32_t *kin = keys, *vin = vals, *ko = kalt, *vo = valt;
     for (int p = 0; p < passes; p++) {
         const int shift = p == 0 ? 0 : first + (p - 1) * digit;
         const int width = p == 0 ? first : digit;
-        switch (width) {
-        case 1: seg_pass<1>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        case 2: seg_pass<2>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        case 3: seg_pass<3>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        case 4: seg_pass<4>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        case 5: seg_pass<5>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        case 6: seg_pass<6>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        case 7: seg_pass<7>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        default: seg_pass<8>(kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial, s); break;
-        }
+        seg_pass_w<uint32_t, uint32_t, false, false>(width, kin, vin, ko, vo, plan, views, nbmax, shift, hist, partial,
+                                                     s);
         uint32_t *tk = kin, *tv = vin;
         kin = ko; vin = vo; ko = tk; vo = tv;
+    }
+    return hipGetLastError();
+}
+
+// Tile sort with 16-bit keys (tiles within the view, at most 2^16 per view):
+// the passes carry 2-byte keys between k16a and k16b and the values between
+// their buffers; the last pass writes the global tile ids to tile_out and
+// the values to val_out. The emission wrote (k16a, val_in); val_in is val_out
+// for an even pass count and val_alt for an odd one, so the values end in
+// val_out.
+static hipError_t seg_tile_sort16(uint16_t *k16a, uint16_t *k16b, uint32_t *val_in, uint32_t *val_other,
+                                  uint32_t *tile_out, uint32_t *val_out, const SegPlan *plan, int views, int64_t n_max,
+                                  int bits, uint32_t *hist, uint32_t *partial, hipStream_t s)
+{
+    if (n_max == 0) return hipSuccess;
+    const int64_t nbmax = (n_max + STILE - 1) / STILE + views;
+    if (bits < 1) bits = 1;
+    const int passes = seg_passes(bits);
+    const int digit = (bits + passes - 1) / passes;
+    const int first = bits - (passes - 1) * digit;   // narrower digit first, as above
+    uint16_t *kin = k16a, *ko = k16b;
+    uint32_t *vin = val_in, *vo = val_other;
+    for (int p = 0; p < passes; p++) {
+        const int shift = p == 0 ? 0 : first + (p - 1) * digit;
+        const int width = p == 0 ? first : digit;
+        if (p + 1 < passes) {
+            seg_pass_w<uint16_t, uint16_t, true, false>(width, kin, vin, ko, vo, plan, views, nbmax, shift, hist,
+                                                        partial, s);
+            uint16_t *tk = kin; kin = ko; ko = tk;
+            uint32_t *tv = vin; vin = vo; vo = tv;
+        } else {
+            seg_pass_w<uint16_t, uint32_t, true, true>(width, kin, vin, tile_out, val_out, plan, views, nbmax, shift,
+                                                       hist, partial, s);
+        }
     }
     return hipGetLastError();
 }
@@ -466,12 +514,15 @@ static hipError_t seg_radix_sort(uint32_t *keys, uint32_t *vals, uint32_t *kalt,
 // exact because a view has at most 2^22 tiles, so local + 1/2 < 2^22 keeps
 // the rounding error (below (local + 1/2) 2^-23 / width) under the
 // 1/(2 width) distance of the quotient from an integer.
+// K = uint32_t: global tile ids; K = uint16_t: tile ids within the view.
+template <typename K>
 __global__ void __launch_bounds__(256) emit_kernel(const uint64_t *__restrict__ rects, int64_t n, ViewTable vt,
                                                    const uint32_t *__restrict__ flat, const uint64_t *__restrict__ off,
                                                    const int64_t *m_dev, int64_t m_max, const int64_t *k_dev,
-                                                   uint32_t *__restrict__ tile_out, uint32_t *__restrict__ id_out,
+                                                   K *__restrict__ tile_out, uint32_t *__restrict__ id_out,
                                                    int64_t capacity)
 {
+    constexpr bool LOCAL = sizeof(K) == 2;
     __shared__ uint32_t s_off[256], s_xy[256], s_w[256], s_base[256], s_tx[256], s_id[256];
     __shared__ float s_rw[256];
     __shared__ uint32_t s_end;
@@ -534,7 +585,8 @@ __global__ void __launch_bounds__(256) emit_kernel(const uint64_t *__restrict__ 
             uint32_t dy = (uint32_t)(((float)local + 0.5f) * s_rw[pr]);
             uint32_t dx = local - dy * wd;
             uint32_t xy = s_xy[pr];
-            tile_out[e_beg + e] = s_base[pr] + ((xy >> 16) + dy) * s_tx[pr] + (xy & 0xffffu) + dx;
+            const uint32_t lt = ((xy >> 16) + dy) * s_tx[pr] + (xy & 0xffffu) + dx;   // tile within the view
+            tile_out[e_beg + e] = (K)(LOCAL ? lt : s_base[pr] + lt);
             id_out[e_beg + e] = s_id[pr];
         }
         p = __shfl(pr, 63, 64);
@@ -696,25 +748,36 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
             return hipSuccess;
         }
     }
-    // 4. emission, grouped by view like the pairs; an odd number of tile
-    // passes starts from the alternate buffers so the result lands in the
-    // caller's
+    // 4. emission, grouped by view like the pairs; the tile passes are
+    // arranged so the result lands in the caller's buffers
     int bits = 1;                                   // tile id within its view
     for (int v = 0; v < vt.nviews; v++)
         while ((int64_t(1) << bits) < (int64_t)(vt.tile_base[v + 1] - vt.tile_base[v])) bits++;
     const bool odd = seg_passes(bits) & 1;
-    uint32_t *ek = odd ? ws.talt : b->tile_keys, *ei = odd ? ws.ialt : b->ids;
-    uint32_t *ak = odd ? b->tile_keys : ws.talt, *ai = odd ? b->ids : ws.ialt;
-    if (vn > 0) {
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, s,
-                           (const uint64_t *)ws.rect, n, vt,
+    const dim3 eg((unsigned)((vn + 255) / 256)), eb(256);
+    if (vn > 0 && bits <= 16) {
+        // 2-byte tile keys within the view until the last pass, which writes
+        // the global ids; both 2-byte key arrays fit in the alternate key buffer
+        uint16_t *k16a = (uint16_t *)ws.talt, *k16b = k16a + cap;
+        uint32_t *vin = odd ? ws.ialt : b->ids, *vother = odd ? b->ids : ws.ialt;
+        hipLaunchKernelGGL(emit_kernel<uint16_t>, eg, eb, 0, s, (const uint64_t *)ws.rect, n, vt,
+                           (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
+                           (const int64_t *)b->n_instances, k16a, vin, cap);
+        hipLaunchKernelGGL(instance_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const SegPlan *)ws.pplan,
+                           (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan);
+        // 5. stable sort by tile within each view
+        e = seg_tile_sort16(k16a, k16b, vin, vother, b->tile_keys, b->ids, ws.iplan, vt.nviews, cap, bits, ws.hist,
+                            (uint32_t *)ws.partial, s);
+        if (e != hipSuccess) return e;
+    } else if (vn > 0) {
+        uint32_t *ek = odd ? ws.talt : b->tile_keys, *ei = odd ? ws.ialt : b->ids;
+        uint32_t *ak = odd ? b->tile_keys : ws.talt, *ai = odd ? b->ids : ws.ialt;
+        hipLaunchKernelGGL(emit_kernel<uint32_t>, eg, eb, 0, s, (const uint64_t *)ws.rect, n, vt,
                            (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
                            (const int64_t *)b->n_instances, ek, ei, cap);
         hipLaunchKernelGGL(instance_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const SegPlan *)ws.pplan,
                            (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan);
-    }
-    // 5. stable sort by tile within each view
-    if (vn > 0) {
+        // 5. stable sort by tile within each view
         e = seg_radix_sort(ek, ei, ak, ai, ws.iplan, vt.nviews, cap, bits, ws.hist, (uint32_t *)ws.partial, s);
         if (e != hipSuccess) return e;
     }

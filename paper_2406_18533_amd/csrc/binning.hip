@@ -77,41 +77,36 @@ __global__ void __launch_bounds__(SB) scan_reduce_kernel(Load load, const int64_
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-template <typename U>
-__global__ void __launch_bounds__(SB) scan_partials_kernel(U *partial, int64_t nb, int64_t *total_out)
-{
-    int64_t per = (nb + SB - 1) / SB;
-    int64_t b0 = threadIdx.x * per;
-    U acc = 0;
-    for (int64_t j = 0; j < per; j++)
-        if (b0 + j < nb) acc += partial[b0 + j];
-    U total;
-    U run = block_excl_scan(acc, total);
-    for (int64_t j = 0; j < per; j++)
-        if (b0 + j < nb) {
-            U t = partial[b0 + j];
-            partial[b0 + j] = run;
-            run += t;
-        }
-    if (threadIdx.x == 0 && total_out) *total_out = (int64_t)total;
-}
-
 // LDS slot of item i of a 4096-item tile: one pad word per 32 items keeps
 // the per-thread (blocked) accesses off a single bank.
 __device__ __forceinline__ int pad_slot(int i) { return i + (i >> 5); }
 
-// Second pass of the scan: each block scans its tile of 4096 items and
-// stores the exclusive prefix of every item (plus the block's offset).
-// Items are loaded and stored coalesced (item j*256 + thread of the tile)
-// and transposed through LDS to the blocked order the scan needs.
+// Second pass of the scan: each block adds up the sums of the blocks before
+// it (its offset; block 0 also writes the grand total), scans its tile of
+// 4096 items and stores the exclusive prefix of every item. Items are loaded
+// and stored coalesced (item j*256 + thread of the tile) and transposed
+// through LDS to the blocked order the scan needs.
 template <typename U, typename Load, typename Store>
 __global__ void __launch_bounds__(SB) scan_down_kernel(Load load, Store store, const int64_t *n_dev, int64_t n_max,
-                                                       const U *partial)
+                                                       const U *partial, int64_t nb, int64_t *total_out)
 {
     __shared__ U sm[STILE + STILE / 32];
     int64_t n = count_of(n_dev, n_max);
     int64_t base = (int64_t)blockIdx.x * STILE;
+    if (blockIdx.x == 0 && total_out) {               // block-uniform
+        U a = 0;
+        for (int64_t j = threadIdx.x; j < nb; j += SB) a += partial[j];
+        U all;
+        block_excl_scan(a, all);
+        if (threadIdx.x == 0) *total_out = (int64_t)all;
+    }
     if (base >= n) return;
+    U boff;                                           // sum of the blocks before this one
+    {
+        U a = 0;
+        for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += SB) a += partial[j];
+        block_excl_scan(a, boff);
+    }
     for (int j = 0; j < SITEMS; j++) {
         int i = j * SB + threadIdx.x;
         sm[pad_slot(i)] = base + i < n ? load(base + i) : U(0);
@@ -124,13 +119,13 @@ __global__ void __launch_bounds__(SB) scan_down_kernel(Load load, Store store, c
         acc += vals[j];
     }
     U total;
-    U run = block_excl_scan(acc, total) + partial[blockIdx.x];   // (synchronises the block)
+    U run = block_excl_scan(acc, total) + boff;                  // (synchronises the block)
     for (int j = 0; j < SITEMS; j++) {
         sm[pad_slot(threadIdx.x * SITEMS + j)] = run;             // exclusive prefix, in place
         run += vals[j];
     }
     __syncthreads();
-    U end = partial[blockIdx.x] + total;
+    U end = boff + total;
     for (int j = 0; j < SITEMS; j++) {
         int i = j * SB + threadIdx.x;
         if (base + i >= n) break;
@@ -147,9 +142,8 @@ static hipError_t device_scan(Load load, Store store, const int64_t *n_dev, int6
     int64_t nb = (n_max + STILE - 1) / STILE;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL((scan_reduce_kernel<U, Load>), dim3((unsigned)nb), dim3(SB), 0, s, load, n_dev, n_max, partial);
-    hipLaunchKernelGGL((scan_partials_kernel<U>), dim3(1), dim3(SB), 0, s, partial, nb, total_out);
     hipLaunchKernelGGL((scan_down_kernel<U, Load, Store>), dim3((unsigned)nb), dim3(SB), 0, s, load, store, n_dev,
-                       n_max, (const U *)partial);
+                       n_max, (const U *)partial, nb, total_out);
     return hipGetLastError();
 }
 
@@ -217,35 +211,52 @@ __device__ __forceinline__ void plan_finish(SegPlan *p, int views)
 }
 
 // Pair segments: the compacted pairs are in flat (view-major) order, so view
-// v starts at the first flat index >= v n.
-__global__ void pair_plan_kernel(const uint32_t *__restrict__ flat, const int64_t *m_dev, int64_t m_max, int64_t n,
-                                 int views, SegPlan *plan)
+// v starts at the first flat index >= v n. One wavefront per view searches
+// 64-ary: its lanes sample 64 evenly spaced entries of the current interval
+// and a ballot narrows it 64-fold (four rounds for 16M pairs).
+constexpr int PLAN_NT = 1024;
+
+__global__ void __launch_bounds__(PLAN_NT) pair_plan_kernel(const uint32_t *__restrict__ flat, const int64_t *m_dev,
+                                                            int64_t m_max, int64_t n, int views, SegPlan *plan)
 {
-    const int v = threadIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t m = count_of(m_dev, m_max);
-    if (v < views) {
-        int64_t lo = 0, hi = m;                       // first j with flat[j] >= v n
+    for (int v = w; v < views; v += PLAN_NT / 64) {   // wave-uniform
         const uint64_t key = (uint64_t)v * (uint64_t)n;
+        int64_t lo = 0, hi = m;                        // the answer lies in [lo, hi]
         while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if ((uint64_t)flat[mid] < key) lo = mid + 1;
-            else hi = mid;
+            const int64_t step = (hi - lo + 63) / 64;
+            const int64_t idx = lo + lane * step;
+            const bool below = idx < hi && (uint64_t)flat[idx] < key;
+            const int c = __popcll(__ballot(below));  // samples below the key: a prefix of the lanes
+            if (c == 0) {
+                hi = lo;
+            } else {
+                const int64_t nlo = lo + (int64_t)(c - 1) * step + 1;
+                const int64_t nhi = lo + (int64_t)c * step < hi ? lo + (int64_t)c * step : hi;
+                lo = nlo;
+                hi = nhi;
+            }
         }
-        plan->start[v] = lo;
-        plan->base[v] = 0u;
+        if (lane == 0) {
+            plan->start[v] = lo;
+            plan->base[v] = 0u;
+        }
     }
-    if (v == 0) plan->start[views] = m;
+    if (threadIdx.x == 0) plan->start[views] = m;
     __syncthreads();
-    if (v == 0) plan_finish(plan, views);
+    if (threadIdx.x == 0) plan_finish(plan, views);
 }
 
 // Instance segments: view v's instances start at the offset of its first
 // pair (the emission keeps the pairs' view grouping); clipped to capacity.
 __global__ void instance_plan_kernel(const SegPlan *__restrict__ pairs, const uint64_t *__restrict__ off,
-                                     const int64_t *k_dev, int64_t cap, ViewTable vt, SegPlan *plan)
+                                     const int64_t *k_dev, int64_t cap, ViewTable vt, SegPlan *plan,
+                                     int32_t *overflow)
 {
     const int v = threadIdx.x, views = vt.nviews;
     int64_t K = *k_dev < cap ? *k_dev : cap;
+    if (v == 0) *overflow = *k_dev > cap ? 1 : 0;
     const int64_t m = pairs->start[views];
     if (v < views) {
         int64_t j = pairs->start[v];
@@ -722,7 +733,7 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
                               (uint32_t *)ws.partial, ws.m_dev, s);
     if (e != hipSuccess) return e;
     if (vn > 0)
-        hipLaunchKernelGGL(pair_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const uint32_t *)ws.v1,
+        hipLaunchKernelGGL(pair_plan_kernel, dim3(1), dim3(PLAN_NT), 0, s, (const uint32_t *)ws.v1,
                            (const int64_t *)ws.m_dev, vn, n, vt.nviews, ws.pplan);
     // 2. stable sort by FP32 depth bits within each view (4 passes: an even
     // count, so the result is back in k1 / v1)
@@ -736,7 +747,8 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
                            (const int64_t *)ws.m_dev, vn, ws.k1, ws.rect);
     e = device_scan<uint64_t>(U32AsU64Load{ws.k1}, U64Store{ws.off}, ws.m_dev, vn, ws.partial, b->n_instances, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap, b->overflow);
+    if (vn == 0)   // (otherwise the instance plan writes the flag, or the capacity check below)
+        hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap, b->overflow);
     if (check) {
         int64_t K = 0;
         e = hipMemcpyAsync(&K, b->n_instances, sizeof(int64_t), hipMemcpyDeviceToHost, s);
@@ -745,7 +757,9 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
         if (e != hipSuccess) return e;
         if (K > cap) {
             *capacity_err = 1;
-            return hipSuccess;
+            hipLaunchKernelGGL(overflow_kernel, dim3(1), dim3(1), 0, s, (const int64_t *)b->n_instances, cap,
+                               b->overflow);
+            return hipGetLastError();
         }
     }
     // 4. emission, grouped by view like the pairs; the tile passes are
@@ -764,7 +778,7 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
                            (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
                            (const int64_t *)b->n_instances, k16a, vin, cap);
         hipLaunchKernelGGL(instance_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const SegPlan *)ws.pplan,
-                           (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan);
+                           (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan, b->overflow);
         // 5. stable sort by tile within each view
         e = seg_tile_sort16(k16a, k16b, vin, vother, b->tile_keys, b->ids, ws.iplan, vt.nviews, cap, bits, ws.hist,
                             (uint32_t *)ws.partial, s);
@@ -776,7 +790,7 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
                            (const uint32_t *)ws.v1, (const uint64_t *)ws.off, (const int64_t *)ws.m_dev, vn,
                            (const int64_t *)b->n_instances, ek, ei, cap);
         hipLaunchKernelGGL(instance_plan_kernel, dim3(1), dim3(MAXV), 0, s, (const SegPlan *)ws.pplan,
-                           (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan);
+                           (const uint64_t *)ws.off, (const int64_t *)b->n_instances, cap, vt, ws.iplan, b->overflow);
         // 5. stable sort by tile within each view
         e = seg_radix_sort(ek, ei, ak, ai, ws.iplan, vt.nviews, cap, bits, ws.hist, (uint32_t *)ws.partial, s);
         if (e != hipSuccess) return e;

@@ -381,26 +381,22 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
     const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
     for (int v = 0; v < views; v++)
         if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
-    if (!vis) {
-        if (ADAM) {                                   // seen by no view: Adam with a zero gradient
-            const T zero[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-            adam_row_block<T, 3>(P, ad, 0, n, i, zero);
-            asm volatile("" ::: "memory");
-            adam_row_block<T, 8>(P, ad, 3, n, i, zero);
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                adam_row_block<T, 12>(P, ad, 11 + 12 * b, n, i, zero);
-                asm volatile("" ::: "memory");
-            }
-        }
-        return;
+    // Gaussians seen by no view have nothing to add and, with ADAM, take the
+    // step with a zero gradient. Seen and unseen Gaussians share wavefronts
+    // (visibility is scattered over the index range), so the gradients are
+    // formed under `seen` and every Adam block below runs once for all lanes.
+    const bool seen = vis != 0;
+    if (!ADAM && !seen) return;
+    T x[3] = {T(0), T(0), T(0)};
+    if (seen) {
+        x[0] = P[i];
+        x[1] = P[n + i];
+        x[2] = P[2 * n + i];
     }
-    T x[3] = {P[i], P[n + i], P[2 * n + i]};
-    T gpos[3];
+    T gpos[3] = {T(0), T(0), T(0)};
     {
-        T g8[8];
-        geom_grads(P, n, i, x, cams, views, vis, dproj, gpos, g8);
+        T g8[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+        if (seen) geom_grads(P, n, i, x, cams, views, vis, dproj, gpos, g8);
         if (!ADAM) {
             for (int r = 0; r < 8; r++) grad[(3 + r) * n + i] += g8[r];
         } else {
@@ -409,39 +405,41 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
         }
     }
     asm volatile("" ::: "memory");
-    T sh[3][16], gsh[3][16];
+    T gsh[3][16];
     for (int k2 = 0; k2 < 16; k2++)
-        for (int c = 0; c < 3; c++) {
-            sh[c][k2] = P[(11 + 3 * k2 + c) * n + i];
-            gsh[c][k2] = T(0);
-        }
+        for (int c = 0; c < 3; c++) gsh[c][k2] = T(0);
     T gmean[3] = {0, 0, 0};
-    for (int v = 0; v < views; v++) {
-        if (!((vis >> v) & 1ull)) continue;
-        const T *dr = dproj + ((int64_t)v * n + i) * REC;
-        T drgb[3] = {dr[D_RGB], dr[D_RGB + 1], dr[D_RGB + 2]};
-        const gs_camera *cm = cams + v;
-        T cen[3];
-        for (int j = 0; j < 3; j++)
-            cen[j] = (T)(-(cm->R[j] * cm->t[0] + cm->R[3 + j] * cm->t[1] + cm->R[6 + j] * cm->t[2]));
-        T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
-        T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
-        T Y[16];
-        sh_basis(dir[0], dir[1], dir[2], Y);
-        T raw[3] = {T(0), T(0), T(0)};   // each summed in the forward's order, so the clamp mask agrees
+    if (seen) {
+        T sh[3][16];
         for (int k2 = 0; k2 < 16; k2++)
-            for (int c = 0; c < 3; c++) raw[c] += sh[c][k2] * Y[k2];
-        T a[3];                          // dL/drgb of the unclamped channels, 0 for clamped ones
-        for (int c = 0; c < 3; c++) a[c] = raw[c] + T(0.5) > T(0) ? drgb[c] : T(0);
-        if (!(raw[0] + T(0.5) > T(0)) && !(raw[1] + T(0.5) > T(0)) && !(raw[2] + T(0.5) > T(0))) continue;
-        for (int k2 = 0; k2 < 16; k2++)
-            for (int c = 0; c < 3; c++) gsh[c][k2] = fma(a[c], Y[k2], gsh[c][k2]);
-        T gd[3];
-        sh_grad(dir[0], dir[1], dir[2], [&](int k2) { return fma(a[2], sh[2][k2], fma(a[1], sh[1][k2], a[0] * sh[0][k2])); },
-                gd);
-        T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
-        for (int j = 0; j < 3; j++) gmean[j] += (gd[j] - dir[j] * dd) * idn;
+            for (int c = 0; c < 3; c++) sh[c][k2] = P[(11 + 3 * k2 + c) * n + i];
+        for (int v = 0; v < views; v++) {
+            if (!((vis >> v) & 1ull)) continue;
+            const T *dr = dproj + ((int64_t)v * n + i) * REC;
+            T drgb[3] = {dr[D_RGB], dr[D_RGB + 1], dr[D_RGB + 2]};
+            const gs_camera *cm = cams + v;
+            T cen[3];
+            for (int j = 0; j < 3; j++)
+                cen[j] = (T)(-(cm->R[j] * cm->t[0] + cm->R[3 + j] * cm->t[1] + cm->R[6 + j] * cm->t[2]));
+            T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
+            T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
+            T Y[16];
+            sh_basis(dir[0], dir[1], dir[2], Y);
+            T raw[3] = {T(0), T(0), T(0)};   // each summed in the forward's order, so the clamp mask agrees
+            for (int k2 = 0; k2 < 16; k2++)
+                for (int c = 0; c < 3; c++) raw[c] += sh[c][k2] * Y[k2];
+            T a[3];                          // dL/drgb of the unclamped channels, 0 for clamped ones
+            for (int c = 0; c < 3; c++) a[c] = raw[c] + T(0.5) > T(0) ? drgb[c] : T(0);
+            if (!(raw[0] + T(0.5) > T(0)) && !(raw[1] + T(0.5) > T(0)) && !(raw[2] + T(0.5) > T(0))) continue;
+            for (int k2 = 0; k2 < 16; k2++)
+                for (int c = 0; c < 3; c++) gsh[c][k2] = fma(a[c], Y[k2], gsh[c][k2]);
+            T gd[3];
+            sh_grad(dir[0], dir[1], dir[2], [&](int k2) { return fma(a[2], sh[2][k2], fma(a[1], sh[1][k2], a[0] * sh[0][k2])); },
+                    gd);
+            T dd = gd[0] * dir[0] + gd[1] * dir[1] + gd[2] * dir[2];
+            for (int j = 0; j < 3; j++) gmean[j] += (gd[j] - dir[j] * dd) * idn;
+        }
     }
     if (!ADAM) {
         for (int k2 = 0; k2 < 16; k2++)

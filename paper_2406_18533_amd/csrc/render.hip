@@ -58,12 +58,15 @@ template <typename T> struct BwdArgs {
     T *dproj;
 };
 
-template <typename T, int CHUNK> struct Stage {
-    V4<T> a[CHUNK];    // u, v, r^2, opacity
-    V4<T> b[CHUNK];    // conic a, b, c, -
-    V4<T> c[CHUNK];    // r, g, b, -
-    V4<T> d[CHUNK];    // scaled conic na, nb, nc (see scaled_conic), -
-    uint32_t id[CHUNK];
+// BWD: the backward also needs the raw conic and the Gaussian index; the
+// forward leaves them out, which keeps its LDS per workgroup small enough
+// for eight workgroups of one wavefront per SIMD.
+template <typename T, int CHUNK, bool BWD> struct Stage {
+    V4<T> a[CHUNK];               // u, v, r^2, opacity
+    V4<T> b[BWD ? CHUNK : 1];     // conic a, b, c, -
+    V4<T> c[CHUNK];               // r, g, b, -
+    V4<T> d[CHUNK];               // scaled conic na, nb, nc (see scaled_conic), -
+    uint32_t id[BWD ? CHUNK : 1];
     uint32_t pos[CHUNK];   // position of the record in the tile's list
     uint32_t band[CHUNK];  // bit k: the record may touch pixel rows 4k..4k+3 of the tile
     uint32_t wcnt[4];
@@ -167,8 +170,8 @@ __device__ __forceinline__ void fetch_records(Fetched<T, CHUNK, NT> &f, const T 
 // returns how many were kept. A band is exactly one wavefront's pixels in
 // every launch shape, so the render loops skip a band with a wave-uniform
 // branch.
-template <typename T, int CHUNK, int NT>
-__device__ __forceinline__ int commit_records(Stage<T, CHUNK> &st, const Fetched<T, CHUNK, NT> &f, T bx0, T by0)
+template <typename T, int CHUNK, int NT, bool BWD>
+__device__ __forceinline__ int commit_records(Stage<T, CHUNK, BWD> &st, const Fetched<T, CHUNK, NT> &f, T bx0, T by0)
 {
     constexpr int NW = NT / 64;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -214,10 +217,10 @@ __device__ __forceinline__ int commit_records(Stage<T, CHUNK> &st, const Fetched
             T na, nb, nc;
             scaled_conic(sb.x, sb.y, sb.z, na, nb, nc);
             st.a[slot] = sa;
-            st.b[slot] = sb;
+            if constexpr (BWD) st.b[slot] = sb;
             st.c[slot] = sc;
             st.d[slot] = V4<T>{na, nb, nc, T(0)};
-            st.id[slot] = f.id[rr];
+            if constexpr (BWD) st.id[slot] = f.id[rr];
             st.pos[slot] = f.pos0 + (uint32_t)q;
             st.band[slot] = bands;
         }
@@ -227,7 +230,8 @@ __device__ __forceinline__ int commit_records(Stage<T, CHUNK> &st, const Fetched
 
 // ------------------------------------------------------------------ forward tile
 template <typename T, int PX, int CHUNK, bool STATS>
-__device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
+__device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, Stage<T, CHUNK, false> &st,
+                         uint32_t *s_red)
 {
     uint32_t n_eval = 0, n_blend = 0;
     const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -369,7 +373,8 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
 
 // ------------------------------------------------------------------ backward tile
 template <typename T, int PX, int CHUNK>
-__device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, Stage<T, CHUNK> &st, uint32_t *s_red)
+__device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, Stage<T, CHUNK, true> &st,
+                         uint32_t *s_red)
 {
     constexpr int NT = 256 / PX;
     int v = view_of_tile(vt, g);
@@ -524,9 +529,9 @@ __device__ __forceinline__ int32_t claim(const SchedState &S, int &qi, int32_t *
 }
 
 template <typename T, int PX, int CHUNK, bool STATS>
-__global__ void __launch_bounds__(256 / PX) render_fwd_kernel(ViewTable vt, FwdArgs<T> A)
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(7))) render_fwd_kernel(ViewTable vt, FwdArgs<T> A)
 {
-    __shared__ Stage<T, CHUNK> st;
+    __shared__ Stage<T, CHUNK, false> st;
     __shared__ uint32_t s_red;
     int32_t g = per_tile_index(blockIdx.x, vt.total_tiles);
     if (g >= vt.total_tiles) return;
@@ -536,7 +541,7 @@ __global__ void __launch_bounds__(256 / PX) render_fwd_kernel(ViewTable vt, FwdA
 template <typename T, int PX, int CHUNK, bool STATS>
 __global__ void __launch_bounds__(256 / PX) render_fwd_persistent(ViewTable vt, FwdArgs<T> A, SchedState S)
 {
-    __shared__ Stage<T, CHUNK> st;
+    __shared__ Stage<T, CHUNK, false> st;
     __shared__ uint32_t s_red;
     __shared__ int32_t s_item;
     int qi = 0;
@@ -551,7 +556,7 @@ template <typename T, int PX, int CHUNK>
 __global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(6)))
 render_bwd_kernel(ViewTable vt, BwdArgs<T> A)
 {
-    __shared__ Stage<T, CHUNK> st;
+    __shared__ Stage<T, CHUNK, true> st;
     __shared__ uint32_t s_red;
     int32_t g = per_tile_index(blockIdx.x, vt.total_tiles);
     if (g >= vt.total_tiles) return;
@@ -561,7 +566,7 @@ render_bwd_kernel(ViewTable vt, BwdArgs<T> A)
 template <typename T, int PX, int CHUNK>
 __global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, BwdArgs<T> A, SchedState S)
 {
-    __shared__ Stage<T, CHUNK> st;
+    __shared__ Stage<T, CHUNK, true> st;
     __shared__ uint32_t s_red;
     __shared__ int32_t s_item;
     int qi = 0;

@@ -135,16 +135,17 @@ def algorithmic(c: dict) -> dict:
     FP32 flops it must execute), per launch, from the exact counts."""
     VN, M, K, T, Pn = c["V"] * c["N"], c["records_on_screen"], c["K"], c["tiles"], c["pixels"]
     N, Ns = c["N"], c["gaussians_on_screen"]
-    radix_passes_depth, radix_passes_tile = 4, 2
+    radix_passes_depth = 4
     return {
         # read means of all, the other 224 B of Gaussians on screen; write a 48-B record per on-screen
         # (view, Gaussian) and a 4-B "no tiles" marker for the rest
         "gs_project": ("hbm", 12 * N + 224 * Ns + 48 * M + 4 * (VN - M)),
         # compaction (4 B flag + 4 B depth in, 8 B out per pair), 4 depth passes over pairs (20 B each),
-        # offsets (16 B per pair), emission (20 B per pair + 8 B per instance), 2 tile passes over
-        # instances (20 B each), ranges (4 B per instance + 8 B per tile)
-        "gs_bin_sort": ("hbm", 4 * VN + 12 * M + radix_passes_depth * 20 * M + 16 * M + 20 * M + 8 * K
-                        + radix_passes_tile * 20 * K + 4 * K + 8 * T),
+        # offsets (16 B per pair), emission (20 B per pair + a 2-B tile key and 4-B id per instance),
+        # 2 tile passes over instances (2-B key counted, then 2+4 B read and written: 14 B; the last
+        # pass writes the 4-B global tile ids: 16 B), ranges (4 B per instance + 8 B per tile)
+        "gs_bin_sort": ("hbm", 4 * VN + 12 * M + radix_passes_depth * 20 * M + 16 * M + 20 * M + 6 * K
+                        + 14 * K + 16 * K + 4 * K + 8 * T),
         # 17 flops to evaluate a pair (offset, circle, quadratic form, exp, opacity), 9 more to blend it
         "gs_render_fwd": ("alu", 17 * c["pairs_evaluated_fwd"] + 9 * c["pairs_blended"]),
         # the same, with the L1 loss and its gradient (a few flops per pixel channel) in the output stage

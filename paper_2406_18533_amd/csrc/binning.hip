@@ -9,10 +9,11 @@
 //      keeping (view-major, index) order;
 //   2. stable radix sort of each view's pairs by FP32 depth bits (4 passes);
 //   3. exclusive scan of their tile counts in that order -> instance offsets;
-//   4. emit (global tile id, Gaussian index) per tile of each pair's rectangle
+//   4. emit (tile, Gaussian index) per tile of each pair's rectangle
 //      (grouped by view, since the pairs are);
 //   5. stable radix sort of each view's instances by tile within the view
-//      (13 bits, two passes, for a 1920x1080 view).
+//      (13 bits, two passes, for a 1920x1080 view; 2-byte keys while a view
+//      has at most 2^16 tiles, the last pass writing the global tile ids).
 // Stability of step 5 keeps step 2's (depth, index) order inside each tile.
 // Only step 5 runs over the duplicated instances, so the wide depth digits
 // cost passes over the pairs, not over the (typically 5-10x larger)
@@ -185,7 +186,8 @@ struct U32Store {
 };
 
 // ---------------------------------------------------------------- radix sort
-// View-segmented stable LSD radix sort of 32-bit keys with 32-bit values.
+// View-segmented stable LSD radix sort of 32-bit (or, for tiles, 16-bit)
+// keys with 32-bit values.
 // The items of view v occupy [start[v], start[v + 1]) and a pass orders each
 // view's items among themselves, by a digit of (key - base[v]): the views
 // stay where they are. A block owns one 4096-item tile of one view (view v

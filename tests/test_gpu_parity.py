@@ -130,6 +130,35 @@ def test_bin_sort_bit_exact(name):
     assert (ranges_g == ranges_o).all()
 
 
+def wide_views(w: int, h: int):
+    """A view of w x h pixels beside a small one: with more than 2^16 tiles
+    in the view the tile sort runs on 4-byte keys (three passes for 2^18
+    tiles), with exactly 2^16 on 2-byte keys at their limit."""
+    P = scenes.uniform_cube_gaussians(20_000, 9)
+    cams = [scenes.orbit_camera(w, h, 3.0, 0.7, 0.3), scenes.orbit_camera(96, 64, 3.5, 2.5, 0.4)]
+    return P, cams
+
+
+@pytest.mark.parametrize("w,h", [(4096, 4096), (8192, 4608)])
+def test_bin_sort_bit_exact_many_tiles_per_view(w, h):
+    gp = _gp()
+    P, cams = wide_views(w, h)
+    assert oracle.tile_base(cams)[1] == ((w + 15) // 16) * ((h + 15) // 16)
+    f = gp.forward(gp.to_dev(P), cams, BG)
+    pf = gp.proj_fields(f["proj"])
+    r = np.where(pf["radius"] > 0, pf["radius"], 0).astype(np.float32)
+    keys_o, ids_o, ranges_o = oracle.bin_sort(pf["u"], pf["v"], r, pf["depth"], cams)
+    keys_g, ids_g, ranges_g = gp.bins_numpy(f)
+    assert keys_g.shape == keys_o.shape and keys_o.size > 100_000
+    hi = oracle.tile_base(cams)[1]
+    tile = keys_o >> np.uint64(32)
+    big = tile[tile < hi]                  # the large view's tiles: past 2^16, or in the top half of 2^16
+    assert int(big.max()) >= (65_536 if hi > 65_536 else 32_768)
+    assert (keys_g == keys_o).all()
+    assert (ids_g == ids_o).all()
+    assert (ranges_g == ranges_o).all()
+
+
 # ----------------------------------------------------------------------------- render forward
 def _render_parity(f, P, cams, gp):
     pf = gp.proj_fields(f["proj"])

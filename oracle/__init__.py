@@ -218,6 +218,84 @@ def l1_loss(images: list, targets: list):
     return loss, grads
 
 
+# ----------------------------------------------------------------------------- L1 + D-SSIM loss
+# The loss step of the paper's background section (step 3: L1 and SSIM over
+# pixel windows). Readings: SSIM per colour channel with an 11x11 Gaussian
+# window of standard deviation 1.5 (normalised), zero padding outside the
+# image, C1 = 0.01^2, C2 = 0.03^2, averaged over the 3HW values of a view;
+# loss of a view = (1 - lam) L1 + lam (1 - SSIM), lam = 0.2; batch loss =
+# mean over the views.
+SSIM_WIN, SSIM_SIGMA, SSIM_C1, SSIM_C2 = 11, 1.5, 0.01 ** 2, 0.03 ** 2
+
+
+def ssim_window_1d() -> np.ndarray:
+    k = np.arange(SSIM_WIN, dtype=np.float64) - SSIM_WIN // 2
+    g = np.exp(-k * k / (2.0 * SSIM_SIGMA ** 2))
+    return g / g.sum()
+
+
+def _filter(img: np.ndarray) -> np.ndarray:
+    """Window-weighted sum around every pixel of an [H, W] image, zero
+    outside: out[y, x] = sum_ij g[i] g[j] img[y + i - 5, x + j - 5] (the
+    2-D window is the outer product, so rows then columns)."""
+    g, r = ssim_window_1d(), SSIM_WIN // 2
+    H, W = img.shape
+    pad = np.zeros((H + 2 * r, W + 2 * r))
+    pad[r:r + H, r:r + W] = img
+    rows = sum(g[j] * pad[:, j:j + W] for j in range(SSIM_WIN))      # [H + 2r, W]
+    return sum(g[i] * rows[i:i + H, :] for i in range(SSIM_WIN))     # [H, W]
+
+
+def ssim_map(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Per-pixel SSIM of two [H, W] images."""
+    mx, my = _filter(x), _filter(y)
+    sxx = _filter(x * x) - mx * mx
+    syy = _filter(y * y) - my * my
+    sxy = _filter(x * y) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def ssim_grad(x: np.ndarray, y: np.ndarray, dS: np.ndarray) -> np.ndarray:
+    """Gradient with respect to x of sum_p dS[p] SSIM[p]. SSIM depends on x
+    through the filtered mean m = G x, the filtered square e = G x^2 and the
+    filtered product f = G (x y) (with var = e - m^2, cov = f - m my); the
+    filter is symmetric with zero padding, so its adjoint is itself and
+    d/dx = G(dS dS/dm) + 2 x G(dS dS/de) + y G(dS dS/df)."""
+    mx, my = _filter(x), _filter(y)
+    sxx = _filter(x * x) - mx * mx
+    syy = _filter(y * y) - my * my
+    sxy = _filter(x * y) - mx * my
+    A = 2 * mx * my + SSIM_C1
+    B = 2 * sxy + SSIM_C2
+    Cm = mx * mx + my * my + SSIM_C1
+    D = sxx + syy + SSIM_C2
+    S = A * B / (Cm * D)
+    dS_dmx = 2 * my * B / (Cm * D) - S * 2 * mx / Cm      # through the means' terms only
+    dS_dvar = -S / D
+    dS_dcov = 2 * A / (Cm * D)
+    d_m = dS * (dS_dmx + dS_dvar * (-2 * mx) + dS_dcov * (-my))
+    d_e = dS * dS_dvar
+    d_f = dS * dS_dcov
+    return _filter(d_m) + 2 * x * _filter(d_e) + y * _filter(d_f)
+
+
+def l1_dssim_loss(images: list, targets: list, lam: float = 0.2):
+    """Batch loss mean_v [(1 - lam) mean|x - y| + lam (1 - mean SSIM)] over
+    the views' [3, H, W] images, and dL/dimage per view (sign(0) = 0)."""
+    V = len(images)
+    loss, grads = 0.0, []
+    for im, tg in zip(images, targets):
+        x, y = _f64(im), _f64(tg)
+        n = x.size
+        d = x - y
+        S = np.stack([ssim_map(x[c], y[c]) for c in range(x.shape[0])])
+        loss += ((1 - lam) * np.abs(d).mean() + lam * (1 - S.mean())) / V
+        w = -lam / (n * V)                                 # dL/dSSIM[p] for every pixel and channel
+        g = np.stack([ssim_grad(x[c], y[c], np.full(x.shape[1:], w)) for c in range(x.shape[0])])
+        grads.append((1 - lam) * np.sign(d) / (n * V) + g)
+    return loss, grads
+
+
 # ----------------------------------------------------------------------------- pipelines
 def rounded_for_binning(proj: np.ndarray):
     """FP32 copies of (u, v, radius, depth): binning decides in FP32."""

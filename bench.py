@@ -106,6 +106,46 @@ def entry_timings(tr, reps: int):
     return {k: v / reps for k, v in acc.items()}
 
 
+def dssim_side(tr, P, cams_list, targets, steps: int, warmup: int, lam: float = 0.2):
+    """The L1 + D-SSIM loss: its entry's average time on the step's rendered
+    images (HIP events) against the HBM roofline of its algorithmic bytes
+    (44 per image value: the forward reads both images and writes three
+    coefficient maps, the backward reads the maps and both images and writes
+    the gradient), and the whole step with that loss in place of L1."""
+    import dataclasses
+    import torch
+    from paper_2406_18533_amd import raster as R
+    from paper_2406_18533_amd import train
+    buf = R.DssimBuffers(tr.cams)
+    R.gs_loss_l1_dssim(tr.rgb, tr.targets, tr.cams, buf, lam=lam)
+    reps = 10
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        R.gs_loss_l1_dssim(tr.rgb, tr.targets, tr.cams, buf, lam=lam)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    nbytes = 44 * 3 * tr.cams.total_pixels()
+    gbs = nbytes / (ms / 1e3) / 1e9
+    del buf
+    t2 = train.BatchedTrainer(P.clone(), cams_list, targets, dataclasses.replace(tr.cfg, ssim_lambda=lam))
+    for _ in range(max(warmup, 1)):
+        t2.step()
+        t2.check_overflow()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t2.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = {"lambda": lam, "views_per_s": round(t2.V * steps / (t1 - t0), 2),
+           "ms_per_step": round((t1 - t0) * 1e3 / steps, 4), "loss_ms": round(ms, 4),
+           "loss_bytes": nbytes, "loss_GBps": round(gbs, 1), "loss_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del t2
+    return out
+
+
 def workload_counts(tr):
     """Exact counts of the step's work units, for the algorithmic bytes/flops."""
     import torch
@@ -379,6 +419,7 @@ def main():
     ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-aerial", action="store_true")
+    ap.add_argument("--no-dssim", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="end with a fill and a copy of this many MiB (calibration for HBM byte counters)")
@@ -429,6 +470,11 @@ def main():
     counts = workload_counts(tr)
     roof, per = roofline(timings, counts)
     log(f"timings {json.dumps(timings)}")
+    dssim = None
+    if not args.no_dssim:
+        log("step with the L1 + D-SSIM loss")
+        dssim = dssim_side(tr, P, w.cameras, targets, args.steps, args.warmup)
+        log(f"l1+dssim {json.dumps(dssim)}")
     plain = None
     if not args.no_plain:
         log("plain per-view path")
@@ -482,6 +528,7 @@ def main():
         "plain_path": plain,
         "speedup_vs_plain": round(views_s / plain["views_per_s"], 3) if plain else None,
         "aerial_4k": aerial,
+        "l1_dssim": dssim,
         "serving": serving,
         "roofline": roof,
         "per_kernel": per,

@@ -143,6 +143,10 @@ int64_t gs_total_pixels(const gs_camera *cams_host, int32_t views);
 size_t gs_bin_workspace_bytes(int64_t n, int32_t views, int64_t capacity, int64_t total_tiles);
 size_t gs_sched_workspace_bytes(int64_t total_tiles, int32_t queues);
 size_t gs_loss_workspace_bytes(const gs_camera *cams_host, int32_t views);
+/* Workspace of gs_loss_l1_dssim: three coefficient maps of 3 H W scalars
+ * per view (dtype), then one double per (tile, channel) and 64 more. 0
+ * (with gs_last_error set) when a camera or the dtype is rejected. */
+size_t gs_loss_dssim_workspace_bytes(gs_dtype dtype, const gs_camera *cams_host, int32_t views);
 
 /* ------------------------------------------------------------------ forward */
 /* Gaussian transformation (section 2.1, step 1): for every view v and
@@ -250,6 +254,27 @@ gs_status gs_project_bwd(gs_dtype dtype, const void *params, int64_t n, const gs
 gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host,
                      int32_t views, double scale, void *dL_drgb, double *loss_dev, void *workspace,
                      size_t workspace_bytes, void *stream);
+
+/* Loss (section 2.1 step 3, both terms: L1 per pixel and SSIM over pixel
+ * windows): per view, over its 3 H W values,
+ *   loss_v = (1 - lam) mean |rgb - target| + lam (1 - mean SSIM),
+ * SSIM computed per colour channel over an 11x11 Gaussian window of standard
+ * deviation 1.5 (normalised), zero padding outside the image, C1 = 0.01^2,
+ * C2 = 0.03^2: SSIM = (2 mx my + C1)(2 cov + C2) / ((mx^2 + my^2 + C1)
+ * (var_x + var_y + C2)) from the window's means, variances and covariance.
+ * *loss_dev = (scale / views) sum_v loss_v (one double, device; summed per
+ * 16x16 tile and channel, then over those in a fixed order: deterministic).
+ * dL_drgb (like rgb) = the exact gradient of that loss with respect to rgb
+ * (sign(0) = 0 for the L1 part). lam in [0, 1]. The paper names the two
+ * terms but not their weight, window or constants; the values above and
+ * lam = 0.2 are those of the original 3D Gaussian splatting loss. rgb/target: [3][H][W] per view, views concatenated; values are not
+ * clamped. workspace: gs_loss_dssim_workspace_bytes; its contents on return
+ * are scratch. The gradient is written by a second pass over coefficient
+ * maps the first pass leaves in the workspace, so dL_drgb must not alias
+ * rgb or target. */
+gs_status gs_loss_l1_dssim(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host,
+                           int32_t views, double lam, double scale, void *dL_drgb, double *loss_dev,
+                           void *workspace, size_t workspace_bytes, void *stream);
 
 /* Render forward with the L1 loss fused into its output stage: everything
  * gs_render_fwd writes (without pair_stats), plus dL_drgb exactly as

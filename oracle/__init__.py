@@ -279,9 +279,10 @@ def ssim_grad(x: np.ndarray, y: np.ndarray, dS: np.ndarray) -> np.ndarray:
     return _filter(d_m) + 2 * x * _filter(d_e) + y * _filter(d_f)
 
 
-def l1_dssim_loss(images: list, targets: list, lam: float = 0.2):
+def l1_dssim_loss(images: list, targets: list, lam: float = 0.2, with_grad: bool = True):
     """Batch loss mean_v [(1 - lam) mean|x - y| + lam (1 - mean SSIM)] over
-    the views' [3, H, W] images, and dL/dimage per view (sign(0) = 0)."""
+    the views' [3, H, W] images, and dL/dimage per view (sign(0) = 0; None
+    per view when with_grad is false)."""
     V = len(images)
     loss, grads = 0.0, []
     for im, tg in zip(images, targets):
@@ -290,6 +291,9 @@ def l1_dssim_loss(images: list, targets: list, lam: float = 0.2):
         d = x - y
         S = np.stack([ssim_map(x[c], y[c]) for c in range(x.shape[0])])
         loss += ((1 - lam) * np.abs(d).mean() + lam * (1 - S.mean())) / V
+        if not with_grad:
+            grads.append(None)
+            continue
         w = -lam / (n * V)                                 # dL/dSSIM[p] for every pixel and channel
         g = np.stack([ssim_grad(x[c], y[c], np.full(x.shape[1:], w)) for c in range(x.shape[0])])
         grads.append((1 - lam) * np.sign(d) / (n * V) + g)

@@ -15,9 +15,10 @@ GS_MAX_VIEWS = 64
 
 EXPORTS = [
     "gs_version", "gs_last_error", "gs_init", "gs_projected_bytes", "gs_total_tiles", "gs_total_pixels",
-    "gs_bin_workspace_bytes", "gs_sched_workspace_bytes", "gs_loss_workspace_bytes", "gs_project",
+    "gs_bin_workspace_bytes", "gs_sched_workspace_bytes", "gs_loss_workspace_bytes",
+    "gs_loss_dssim_workspace_bytes", "gs_project",
     "gs_bin_sort", "gs_bins_keys64", "gs_render_fwd", "gs_render_bwd", "gs_render_bwd_pixels", "gs_project_bwd",
-    "gs_loss_l1", "gs_render_fwd_l1", "gs_adam_step", "gs_project_bwd_adam", "gs_sched_plan",
+    "gs_loss_l1", "gs_loss_l1_dssim", "gs_render_fwd_l1", "gs_adam_step", "gs_project_bwd_adam", "gs_sched_plan",
 ]
 
 
@@ -74,6 +75,7 @@ def load() -> C.CDLL:
         "gs_bin_workspace_bytes": ([i64, i32, i64, i64], sz),
         "gs_sched_workspace_bytes": ([i64, i32], sz),
         "gs_loss_workspace_bytes": ([cam_p, i32], sz),
+        "gs_loss_dssim_workspace_bytes": ([i32, cam_p, i32], sz),
         "gs_project": ([i32, p, i64, p, cam_p, i32, p, p], i32),
         "gs_bin_sort": ([i32, p, i64, cam_p, i32, C.POINTER(GsBins), i32, p], i32),
         "gs_bins_keys64": ([i32, p, i64, cam_p, i32, C.POINTER(GsBins), p, p], i32),
@@ -87,6 +89,7 @@ def load() -> C.CDLL:
                                   C.POINTER(GsSched), p, p, p, p, p], i32),
         "gs_project_bwd": ([i32, p, i64, p, cam_p, i32, p, p, i32, p, p], i32),
         "gs_loss_l1": ([i32, p, p, cam_p, i32, C.c_double, p, p, p, sz, p], i32),
+        "gs_loss_l1_dssim": ([i32, p, p, cam_p, i32, C.c_double, C.c_double, p, p, p, sz, p], i32),
         "gs_adam_step": ([i32, p, p, p, p, i64, C.POINTER(GsAdamHparams), p, p, p, p], i32),
         "gs_project_bwd_adam": ([i32, p, i64, p, cam_p, i32, p, p, p, p, p, C.POINTER(GsAdamHparams), p, p, p, p],
                                 i32),

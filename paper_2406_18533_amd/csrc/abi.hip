@@ -36,6 +36,10 @@ hipError_t launch_adam(void *, void *, void *, void *, int64_t, const gs_adam_hp
 template <typename T>
 hipError_t launch_l1(const void *, const void *, const ViewTable &, double, void *, double *, void *, hipStream_t);
 size_t loss_ws_bytes(int32_t views);
+template <typename T>
+hipError_t launch_l1_dssim(const void *, const void *, const ViewTable &, double, double, void *, double *, void *,
+                           hipStream_t);
+size_t dssim_ws_bytes(const ViewTable &vt, size_t elem);
 
 ViewTable make_view_table(const gs_camera *cams, int32_t views)
 {
@@ -193,6 +197,20 @@ size_t gs_loss_workspace_bytes(const gs_camera *cams, int32_t views)
     size_t tiles = ((size_t)make_view_table(cams, views).total_tiles + LOSS_SUM_BLOCKS) * sizeof(double);   // gs_render_fwd_l1
     size_t ws = loss_ws_bytes(views);
     return ws > tiles ? ws : tiles;
+}
+
+size_t gs_loss_dssim_workspace_bytes(gs_dtype dtype, const gs_camera *cams, int32_t views)
+{
+    std::string why;
+    if (!dtype_ok(dtype)) {
+        fail(GS_ERR_ARG, "bad dtype");
+        return 0;
+    }
+    if (!cams_ok(cams, views, why)) {
+        fail(GS_ERR_ARG, why);
+        return 0;
+    }
+    return dssim_ws_bytes(make_view_table(cams, views), dtype == GS_F32 ? sizeof(float) : sizeof(double));
 }
 
 gs_status gs_project(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
@@ -439,6 +457,28 @@ gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const 
     hipError_t e = dtype == GS_F32 ? launch_l1<float>(rgb, target, vt, scale, dL_drgb, loss_dev, workspace, s)
                                    : launch_l1<double>(rgb, target, vt, scale, dL_drgb, loss_dev, workspace, s);
     return hip_status(e, "gs_loss_l1");
+}
+
+gs_status gs_loss_l1_dssim(gs_dtype dtype, const void *rgb, const void *target, const gs_camera *cams_host,
+                           int32_t views, double lam, double scale, void *dL_drgb, double *loss_dev, void *workspace,
+                           size_t workspace_bytes, void *stream)
+{
+    std::string why;
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    CHECK_ARG(rgb && target && dL_drgb && loss_dev && workspace, "null pointer");
+    CHECK_ARG(dL_drgb != rgb && dL_drgb != target, "dL_drgb aliases an input");
+    CHECK_ARG(isfinite(scale), "bad scale");
+    CHECK_ARG(lam >= 0.0 && lam <= 1.0, "lam outside [0, 1]");
+    ViewTable vt = make_view_table(cams_host, views);
+    const size_t elem = dtype == GS_F32 ? sizeof(float) : sizeof(double);
+    CHECK_ARG(workspace_bytes >= dssim_ws_bytes(vt, elem), "loss workspace too small");
+    CHECK_ARG(((uintptr_t)workspace & 7) == 0, "workspace not 8-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32
+                       ? launch_l1_dssim<float>(rgb, target, vt, lam, scale, dL_drgb, loss_dev, workspace, s)
+                       : launch_l1_dssim<double>(rgb, target, vt, lam, scale, dL_drgb, loss_dev, workspace, s);
+    return hip_status(e, "gs_loss_l1_dssim");
 }
 
 gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *v, int64_t n,

@@ -55,6 +55,10 @@ struct ViewTable {
 
 ViewTable make_view_table(const gs_camera *cams, int32_t views);
 
+// Deterministic sum of n per-tile loss shares into *loss: LOSS_SUM_BLOCKS
+// block sums (written to bsum) in a fixed order, then one fixed tree.
+hipError_t launch_tile_sum(const double *part, int64_t n, double *bsum, double *loss, hipStream_t s);
+
 // Persistent-scheduler state inside the caller's workspace.
 struct SchedState {
     int32_t *cursor;   // [queues] next tile of each queue

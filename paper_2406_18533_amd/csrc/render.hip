@@ -621,6 +621,13 @@ __global__ void __launch_bounds__(64) loss_tiles_final_kernel(const double *__re
     if (threadIdx.x == 0) *loss = a;
 }
 
+hipError_t launch_tile_sum(const double *part, int64_t n, double *bsum, double *loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(loss_tiles_part_kernel, dim3(LOSS_SUM_BLOCKS), dim3(256), 0, s, part, n, bsum);
+    hipLaunchKernelGGL(loss_tiles_final_kernel, dim3(1), dim3(64), 0, s, (const double *)bsum, loss);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, const gs_bins *b, const float *bg,
                              const LaunchShape &sh, void *rgb, void *finalT, uint32_t *last, uint32_t *wf,
@@ -660,12 +667,7 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     }
 #undef GS_FWD
 #undef GS_FWD_S
-    if (target) {
-        double *bsum = loss_tiles + vt.total_tiles;
-        hipLaunchKernelGGL(loss_tiles_part_kernel, dim3(LOSS_SUM_BLOCKS), dim3(256), 0, s, (const double *)loss_tiles,
-                           (int64_t)vt.total_tiles, bsum);
-        hipLaunchKernelGGL(loss_tiles_final_kernel, dim3(1), dim3(64), 0, s, (const double *)bsum, loss);
-    }
+    if (target) return launch_tile_sum(loss_tiles, (int64_t)vt.total_tiles, loss_tiles + vt.total_tiles, loss, s);
     return hipGetLastError();
 }
 

@@ -296,6 +296,27 @@ def gs_loss_l1(rgb: torch.Tensor, target: torch.Tensor, cams: Cameras, buf: Loss
     return buf.loss, buf.dL
 
 
+class DssimBuffers:
+    """Outputs and workspace of gs_loss_l1_dssim for one camera set."""
+
+    def __init__(self, cams: Cameras, dtype=torch.float32, device="cuda"):
+        P = cams.total_pixels()
+        self.dL = torch.empty(3 * P, dtype=dtype, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        wsb = int(_lib.load().gs_loss_dssim_workspace_bytes(_dtype_code(dtype), cams.host_ptr, cams.n))
+        if wsb == 0:
+            check(_lib.GS_ERR_ARG)
+        self.workspace = torch.empty(wsb, dtype=torch.uint8, device=device)
+
+
+def gs_loss_l1_dssim(rgb: torch.Tensor, target: torch.Tensor, cams: Cameras, buf: DssimBuffers, lam: float = 0.2,
+                     scale: float = 1.0, stream=None):
+    check(_lib.load().gs_loss_l1_dssim(_dtype_code(rgb.dtype), _ptr(rgb), _ptr(target), cams.host_ptr, cams.n,
+                                       float(lam), float(scale), _ptr(buf.dL), _ptr(buf.loss),
+                                       _ptr(buf.workspace), buf.workspace.numel(), _stream(stream)))
+    return buf.loss, buf.dL
+
+
 def adam_hparams(lr6, beta1=0.9, beta2=0.999, eps=1e-15, batch_size=1, zero_grad=True) -> GsAdamHparams:
     return GsAdamHparams((C.c_double * 6)(*[float(x) for x in lr6]), beta1, beta2, eps, int(batch_size),
                          int(zero_grad))

@@ -40,6 +40,7 @@ class TrainConfig:
     graph: bool = True
     fused_adam: bool = True         # transformation backward and Adam in one pass (gs_project_bwd_adam)
     fused_loss: bool = True         # L1 loss in the render forward's output stage (gs_render_fwd_l1)
+    ssim_lambda: float = 0.0        # > 0: loss (1 - lambda) L1 + lambda (1 - SSIM) (gs_loss_l1_dssim)
     extra: dict = field(default_factory=dict)
 
 
@@ -64,7 +65,10 @@ class BatchedTrainer:
         self.rgb = torch.empty(3 * P_all, dtype=torch.float32, device=dev)
         self.T = torch.empty(P_all, dtype=torch.float32, device=dev)
         self.last = torch.empty(P_all, dtype=torch.int32, device=dev)
-        self.loss_buf = R.LossBuffers(self.cams, device=dev)
+        if self.cfg.ssim_lambda > 0.0:
+            self.loss_buf = R.DssimBuffers(self.cams, device=dev)
+        else:
+            self.loss_buf = R.LossBuffers(self.cams, device=dev)
         T_all = self.cams.total_tiles()
         self.work_fwd = torch.zeros(T_all, dtype=torch.int32, device=dev)
         self.work_bwd = torch.zeros(T_all, dtype=torch.int32, device=dev)
@@ -104,7 +108,11 @@ class BatchedTrainer:
 
     def _render(self):
         """Render forward, and the loss with its gradient (fused or after)."""
-        if self.cfg.fused_loss:
+        if self.cfg.ssim_lambda > 0.0:
+            R.gs_render_fwd(self.proj, self.n, self.bins, self.cams, self.cfg.bg, self.sched_fwd, self.rgb, self.T,
+                            self.last, self.work_fwd, self.work_bwd)
+            R.gs_loss_l1_dssim(self.rgb, self.targets, self.cams, self.loss_buf, lam=self.cfg.ssim_lambda)
+        elif self.cfg.fused_loss:
             R.gs_render_fwd_l1(self.proj, self.n, self.bins, self.cams, self.targets, self.loss_buf, self.cfg.bg,
                                self.sched_fwd, self.rgb, self.T, self.last, self.work_fwd, self.work_bwd)
         else:

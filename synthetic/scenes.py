@@ -259,3 +259,30 @@ def random_images(cameras: list, seed: int, dtype=torch.float32) -> torch.Tensor
     gen = torch.Generator().manual_seed(seed)
     total = sum(3 * c["width"] * c["height"] for c in cameras)
     return torch.rand(total, generator=gen, dtype=torch.float64).to(dtype)
+
+
+def image_pair(cameras: list, seed: int, dtype=torch.float32, noise: float = 0.05):
+    """A (rendered, target) pair of concatenated planar [3][H][W] images shaped
+    like a training step's: the target a smooth colour field with fine noise,
+    a flat rectangle and values clipped to [0, 1] (saturated areas); the
+    rendered image the target plus independent noise of standard deviation
+    `noise`, clipped the same way, and equal to it on the flat rectangle."""
+    gen = np.random.default_rng(seed)
+    rgb, tgt = [], []
+    for c in cameras:
+        W, H = c["width"], c["height"]
+        yy, xx = np.meshgrid(np.arange(H) / max(H, 1), np.arange(W) / max(W, 1), indexing="ij")
+        t = np.empty((3, H, W))
+        for ch in range(3):
+            f1, f2, ph = gen.uniform(1, 8), gen.uniform(1, 8), gen.uniform(0, 2 * math.pi)
+            t[ch] = 0.5 + 0.6 * np.sin(f1 * 2 * math.pi * xx + ph) * np.cos(f2 * 2 * math.pi * yy)
+        t += 0.03 * gen.standard_normal(t.shape)
+        x0, y0 = int(gen.integers(0, max(W // 2, 1))), int(gen.integers(0, max(H // 2, 1)))
+        flat = (slice(None), slice(y0, y0 + max(H // 4, 1)), slice(x0, x0 + max(W // 4, 1)))
+        t[flat] = gen.uniform(0.1, 0.9)
+        t = np.clip(t, 0.0, 1.0)
+        r = np.clip(t + noise * gen.standard_normal(t.shape), 0.0, 1.0)
+        r[flat] = t[flat]
+        rgb.append(r.ravel())
+        tgt.append(t.ravel())
+    return (torch.from_numpy(np.concatenate(rgb)).to(dtype), torch.from_numpy(np.concatenate(tgt)).to(dtype))

@@ -216,14 +216,15 @@ def test_fused_backward_adam_equals_separate_calls(n):
     assert not torch.equal(state["fused"]["P"], P.cuda())
 
 
-def test_graph_replay_equals_eager_steps():
+@pytest.mark.parametrize("lam", [0.0, 0.2])
+def test_graph_replay_equals_eager_steps(lam):
     """Whole-step graph replays, with eager work and synchronisations in
-    between, track eager steps from the same start."""
+    between, track eager steps from the same start (L1 loss, and L1 + D-SSIM)."""
     from paper_2406_18533_amd import _lib, train
     P, cams, tgt = _small_batch()
     P0 = P.cuda()
-    eager = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=False))
-    graph = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=True))
+    eager = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=False, ssim_lambda=lam))
+    graph = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=True, ssim_lambda=lam))
     for k in range(4):
         eager.step()
         graph.step()

@@ -129,7 +129,7 @@ def dssim_side(tr, P, cams_list, targets, steps: int, warmup: int, lam: float = 
     nbytes = 44 * 3 * tr.cams.total_pixels()
     gbs = nbytes / (ms / 1e3) / 1e9
     del buf
-    t2 = train.BatchedTrainer(P.clone(), cams_list, targets, dataclasses.replace(tr.cfg, ssim_lambda=lam))
+    t2 = train.BatchedTrainer(P.clone(), cams_list, targets, dataclasses.replace(tr.cfg, ssim_lambda=lam, extra=dict(tr.cfg.extra)))
     for _ in range(max(warmup, 1)):
         t2.step()
         t2.check_overflow()

@@ -84,10 +84,13 @@ class BatchedTrainer:
         self._skip_flag = torch.ones(1, dtype=torch.int32, device=dev)
 
     def _make_sched(self):
+        """Schedulers of the two render passes: the per-pass modes the
+        autotuner recorded in cfg.extra, else cfg.mode for both."""
         c = self.cfg
-        self.sched_fwd = R.Sched(self.cams, c.mode, c.fwd_shape[0], c.fwd_shape[1], c.workers, c.queues,
+        fm, bm = c.extra.get("fwd_mode", c.mode), c.extra.get("bwd_mode", c.mode)
+        self.sched_fwd = R.Sched(self.cams, fm, c.fwd_shape[0], c.fwd_shape[1], c.workers, c.queues,
                                  tile_cost=self.work_fwd)
-        self.sched_bwd = R.Sched(self.cams, c.mode, c.bwd_shape[0], c.bwd_shape[1], c.workers, c.queues,
+        self.sched_bwd = R.Sched(self.cams, bm, c.bwd_shape[0], c.bwd_shape[1], c.workers, c.queues,
                                  tile_cost=self.work_bwd)
 
     def set_shapes(self, fwd_shape=None, bwd_shape=None, mode=None):
@@ -97,6 +100,8 @@ class BatchedTrainer:
             self.cfg.bwd_shape = tuple(bwd_shape)
         if mode is not None:
             self.cfg.mode = mode
+            self.cfg.extra.pop("fwd_mode", None)
+            self.cfg.extra.pop("bwd_mode", None)
         self._make_sched()
         self.graph = None
 

@@ -141,7 +141,8 @@ def dssim_side(tr, P, cams_list, targets, steps: int, warmup: int, lam: float = 
     t1 = time.perf_counter()
     out = {"lambda": lam, "views_per_s": round(t2.V * steps / (t1 - t0), 2),
            "ms_per_step": round((t1 - t0) * 1e3 / steps, 4), "loss_ms": round(ms, 4),
-           "loss_bytes": nbytes, "loss_GBps": round(gbs, 1), "loss_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+           "loss_bytes": nbytes, "loss_GBps": round(gbs, 1), "loss_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "loss_traffic": measured_traffic("gs_loss_l1_dssim")}
     del t2
     return out
 
@@ -207,7 +208,8 @@ def algorithmic(c: dict) -> dict:
 # Kernel sources whose HBM traffic per launch was measured with hardware counters.
 TRAFFIC_SOURCES = {"gs_render_bwd_pixels": ["render.hip", "common.hpp"],
                    "gs_render_fwd": ["render.hip", "common.hpp"],
-                   "gs_render_fwd_l1": ["render.hip", "common.hpp"]}
+                   "gs_render_fwd_l1": ["render.hip", "common.hpp"],
+                   "gs_loss_l1_dssim": ["ssim.hip", "common.hpp"]}
 
 
 def source_digest(entry: str):
@@ -223,7 +225,7 @@ def measured_traffic(entry: str):
     """HBM bytes per launch of the entry's kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
     None when there is none or the kernel's sources changed since."""
-    path = os.path.join(ROOT, "profiles", "render_16x1080p_1M_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", "train_step_16x1080p_1M_hbm_traffic.md")
     if entry not in TRAFFIC_SOURCES or not os.path.exists(path):
         return None
     rows = {}

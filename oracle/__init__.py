@@ -300,6 +300,96 @@ def l1_dssim_loss(images: list, targets: list, lam: float = 0.2, with_grad: bool
     return loss, grads
 
 
+# ----------------------------------------------------------------------------- densification
+# Adaptive densification (the training process of section 2.1 and appendix
+# A.1): Gaussians whose projected position gradient is large are cloned
+# (small ones) or split (large ones, by a scale threshold); Gaussians of low
+# opacity (or too large) are pruned; opacities are reset periodically. The
+# paper names these steps and their hyperparameters, not their arithmetic;
+# the readings follow the original 3D Gaussian splatting procedure:
+#  - statistic: per (view, Gaussian) visible record, the norm of the loss
+#    gradient w.r.t. the projected centre (u, v) in pixels, times `scale` (the
+#    batch size, so it is the gradient of that view's own loss), summed per
+#    Gaussian with a count of the visible records;
+#  - selected: count > 0 and sum >= threshold * count (in FP64);
+#  - split if selected and max log-scale > split_log_scale, else clone;
+#  - pruned: opacity logit < prune_logit or max log-scale > prune_log_scale
+#    (decided in the logit / log domain, exact on FP32 inputs);
+#  - split children k = 0, 1: mean + R(q) (exp(log-scale) * noise[k]),
+#    log-scale - log(1.6), every other parameter copied; a child is pruned by
+#    the same rule (its max log-scale is the parent's minus log(1.6), decided
+#    as parent's > prune_log_scale + log(1.6)); the split parent is removed;
+#  - a clone is an exact copy; a pruned parent's clone is pruned too;
+#  - output order: kept originals, clones, first children, second children,
+#    each in index order; Adam moments are copied for kept originals and zero
+#    for new Gaussians.
+SPLIT_SHRINK = 1.6
+
+
+def densify_stats(du, dv, visible, scale: float = 1.0):
+    """du, dv, visible: [V][N]. Returns (sum [N] of scale * |(du, dv)| over
+    visible records, count [N] of visible records)."""
+    du, dv = _f64(du), _f64(dv)
+    vis = np.asarray(visible, dtype=bool)
+    norms = scale * np.sqrt(du * du + dv * dv)
+    return np.where(vis, norms, 0.0).sum(axis=0), vis.sum(axis=0).astype(np.int64)
+
+
+def quat_rotation(q: np.ndarray) -> np.ndarray:
+    """Rotation matrices [N][3][3] of quaternions [4][N] = (w, x, y, z),
+    normalised first."""
+    q = _f64(q) / np.linalg.norm(_f64(q), axis=0)
+    w, x, y, z = q
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def densify_classes(P, accum, denom, grad_thr, split_log_scale, prune_logit, prune_log_scale):
+    """Boolean masks (kept original, kept clone, kept child 0 = child 1,
+    split) per Gaussian, decided as described above."""
+    P = _f64(P)
+    accum, denom = _f64(accum), np.asarray(denom)
+    maxls = P[3:6].max(axis=0)
+    selected = (denom > 0) & (accum >= grad_thr * denom.astype(np.float64))
+    big = maxls > split_log_scale
+    pruned = (P[10] < prune_logit) | (maxls > prune_log_scale)
+    child_pruned = (P[10] < prune_logit) | (maxls > prune_log_scale + np.log(SPLIT_SHRINK))
+    split = selected & big
+    return ~split & ~pruned, selected & ~big & ~pruned, split & ~child_pruned, split
+
+
+def densify(P, m, v, accum, denom, noise, grad_thr, split_log_scale, prune_logit, prune_log_scale):
+    """One densification: returns (P', m', v') [59][N'] in the output order
+    above. noise: [2][3][N] standard normal draws (inputs, so that any
+    implementation can be checked against this one)."""
+    P, m, v = _f64(P), _f64(m), _f64(v)
+    keep, clone, child, _ = densify_classes(P, accum, denom, grad_thr, split_log_scale, prune_logit,
+                                            prune_log_scale)
+    R = quat_rotation(P[6:10])
+    s = np.exp(P[3:6])
+    parts = [P[:, keep], P[:, clone]]
+    for k in range(2):
+        c = P.copy()
+        c[0:3] = P[0:3] + np.einsum("nij,jn->in", R, s * _f64(noise[k]))
+        c[3:6] = P[3:6] - np.log(SPLIT_SHRINK)
+        parts.append(c[:, child])
+    n_new = int(clone.sum() + 2 * child.sum())
+    z = np.zeros((59, n_new))
+    return (np.concatenate(parts, axis=1), np.concatenate([m[:, keep], z], axis=1),
+            np.concatenate([v[:, keep], z], axis=1))
+
+
+def reset_opacity(P, m, v, max_opacity: float = 0.01) -> None:
+    """In place: opacity = min(opacity, max_opacity), as logits; the opacity
+    row's Adam moments are zeroed."""
+    cap = np.log(max_opacity / (1.0 - max_opacity))
+    P[10] = np.minimum(P[10], cap)
+    m[10] = 0.0
+    v[10] = 0.0
+
+
 # ----------------------------------------------------------------------------- pipelines
 def rounded_for_binning(proj: np.ndarray):
     """FP32 copies of (u, v, radius, depth): binning decides in FP32."""

@@ -147,6 +147,56 @@ def dssim_side(tr, P, cams_list, targets, steps: int, warmup: int, lam: float = 
     return out
 
 
+def densify_side(tr, reps: int = 5):
+    """One densification of the step's Gaussians after a step that
+    accumulates the statistic (selection at its 90th percentile, split above
+    the median largest log-scale, prune below opacity 0.005): average times
+    of the plan and apply entries (HIP events; the host reads the counts in
+    between) and the HBM rate of their algorithmic bytes: plan 25 B per
+    Gaussian (four parameter rows, the statistic, the class byte); apply the
+    class byte and 236 B of parameters per Gaussian, 472 B of moments per kept
+    original, 24 B of noise per split pair and 708 B written per output
+    Gaussian."""
+    import math
+    import torch
+    from paper_2406_18533_amd import raster as R
+    tr.enable_densify_stats()
+    tr.step_eager()
+    torch.cuda.synchronize()
+    acc, cnt = tr.stats
+    seen = cnt > 0
+    thr = float(torch.quantile((acc[seen] / cnt[seen]).float(), 0.9))
+    split_ls = float(torch.quantile(tr.P[3:6].max(dim=0).values.float(), 0.5))
+    h = R.densify_hparams(thr, split_ls, math.log(0.005 / 0.995))
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    noise = torch.randn(2, 3, tr.n, generator=gen, device="cuda")
+    plan = R.DensifyPlan(tr.n)
+    t_plan = t_apply = 0.0
+    for _ in range(reps + 1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        R.gs_densify_plan(tr.P, acc, cnt, h, plan)
+        ev[1].record()
+        K, C, S = (int(x) for x in plan.counts.cpu())
+        ev[2].record()
+        out = R.gs_densify_apply(tr.P, tr.m, tr.v, noise, plan, K + C + 2 * S)
+        ev[3].record()
+        torch.cuda.synchronize()
+        del out
+        if _:
+            t_plan += ev[0].elapsed_time(ev[1]) / reps
+            t_apply += ev[2].elapsed_time(ev[3]) / reps
+    n, n_out = tr.n, K + C + 2 * S
+    b_plan = 25 * n
+    b_apply = n + 236 * n + 472 * K + 24 * S + 708 * n_out
+    tr.enable_densify_stats(False)
+    return {"gaussians": n, "kept": K, "clones": C, "split_pairs": S, "output": n_out,
+            "plan_ms": round(t_plan, 4), "apply_ms": round(t_apply, 4),
+            "plan_GBps": round(b_plan / (t_plan / 1e3) / 1e9, 1),
+            "apply_GBps": round(b_apply / (t_apply / 1e3) / 1e9, 1),
+            "apply_hbm_frac": round(b_apply / (t_apply / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def workload_counts(tr):
     """Exact counts of the step's work units, for the algorithmic bytes/flops."""
     import torch
@@ -422,6 +472,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-aerial", action="store_true")
     ap.add_argument("--no-dssim", action="store_true")
+    ap.add_argument("--no-densify", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="end with a fill and a copy of this many MiB (calibration for HBM byte counters)")
@@ -477,6 +528,11 @@ def main():
         log("step with the L1 + D-SSIM loss")
         dssim = dssim_side(tr, P, w.cameras, targets, args.steps, args.warmup)
         log(f"l1+dssim {json.dumps(dssim)}")
+    dens = None
+    if not args.no_densify:
+        log("densification of the step's Gaussians")
+        dens = densify_side(tr)
+        log(f"densify {json.dumps(dens)}")
     plain = None
     if not args.no_plain:
         log("plain per-view path")
@@ -531,6 +587,7 @@ def main():
         "speedup_vs_plain": round(views_s / plain["views_per_s"], 3) if plain else None,
         "aerial_4k": aerial,
         "l1_dssim": dssim,
+        "densify": dens,
         "serving": serving,
         "roofline": roof,
         "per_kernel": per,

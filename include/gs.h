@@ -122,6 +122,22 @@ typedef struct gs_adam_hparams {
     int32_t zero_grad;        /* 1: write 0 into grad after the update */
 } gs_adam_hparams;
 
+/* Densification thresholds [host] (appendix A.1). A Gaussian is selected
+ * when its statistic count c > 0 and sum s >= grad_threshold * c (compared in
+ * double); selected Gaussians whose largest log-scale exceeds
+ * split_log_scale are split, the others cloned. A Gaussian (or a clone, or a
+ * split child) is pruned when its opacity logit < prune_logit or its largest
+ * log-scale > prune_log_scale; a child's largest log-scale is its parent's
+ * minus log(1.6), so children are pruned when the parent's exceeds
+ * prune_log_scale + log(1.6). Comparing logits and log-scales (not opacities
+ * and scales) keeps every decision exact on the stored values. */
+typedef struct gs_densify_hparams {
+    double grad_threshold;    /* on the mean of the per-view statistic (pixels) */
+    double split_log_scale;   /* log(percent_dense * scene extent) in 3DGS terms */
+    double prune_logit;       /* log(o_min / (1 - o_min)) */
+    double prune_log_scale;   /* log of the largest world scale kept (+inf: no size pruning) */
+} gs_densify_hparams;
+
 /* ------------------------------------------------------------------ library */
 const char *gs_version(void);
 /* Message of the last failed call on this thread ("" if none). */
@@ -322,6 +338,52 @@ gs_status gs_project_bwd_adam(gs_dtype dtype, void *params, int64_t n, const gs_
                               const gs_camera *cams_host, int32_t views, const void *projected,
                               void *dprojected, void *grad, void *m, void *v, const gs_adam_hparams *h,
                               int64_t *step_dev, double *scratch, const int32_t *skip_flag, void *stream);
+
+/* ------------------------------------------------------------------ densification */
+/* Densification statistic (appendix A.1: position variance across steps,
+ * read as the gradient of the loss w.r.t. each Gaussian's projected
+ * centre). For every view v and Gaussian i whose record touches a tile
+ * (tiles touched > 0): accum[i] += scale * |(dL/du, dL/dv)| of that record in
+ * dprojected (pixels), count[i] += 1. Pass scale = batch size so that each
+ * term is the gradient of that view's own loss. Call it after the render
+ * backward and before gs_project_bwd / gs_project_bwd_adam, which clear
+ * dprojected. accum [n] float, count [n] int32, device; both accumulate
+ * (zero them to start a new interval). */
+gs_status gs_densify_stats(gs_dtype dtype, const void *projected, const void *dprojected, int64_t n,
+                           int32_t views, double scale, float *accum, int32_t *count, void *stream);
+
+/* Bytes of workspace for gs_densify_plan / gs_densify_apply on n Gaussians. */
+size_t gs_densify_workspace_bytes(int64_t n);
+
+/* Densification, first half: classifies every Gaussian with the rules of
+ * gs_densify_hparams and counts the output per class. Writes counts_dev[3]
+ * (device int64): kept originals K, clones C, split pairs S; the output has
+ * K + C + 2 S Gaussians. The classes and per-block offsets stay in the
+ * workspace for gs_densify_apply; read counts_dev on the host to size the
+ * output. params [59][n]. */
+gs_status gs_densify_plan(gs_dtype dtype, const void *params, int64_t n, const float *accum,
+                          const int32_t *count, const gs_densify_hparams *h, void *workspace,
+                          size_t workspace_bytes, int64_t *counts_dev, void *stream);
+
+/* Densification, second half: writes the new parameters and Adam moments
+ * [59][n_out], n_out = K + C + 2 S from the plan, in this order: kept
+ * originals, clones (exact copies), first split children, second split
+ * children, each group in index order. A split child k of Gaussian i has
+ * mean + R(q) (exp(log-scale) * noise[k][.][i]), log-scale - log(1.6) and
+ * every other parameter of i; the split parent is removed. Moments are
+ * copied for kept originals and zero for clones and children. noise:
+ * [2][3][n] standard normal draws (device, dtype), supplied by the caller so
+ * that results are reproducible. The workspace must hold the plan of the
+ * same params and h; outputs must not alias inputs. Writes beyond n_out are
+ * never made, whatever the plan says. */
+gs_status gs_densify_apply(gs_dtype dtype, const void *params, const void *m, const void *v, int64_t n,
+                           const void *noise, const void *workspace, size_t workspace_bytes, void *params_out,
+                           void *m_out, void *v_out, int64_t n_out, void *stream);
+
+/* Opacity reset (appendix A.1): opacity logit = min(logit, max_logit) for
+ * every Gaussian; the opacity row of m and v is zeroed. In place. */
+gs_status gs_reset_opacity(gs_dtype dtype, void *params, void *m, void *v, int64_t n, double max_logit,
+                           void *stream);
 
 /* ------------------------------------------------------------------ scheduler */
 /* Algorithm 1 ("Calculation of Division Points") on the device with G =

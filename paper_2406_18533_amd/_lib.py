@@ -19,6 +19,7 @@ EXPORTS = [
     "gs_loss_dssim_workspace_bytes", "gs_project",
     "gs_bin_sort", "gs_bins_keys64", "gs_render_fwd", "gs_render_bwd", "gs_render_bwd_pixels", "gs_project_bwd",
     "gs_loss_l1", "gs_loss_l1_dssim", "gs_render_fwd_l1", "gs_adam_step", "gs_project_bwd_adam", "gs_sched_plan",
+    "gs_densify_stats", "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_reset_opacity",
 ]
 
 
@@ -43,6 +44,11 @@ class GsSched(C.Structure):
 class GsAdamHparams(C.Structure):
     _fields_ = [("lr", C.c_double * 6), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("batch_size", C.c_int32), ("zero_grad", C.c_int32)]
+
+
+class GsDensifyHparams(C.Structure):
+    _fields_ = [("grad_threshold", C.c_double), ("split_log_scale", C.c_double), ("prune_logit", C.c_double),
+                ("prune_log_scale", C.c_double)]
 
 
 class GsError(RuntimeError):
@@ -94,6 +100,11 @@ def load() -> C.CDLL:
         "gs_project_bwd_adam": ([i32, p, i64, p, cam_p, i32, p, p, p, p, p, C.POINTER(GsAdamHparams), p, p, p, p],
                                 i32),
         "gs_sched_plan": ([C.POINTER(GsSched), cam_p, i32, p, p], i32),
+        "gs_densify_stats": ([i32, p, p, i64, i32, C.c_double, p, p, p], i32),
+        "gs_densify_workspace_bytes": ([i64], sz),
+        "gs_densify_plan": ([i32, p, i64, p, p, C.POINTER(GsDensifyHparams), p, sz, p, p], i32),
+        "gs_densify_apply": ([i32, p, p, p, i64, p, p, sz, p, p, p, i64, p], i32),
+        "gs_reset_opacity": ([i32, p, p, p, i64, C.c_double, p], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

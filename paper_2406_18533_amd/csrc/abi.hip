@@ -40,6 +40,16 @@ template <typename T>
 hipError_t launch_l1_dssim(const void *, const void *, const ViewTable &, double, double, void *, double *, void *,
                            hipStream_t);
 size_t dssim_ws_bytes(const ViewTable &vt, size_t elem);
+template <typename T>
+hipError_t launch_densify_stats(const void *, const void *, int64_t, int32_t, double, float *, int32_t *, hipStream_t);
+template <typename T>
+hipError_t launch_densify_plan(const void *, int64_t, const float *, const int32_t *, const gs_densify_hparams &,
+                               void *, int64_t *, hipStream_t);
+template <typename T>
+hipError_t launch_densify_apply(const void *, const void *, const void *, int64_t, const void *, const void *, void *,
+                                void *, void *, int64_t, hipStream_t);
+template <typename T> hipError_t launch_reset_opacity(void *, void *, void *, int64_t, double, hipStream_t);
+size_t densify_ws_bytes(int64_t n);
 
 ViewTable make_view_table(const gs_camera *cams, int32_t views)
 {
@@ -479,6 +489,76 @@ gs_status gs_loss_l1_dssim(gs_dtype dtype, const void *rgb, const void *target, 
                        ? launch_l1_dssim<float>(rgb, target, vt, lam, scale, dL_drgb, loss_dev, workspace, s)
                        : launch_l1_dssim<double>(rgb, target, vt, lam, scale, dL_drgb, loss_dev, workspace, s);
     return hip_status(e, "gs_loss_l1_dssim");
+}
+
+gs_status gs_densify_stats(gs_dtype dtype, const void *projected, const void *dprojected, int64_t n, int32_t views,
+                           double scale, float *accum, int32_t *count, void *stream)
+{
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(n >= 0 && views >= 1 && views <= GS_MAX_VIEWS, "bad n or views");
+    CHECK_ARG(n == 0 || (projected && dprojected && accum && count), "null pointer");
+    CHECK_ARG(isfinite(scale), "bad scale");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32
+                       ? launch_densify_stats<float>(projected, dprojected, n, views, scale, accum, count, s)
+                       : launch_densify_stats<double>(projected, dprojected, n, views, scale, accum, count, s);
+    return hip_status(e, "gs_densify_stats");
+}
+
+size_t gs_densify_workspace_bytes(int64_t n) { return n < 0 ? 0 : densify_ws_bytes(n); }
+
+gs_status gs_densify_plan(gs_dtype dtype, const void *params, int64_t n, const float *accum, const int32_t *count,
+                          const gs_densify_hparams *h, void *workspace, size_t workspace_bytes, int64_t *counts_dev,
+                          void *stream)
+{
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(n >= 0, "n < 0");
+    CHECK_ARG(h && workspace && counts_dev, "null pointer");
+    CHECK_ARG(n == 0 || (params && accum && count), "null pointer");
+    CHECK_ARG(isfinite(h->grad_threshold) && h->grad_threshold >= 0.0, "bad gradient threshold");
+    CHECK_ARG(!isnan(h->split_log_scale) && !isnan(h->prune_logit) && !isnan(h->prune_log_scale), "NaN threshold");
+    CHECK_ARG(workspace_bytes >= densify_ws_bytes(n), "densify workspace too small");
+    CHECK_ARG(((uintptr_t)workspace & 255) == 0, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_densify_plan<float>(params, n, accum, count, *h, workspace, counts_dev, s)
+                                   : launch_densify_plan<double>(params, n, accum, count, *h, workspace, counts_dev, s);
+    return hip_status(e, "gs_densify_plan");
+}
+
+gs_status gs_densify_apply(gs_dtype dtype, const void *params, const void *m, const void *v, int64_t n,
+                           const void *noise, const void *workspace, size_t workspace_bytes, void *params_out,
+                           void *m_out, void *v_out, int64_t n_out, void *stream)
+{
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(n >= 0 && n_out >= 0, "n < 0");
+    CHECK_ARG(workspace, "null pointer");
+    CHECK_ARG(n == 0 || (params && m && v && noise), "null pointer");
+    CHECK_ARG(n_out == 0 || (params_out && m_out && v_out), "null pointer");
+    CHECK_ARG(n_out <= 2 * n, "n_out larger than any plan allows");
+    CHECK_ARG(n_out == 0 || (params_out != params && params_out != m && params_out != v && m_out != params &&
+                             m_out != m && m_out != v && v_out != params && v_out != m && v_out != v),
+              "outputs alias inputs");
+    CHECK_ARG(workspace_bytes >= densify_ws_bytes(n), "densify workspace too small");
+    CHECK_ARG(((uintptr_t)workspace & 255) == 0, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32
+                       ? launch_densify_apply<float>(params, m, v, n, noise, workspace, params_out, m_out, v_out,
+                                                     n_out, s)
+                       : launch_densify_apply<double>(params, m, v, n, noise, workspace, params_out, m_out, v_out,
+                                                      n_out, s);
+    return hip_status(e, "gs_densify_apply");
+}
+
+gs_status gs_reset_opacity(gs_dtype dtype, void *params, void *m, void *v, int64_t n, double max_logit, void *stream)
+{
+    CHECK_ARG(dtype_ok(dtype), "bad dtype");
+    CHECK_ARG(n >= 0, "n < 0");
+    CHECK_ARG(n == 0 || (params && m && v), "null pointer");
+    CHECK_ARG(!isnan(max_logit), "NaN max_logit");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = dtype == GS_F32 ? launch_reset_opacity<float>(params, m, v, n, max_logit, s)
+                                   : launch_reset_opacity<double>(params, m, v, n, max_logit, s);
+    return hip_status(e, "gs_reset_opacity");
 }
 
 gs_status gs_adam_step(gs_dtype dtype, void *params, void *grad, void *m, void *v, int64_t n,

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import GsAdamHparams, GsBins, GsCamera, GsSched, check
+from ._lib import GsAdamHparams, GsBins, GsCamera, GsDensifyHparams, GsSched, check
 
 TILE = 16
 
@@ -338,6 +338,58 @@ def gs_project_bwd_adam(params, cams: Cameras, projected: torch.Tensor, dproject
                                           cams.n, _ptr(projected), _ptr(dprojected), _ptr(grad), _ptr(m), _ptr(v),
                                           C.byref(h), _ptr(step), _ptr(scratch), _ptr(skip_flag),
                                           _stream(stream)))
+
+
+# --------------------------------------------------------------------------- densification
+def densify_hparams(grad_threshold: float, split_log_scale: float, prune_logit: float,
+                    prune_log_scale: float = math.inf) -> GsDensifyHparams:
+    return GsDensifyHparams(float(grad_threshold), float(split_log_scale), float(prune_logit),
+                            float(prune_log_scale))
+
+
+def gs_densify_stats(projected: torch.Tensor, dprojected: torch.Tensor, n: int, views: int, accum: torch.Tensor,
+                     count: torch.Tensor, scale: float = 1.0, stream=None):
+    assert accum.dtype == torch.float32 and count.dtype == torch.int32 and accum.numel() >= n and count.numel() >= n
+    check(_lib.load().gs_densify_stats(_dtype_code(dprojected.dtype), _ptr(projected), _ptr(dprojected), int(n),
+                                       int(views), float(scale), _ptr(accum), _ptr(count), _stream(stream)))
+    return accum, count
+
+
+class DensifyPlan:
+    """Workspace and device counts of one densification."""
+
+    def __init__(self, n: int, device="cuda"):
+        self.n = int(n)
+        wsb = int(_lib.load().gs_densify_workspace_bytes(self.n))
+        self.workspace = torch.empty(max(wsb, 256), dtype=torch.uint8, device=device)
+        self.counts = torch.zeros(3, dtype=torch.int64, device=device)
+
+
+def gs_densify_plan(params: torch.Tensor, accum: torch.Tensor, count: torch.Tensor, h: GsDensifyHparams,
+                    plan: DensifyPlan, stream=None) -> DensifyPlan:
+    n = params.shape[1]
+    assert n == plan.n and params.is_contiguous()
+    check(_lib.load().gs_densify_plan(_dtype_code(params.dtype), _ptr(params), n, _ptr(accum), _ptr(count),
+                                      C.byref(h), _ptr(plan.workspace), plan.workspace.numel(), _ptr(plan.counts),
+                                      _stream(stream)))
+    return plan
+
+
+def gs_densify_apply(params, m, v, noise: torch.Tensor, plan: DensifyPlan, n_out: int, stream=None):
+    """New (params, m, v) [59][n_out]; n_out = K + C + 2 S from the plan's counts."""
+    n = params.shape[1]
+    assert noise.dtype == params.dtype and noise.numel() == 6 * n
+    po = torch.empty(59, n_out, dtype=params.dtype, device=params.device)
+    mo, vo = torch.empty_like(po), torch.empty_like(po)
+    check(_lib.load().gs_densify_apply(_dtype_code(params.dtype), _ptr(params), _ptr(m), _ptr(v), n, _ptr(noise),
+                                       _ptr(plan.workspace), plan.workspace.numel(), _ptr(po), _ptr(mo), _ptr(vo),
+                                       int(n_out), _stream(stream)))
+    return po, mo, vo
+
+
+def gs_reset_opacity(params, m, v, max_logit: float, stream=None):
+    check(_lib.load().gs_reset_opacity(_dtype_code(params.dtype), _ptr(params), _ptr(m), _ptr(v), params.shape[1],
+                                       float(max_logit), _stream(stream)))
 
 
 def gs_sched_plan(sched: Sched, cams: Cameras, dp_out: torch.Tensor | None = None, stream=None):

@@ -16,6 +16,7 @@ stream.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import torch
@@ -75,13 +76,17 @@ class BatchedTrainer:
         self.hp = R.adam_hparams(self.cfg.lr, self.cfg.beta1, self.cfg.beta2, self.cfg.eps, batch_size=self.V,
                                  zero_grad=True)
         self._make_sched()
-        R.gs_project(self.P, self.cams, self.proj)
-        K = int(self.proj[..., 11].double().sum().item())
-        self.bins = R.Bins(self.n, self.cams, max(int(K * self.cfg.headroom), 1024))
+        self._size_bins()
+        self.stats = None                 # densification statistic (accum, count) while enabled
         self.graph = None
         self.overflows = 0
         self._flag_host = torch.zeros(1, dtype=torch.int32, pin_memory=True)
         self._skip_flag = torch.ones(1, dtype=torch.int32, device=dev)
+
+    def _size_bins(self):
+        R.gs_project(self.P, self.cams, self.proj)
+        K = int(self.proj[..., 11].double().sum().item())
+        self.bins = R.Bins(self.n, self.cams, max(int(K * self.cfg.headroom), 1024))
 
     def _make_sched(self):
         """Schedulers of the two render passes: the per-pass modes the
@@ -128,7 +133,50 @@ class BatchedTrainer:
     def backward_and_update(self):
         R.gs_render_bwd_pixels(self.proj, self.n, self.bins, self.cams, self.T, self.last, self.loss_buf.dL,
                                self.dproj, self.cfg.bg, self.sched_bwd)
+        self._accumulate_stats()
         self._update(self.bins.overflow)
+
+    def _accumulate_stats(self):
+        if self.stats is not None:
+            R.gs_densify_stats(self.proj, self.dproj, self.n, self.V, self.stats[0], self.stats[1],
+                               scale=float(self.V))
+
+    # -- densification (appendix A.1) -------------------------------------------------------
+    def enable_densify_stats(self, on: bool = True):
+        """Accumulate the position-gradient statistic in every step from now on."""
+        dev = self.P.device
+        self.stats = (torch.zeros(self.n, dtype=torch.float32, device=dev),
+                      torch.zeros(self.n, dtype=torch.int32, device=dev)) if on else None
+        self.graph = None
+
+    def densify(self, h, seed: int = 0):
+        """Clone / split / prune with the accumulated statistic; resizes every
+        per-Gaussian buffer, restarts the statistic and re-captures the step.
+        Returns the class counts (kept, clones, split pairs)."""
+        assert self.stats is not None, "enable_densify_stats first"
+        torch.cuda.synchronize()
+        plan = R.DensifyPlan(self.n)
+        R.gs_densify_plan(self.P, self.stats[0], self.stats[1], h, plan)
+        gen = torch.Generator(device=self.P.device).manual_seed(seed)
+        noise = torch.randn(2, 3, self.n, generator=gen, device=self.P.device, dtype=self.P.dtype)
+        K, C, S = (int(x) for x in plan.counts.cpu())
+        self.P, self.m, self.v = R.gs_densify_apply(self.P, self.m, self.v, noise, plan, K + C + 2 * S)
+        self._resize()
+        return K, C, S
+
+    def reset_opacity(self, max_opacity: float = 0.01):
+        R.gs_reset_opacity(self.P, self.m, self.v, math.log(max_opacity / (1.0 - max_opacity)))
+
+    def _resize(self):
+        dev = self.P.device
+        self.n = self.P.shape[1]
+        self.grad = torch.zeros_like(self.P)
+        self.proj = R.alloc_projected(self.n, self.V, torch.float32, dev)
+        self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self._size_bins()
+        if self.stats is not None:
+            self.enable_densify_stats()
+        self.graph = None
 
     def _update(self, skip_flag):
         if self.cfg.fused_adam:

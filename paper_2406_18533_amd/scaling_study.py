@@ -1,0 +1,200 @@
+"""Batch-size scaling study of Adam's hyperparameters (section 4: the
+square-root learning-rate rule, eq. "lambda", and the exponential momentum
+rule, eq. "beta"; their empirical test and the appendix ablation), on a
+synthetic scene with the library's own training step.
+
+Protocol, after the paper's: train at batch size 1 for a while, reset the
+optimizer state, then continue from that point with batch size b over the
+same sequence of views, under different rules, and compare the cumulative
+update of the diffuse colour parameters (SH degree 0, rows 11-13) with the
+batch-size-1 continuation: its cosine similarity and its norm ratio. The
+learning-rate rules are constant (lr), square root (lr sqrt(b)) and linear
+(lr b), all with the exponential momentum rule; the momentum rules are
+unchanged (beta) and exponential (beta^b), both with the square-root
+learning rate. The fused Adam kernel always applies lr sqrt(b) and beta^b,
+so the other rules are reached by handing it lr / sqrt(b), lr sqrt(b) or
+beta^(1/b).
+
+Also measured: the precision (inverse of the average per-parameter
+variance) of the batch-mean gradient of the diffuse colours against the
+batch size, from gradients of single views (the independent-gradients
+argument predicts it grows linearly in b while views are uncorrelated),
+corrected for drawing the batch's views without replacement.
+
+Run: python -m paper_2406_18533_amd.scaling_study [--out FILE]
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import sys
+import time
+
+import torch
+
+from . import raster as R
+from . import train
+
+DC = slice(11, 14)
+
+
+@dataclasses.dataclass
+class StudyConfig:
+    gaussians: int = 200_000
+    views: int = 64
+    res: int = 256
+    pretrain_steps: int = 300
+    images: int = 256                   # views consumed by every continuation
+    batches: tuple = (4, 16, 32)
+    variance_batches: tuple = (1, 2, 4, 8, 16, 32, 64)
+    variance_trials: int = 16
+    seed: int = 0
+
+
+def make_scene(c: StudyConfig):
+    """Target scene (clustered Gaussians), its renders from `views` cameras on a
+    sphere, and the starting scene: the target with means moved by N(0, 0.02)
+    and diffuse colours by N(0, 0.3)."""
+    from synthetic import scenes
+    tgt = scenes.clustered_gaussians(c.gaussians, c.seed)
+    cams = scenes.sphere_cameras(c.views, c.seed + 1, c.res, c.res)
+    start = scenes.jittered(tgt, c.seed + 2)
+    g = torch.Generator().manual_seed(c.seed + 3)
+    start[DC] += 0.3 * torch.randn(3, c.gaussians, generator=g).to(start.dtype)
+    images = []
+    for cam in cams:
+        cm = R.Cameras([cam])
+        proj = R.gs_project(tgt.cuda(), cm)
+        K = int(proj[..., 11].double().sum().item())
+        bins = R.Bins(c.gaussians, cm, K + 1024)
+        R.gs_bin_sort(proj, c.gaussians, cm, bins)
+        rgb, _, _ = R.gs_render_fwd(proj, c.gaussians, bins, cm)
+        images.append(rgb.clone())
+    torch.cuda.synchronize()
+    return start.cuda(), cams, images
+
+
+class Runner:
+    """A graph-captured trainer over batches of b views whose camera poses and
+    target images are rewritten in place before every step."""
+
+    def __init__(self, P, cams, images, b: int, lr6, beta1: float, beta2: float):
+        self.cams, self.images, self.b = cams, images, b
+        cfg = train.TrainConfig(lr=tuple(lr6), beta1=beta1, beta2=beta2)
+        first = list(range(b))
+        tgt = torch.cat([images[j] for j in first])
+        self.tr = train.BatchedTrainer(P.clone(), [cams[j] for j in first], tgt, cfg)
+
+    def run(self, seq):
+        tr = self.tr
+        for s in range(0, len(seq) - self.b + 1, self.b):
+            batch = seq[s:s + self.b]
+            tr.cams.update([self.cams[j] for j in batch])
+            tr.targets.copy_(torch.cat([self.images[j] for j in batch]))
+            tr.step()
+            tr.check_overflow()
+        torch.cuda.synchronize()
+        return tr.P
+
+
+def rule_hparams(base_lr, beta1: float, beta2: float, b: int, lr_rule: str, mom_rule: str):
+    """(lr6, beta1, beta2) to hand to the fused Adam (which applies lr sqrt(b)
+    and beta^b) so that the effective rule is the one named."""
+    f = {"constant": 1.0 / math.sqrt(b), "sqrt": 1.0, "linear": math.sqrt(b)}[lr_rule]
+    lr6 = [x * f for x in base_lr]
+    if mom_rule == "unchanged":
+        return lr6, beta1 ** (1.0 / b), beta2 ** (1.0 / b)
+    return lr6, beta1, beta2
+
+
+def _compare(delta, ref):
+    return {"cosine": float((delta * ref).sum() / (delta.norm() * ref.norm())),
+            "norm_ratio": float(delta.norm() / ref.norm())}
+
+
+def gradient_precision(P, cams, images, c: StudyConfig):
+    """Inverse of the average per-parameter variance of the batch-mean
+    diffuse-colour gradient, per batch size, over random batches of distinct
+    views. Batches are drawn without replacement from the study's V views,
+    which shrinks the variance by (V - b) / (V - 1) on its own; the values are
+    divided by that factor (batch sizes below V only), so that uncorrelated
+    views give precision b times that of one view."""
+    n = P.shape[1]
+    grads = []
+    for k, cam in enumerate(cams):
+        cm = R.Cameras([cam])
+        proj = R.gs_project(P, cm)
+        K = int(proj[..., 11].double().sum().item())
+        bins = R.Bins(n, cm, K + 1024)
+        R.gs_bin_sort(proj, n, cm, bins)
+        buf = R.LossBuffers(cm)
+        _, T, last = R.gs_render_fwd_l1(proj, n, bins, cm, images[k], buf)
+        grad = torch.zeros_like(P)
+        R.gs_render_bwd(P, proj, bins, cm, T, last, buf.dL, grad)
+        grads.append(grad[DC].flatten().clone())
+    G = torch.stack(grads)                             # [views][3 n], each a single view's gradient
+    gen = torch.Generator().manual_seed(c.seed + 9)
+    out = {}
+    V = len(cams)
+    for b in c.variance_batches:
+        if b >= V:
+            continue
+        means = []
+        for _ in range(max(c.variance_trials, 2)):
+            idx = torch.randperm(len(cams), generator=gen)[:b].cuda()
+            means.append(G[idx].mean(dim=0))
+        M = torch.stack(means)
+        out[b] = float(1.0 / M.var(dim=0).mean() * (V - b) / (V - 1))
+    return out
+
+
+def run_study(c: StudyConfig, log=print):
+    t0 = time.perf_counter()
+    P0, cams, images = make_scene(c)
+    base = train.TrainConfig()
+    b1, b2 = base.beta1, base.beta2
+    log(f"pre-training {c.pretrain_steps} steps at batch size 1")
+    gen = torch.Generator().manual_seed(c.seed + 5)
+    pre_seq = torch.randint(0, c.views, (c.pretrain_steps,), generator=gen).tolist()
+    P_pre = Runner(P0, cams, images, 1, base.lr, b1, b2).run(pre_seq).clone()
+    seq = torch.randint(0, c.views, (c.images,), generator=gen).tolist()
+    ref = Runner(P_pre, cams, images, 1, base.lr, b1, b2).run(seq)[DC] - P_pre[DC]
+    res = {"config": dataclasses.asdict(c), "lr_rules": {}, "momentum_rules": {}}
+    for b in c.batches:
+        for lr_rule in ("constant", "sqrt", "linear"):
+            lr6, x1, x2 = rule_hparams(base.lr, b1, b2, b, lr_rule, "exp")
+            d = Runner(P_pre, cams, images, b, lr6, x1, x2).run(seq)[DC] - P_pre[DC]
+            res["lr_rules"].setdefault(lr_rule, {})[b] = _compare(d, ref)
+        lr6, x1, x2 = rule_hparams(base.lr, b1, b2, b, "sqrt", "unchanged")
+        d = Runner(P_pre, cams, images, b, lr6, x1, x2).run(seq)[DC] - P_pre[DC]
+        res["momentum_rules"].setdefault("unchanged", {})[b] = _compare(d, ref)
+        res["momentum_rules"].setdefault("exp", {})[b] = res["lr_rules"]["sqrt"][b]
+        log(f"b={b}: " + json.dumps({k: v[b] for k, v in res["lr_rules"].items()}))
+    res["gradient_precision"] = gradient_precision(P_pre, cams, images, c)
+    res["seconds"] = round(time.perf_counter() - t0, 1)
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--small", action="store_true", help="a reduced configuration (tests)")
+    args = ap.parse_args(argv)
+    R.init(0)
+    c = StudyConfig()
+    if args.small:
+        c = StudyConfig(gaussians=30_000, views=16, res=96, pretrain_steps=40, images=32, batches=(8,),
+                        variance_batches=(1, 4, 8), variance_trials=8)
+    res = run_study(c, log=lambda s: print(s, file=sys.stderr, flush=True))
+    text = json.dumps(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+    return res
+
+
+if __name__ == "__main__":
+    main()

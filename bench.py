@@ -118,6 +118,11 @@ def dssim_side(tr, P, cams_list, targets, steps: int, warmup: int, lam: float = 
     from paper_2406_18533_amd import train
     buf = R.DssimBuffers(tr.cams)
     R.gs_loss_l1_dssim(tr.rgb, tr.targets, tr.cams, buf, lam=lam)
+    c0 = tr.cams.dicts[0]
+    per = 3 * c0["width"] * c0["height"]
+    shape = (3, c0["height"], c0["width"])
+    sample = (tr.rgb[:per].double().cpu().numpy().reshape(shape),
+              tr.targets[:per].double().cpu().numpy().reshape(shape), tr.V)
     reps = 10
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
@@ -144,7 +149,7 @@ def dssim_side(tr, P, cams_list, targets, steps: int, warmup: int, lam: float = 
            "loss_bytes": nbytes, "loss_GBps": round(gbs, 1), "loss_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
            "loss_traffic": measured_traffic("gs_loss_l1_dssim")}
     del t2
-    return out
+    return out, sample
 
 
 def densify_side(tr, reps: int = 5):
@@ -186,15 +191,19 @@ def densify_side(tr, reps: int = 5):
         if _:
             t_plan += ev[0].elapsed_time(ev[1]) / reps
             t_apply += ev[2].elapsed_time(ev[3]) / reps
+    sample = {"P": tr.P.double().cpu().numpy(), "m": tr.m.double().cpu().numpy(), "v": tr.v.double().cpu().numpy(),
+              "accum": acc.double().cpu().numpy(), "count": cnt.cpu().numpy(),
+              "noise": noise.double().cpu().numpy(),
+              "hp": (h.grad_threshold, h.split_log_scale, h.prune_logit, h.prune_log_scale)}
     n, n_out = tr.n, K + C + 2 * S
     b_plan = 25 * n
     b_apply = n + 236 * n + 472 * K + 24 * S + 708 * n_out
     tr.enable_densify_stats(False)
-    return {"gaussians": n, "kept": K, "clones": C, "split_pairs": S, "output": n_out,
+    return ({"gaussians": n, "kept": K, "clones": C, "split_pairs": S, "output": n_out,
             "plan_ms": round(t_plan, 4), "apply_ms": round(t_apply, 4),
             "plan_GBps": round(b_plan / (t_plan / 1e3) / 1e9, 1),
             "apply_GBps": round(b_apply / (t_apply / 1e3) / 1e9, 1),
-            "apply_hbm_frac": round(b_apply / (t_apply / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "apply_hbm_frac": round(b_apply / (t_apply / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}, sample)
 
 
 def workload_counts(tr):
@@ -316,10 +325,13 @@ def roofline(timings: dict, counts: dict):
     return out, per
 
 
-def cpu_baseline(workload, sample_views: int = 6):
+def cpu_baseline(workload, sample_views: int = 6, side: dict | None = None):
     """The FP64 oracle on a bounded sample: the whole per-view pipeline of one
     view of the batch (transformation, binning, render, loss, render and
-    transformation backward) plus one Adam step, extrapolated to the batch."""
+    transformation backward) plus one Adam step, extrapolated to the batch.
+    With `side` (inputs the side lines captured on the GPU), also the oracle
+    of the L1 + D-SSIM loss on one view of the batch and of one
+    densification of the step's Gaussians."""
     import numpy as np
     import oracle
     P = workload.params.double().numpy()
@@ -338,10 +350,27 @@ def cpu_baseline(workload, sample_views: int = 6):
     per_view = (t1 - t0) / sample_views
     step = per_view * len(workload.cameras) + (t2 - t1)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(len(workload.cameras) / step, 5), "unit": "views/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample_views} of {len(workload.cameras)} views ({cams[0]['width']}x{cams[0]['height']}, "
-                      f"N={P.shape[1]}), full per-view pipeline in {per_view:.1f} s + Adam in {t2 - t1:.1f} s, "
-                      f"extrapolated linearly to the batch"}
+    out = {"value": round(len(workload.cameras) / step, 5), "unit": "views/s", "cores": threads, "kind": "oracle",
+           "sample": f"{sample_views} of {len(workload.cameras)} views ({cams[0]['width']}x{cams[0]['height']}, "
+                     f"N={P.shape[1]}), full per-view pipeline in {per_view:.1f} s + Adam in {t2 - t1:.1f} s, "
+                     f"extrapolated linearly to the batch"}
+    side = side or {}
+    if "dssim" in side:
+        x, y, V = side["dssim"]
+        t0 = time.perf_counter()
+        oracle.l1_dssim_loss([x], [y], 0.2)
+        dt = time.perf_counter() - t0
+        out["l1_dssim"] = {"value": round(1.0 / (dt * V), 5), "unit": "batches/s", "kind": "oracle",
+                           "sample": f"1 of {V} views ({x.shape[2]}x{x.shape[1]}): loss and gradient in {dt:.1f} s, "
+                                     f"extrapolated to the batch"}
+    if "densify" in side:
+        a = side["densify"]
+        t0 = time.perf_counter()
+        oracle.densify(a["P"], a["m"], a["v"], a["accum"], a["count"], a["noise"], *a["hp"])
+        dt = time.perf_counter() - t0
+        out["densify"] = {"value": round(a["P"].shape[1] / dt, 1), "unit": "Gaussians/s", "kind": "oracle",
+                          "sample": f"one densification of all {a['P'].shape[1]} Gaussians in {dt:.2f} s"}
+    return out
 
 
 def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, max_views: int = 8):
@@ -523,15 +552,15 @@ def main():
     counts = workload_counts(tr)
     roof, per = roofline(timings, counts)
     log(f"timings {json.dumps(timings)}")
-    dssim = None
+    dssim, side = None, {}
     if not args.no_dssim:
         log("step with the L1 + D-SSIM loss")
-        dssim = dssim_side(tr, P, w.cameras, targets, args.steps, args.warmup)
+        dssim, side["dssim"] = dssim_side(tr, P, w.cameras, targets, args.steps, args.warmup)
         log(f"l1+dssim {json.dumps(dssim)}")
     dens = None
     if not args.no_densify:
         log("densification of the step's Gaussians")
-        dens = densify_side(tr)
+        dens, side["densify"] = densify_side(tr)
         log(f"densify {json.dumps(dens)}")
     plain = None
     if not args.no_plain:
@@ -564,7 +593,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline (sample)")
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(w, side=side)
     if args.copy_mib:
         log(f"calibration: fill then copy of {args.copy_mib} MiB")
         a = torch.empty(args.copy_mib * 2 ** 18, dtype=torch.float32, device="cuda")

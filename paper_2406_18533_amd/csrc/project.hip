@@ -30,6 +30,16 @@ template <typename T> __device__ __forceinline__ Camera<T> load_camera(const gs_
     return k;
 }
 
+// The cameras of the launch in the kernels' precision, formed once per
+// workgroup into LDS (the conversions from the double-precision camera
+// structs and the camera centres are wave-uniform work that every thread
+// would otherwise repeat for every view). Must be reached by all threads.
+template <typename T> __device__ __forceinline__ void stage_cameras(Camera<T> *cs, const gs_camera *cams, int views)
+{
+    if ((int)threadIdx.x < views) cs[threadIdx.x] = load_camera<T>(cams + threadIdx.x);
+    __syncthreads();
+}
+
 // View-independent part: scale, rotation, opacity and the factor
 // M = R(q) diag(s) of the 3D covariance Sigma = M M^T.
 template <typename T> struct Shape {
@@ -196,6 +206,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
                                                           const gs_camera *__restrict__ cams, int32_t views,
                                                           T *__restrict__ out)
 {
+    __shared__ Camera<T> cs[MAXV];
+    stage_cameras(cs, cams, views);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     T x[3] = {P[i], P[n + i], P[2 * n + i]};
@@ -203,9 +215,9 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
     // Cheap pre-test on the mean alone: in front of some camera's near plane?
     bool any_front = false;
     for (int v = 0; v < views && xok; v++) {
-        const gs_camera *c = cams + v;
-        T z = (T)c->R[6] * x[0] + (T)c->R[7] * x[1] + (T)c->R[8] * x[2] + (T)c->t[2];
-        any_front |= z > (T)c->znear;
+        const Camera<T> &c = cs[v];
+        T z = c.R[6] * x[0] + c.R[7] * x[1] + c.R[8] * x[2] + c.t[2];
+        any_front |= z > c.znear;
     }
     Shape<T> S;
     if (any_front) make_shape(P, n, i, S);
@@ -217,7 +229,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
     uint64_t *rect_out = side_rect<T>(out, vn);
     for (int v = 0; v < views; v++) {
         V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
-        Camera<T> k = load_camera<T>(cams + v);
+        const Camera<T> &k = cs[v];
         Geo<T> g;
         make_geo(x, S, k, g);
         tiles_out[(int64_t)v * n + i] = g.visible ? (uint32_t)g.tiles : 0u;
@@ -242,7 +254,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
     for (int v = 0; v < views; v++) {
         if (!((need_colour >> v) & 1ull)) continue;
         V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
-        Camera<T> k = load_camera<T>(cams + v);
+        const Camera<T> &k = cs[v];
         Geo<T> g;
         make_geo(x, S, k, g);
         T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
@@ -290,7 +302,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
 // opacity logit).
 template <typename T>
 __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, int64_t i, const T x[3],
-                                           const gs_camera *__restrict__ cams, int32_t views, uint64_t vis,
+                                           const Camera<T> *cs, int32_t views, uint64_t vis,
                                            const T *__restrict__ dproj, T gpos[3], T g8[8])
 {
     Shape<T> S;
@@ -301,7 +313,7 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
         const V4<T> *dr = reinterpret_cast<const V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
         V4<T> d0 = dr[0], d1 = dr[1];
         T du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x, dop = d1.y;
-        Camera<T> k = load_camera<T>(cams + v);
+        const Camera<T> &k = cs[v];
         Geo<T> g;
         make_geo(x, S, k, g);
         T iz = g.iz, iz2 = iz * iz;
@@ -375,6 +387,8 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
                                                           const T *__restrict__ proj, T *__restrict__ dproj, int clear,
                                                           T *__restrict__ grad, AdamRef<T> ad)
 {
+    __shared__ Camera<T> cs[MAXV];
+    stage_cameras(cs, cams, views);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     uint64_t vis = 0;
@@ -396,7 +410,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
     T gpos[3] = {T(0), T(0), T(0)};
     {
         T g8[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-        if (seen) geom_grads(P, n, i, x, cams, views, vis, dproj, gpos, g8);
+        if (seen) geom_grads(P, n, i, x, cs, views, vis, dproj, gpos, g8);
         if (!ADAM) {
             for (int r = 0; r < 8; r++) grad[(3 + r) * n + i] += g8[r];
         } else {
@@ -417,10 +431,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
             if (!((vis >> v) & 1ull)) continue;
             const T *dr = dproj + ((int64_t)v * n + i) * REC;
             T drgb[3] = {dr[D_RGB], dr[D_RGB + 1], dr[D_RGB + 2]};
-            const gs_camera *cm = cams + v;
-            T cen[3];
-            for (int j = 0; j < 3; j++)
-                cen[j] = (T)(-(cm->R[j] * cm->t[0] + cm->R[3 + j] * cm->t[1] + cm->R[6 + j] * cm->t[2]));
+            const T *cen = cs[v].cen;
             T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
             T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};

@@ -108,17 +108,18 @@ def test_edge_cases():
     assert c == (4000, 4000, 0)
 
 
-def test_stats_match_oracle():
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_stats_match_oracle(dtype):
     from paper_2406_18533_amd import raster as R
     V, n = 5, 7001
     g = torch.Generator().manual_seed(5)
-    proj = R.alloc_projected(n, V)
+    proj = R.alloc_projected(n, V, dtype)
     tiles, _ = R.projected_side_arrays(proj)
     vis = torch.rand(V, n, generator=g) < 0.4
     tiles.copy_((vis.int() * torch.randint(1, 9, (V, n), generator=g, dtype=torch.int32)).cuda())
-    dproj = torch.zeros(V, n, 12)
-    dproj[..., 0] = torch.randn(V, n, generator=g) * 1e-3
-    dproj[..., 1] = torch.randn(V, n, generator=g) * 1e-3
+    dproj = torch.zeros(V, n, 12, dtype=dtype)
+    dproj[..., 0] = (torch.randn(V, n, generator=g) * 1e-3).to(dtype)
+    dproj[..., 1] = (torch.randn(V, n, generator=g) * 1e-3).to(dtype)
     dproj = dproj.cuda()
     accum = torch.full((n,), 0.25, device="cuda")
     count = torch.full((n,), 2, dtype=torch.int32, device="cuda")
@@ -130,9 +131,10 @@ def test_stats_match_oracle():
     assert np.allclose(accum.cpu().double().numpy(), a + 0.25, rtol=1e-6, atol=0)
 
 
-def test_reset_opacity_matches_oracle():
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_reset_opacity_matches_oracle(dtype):
     from paper_2406_18533_amd import raster as R
-    P, m, v, *_ = _params(3001, 6)
+    P, m, v, *_ = _params(3001, 6, dtype)
     cap = float(np.float32(math.log(0.01 / 0.99)))            # representable: exact comparison
     Pc, mc, vc = P.cuda(), m.cuda(), v.cuda()
     R.gs_reset_opacity(Pc, mc, vc, cap)

@@ -38,7 +38,8 @@ def lib():
         L.oracle_tiles_touched.restype = i64
         L.oracle_bin.argtypes = [d, d, d, d, i64, i32, d, d, i64, d, d, d]
         L.oracle_bin.restype = i64
-        L.oracle_render.argtypes = [d, i64, i32, i32, d, d, d, d, i32, C.c_double, C.c_double, d, d, d, d, d, d]
+        L.oracle_render.argtypes = [d, i64, i32, i32, d, d, d, d, i32, C.c_double, C.c_double, d, d, d, d, d, d,
+                                    d, d, d]
         L.oracle_render_brute.argtypes = [d, i64, i32, i32, d, d, d, d]
         L.oracle_render_bwd.argtypes = [d, i64, i32, i32, d, d, d, d, d]
         L.oracle_render_bwd.restype = C.c_int
@@ -138,7 +139,14 @@ def bin_sort(u, v, r, depth, cams: list):
 def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, depth_check=False,
            pos_tol: float = 0.0, t_tol: float = 1e-5) -> dict:
     """Tiled render of one view from projected fields [ONF][N] (FP64).
-    fragile/depth_check/pos_tol/t_tol only widen the ambiguity flags."""
+
+    "amb" classifies each pixel by the decisions of its walk (circle test,
+    exponent sign, alpha >= 1/255, transmittance stop) that lie within
+    rounding of their thresholds, where a lower-precision implementation may
+    rightly take either branch: 0 none; 1 exactly one, and "rgb_alt",
+    "T_alt", "last_alt" hold the result with that decision taken the other
+    way; 2 more than one, or two contributors whose depth order is a near
+    tie. fragile/depth_check/pos_tol/t_tol only widen those margins."""
     proj = _f64(proj)
     N = proj.shape[1]
     W, H = cam["width"], cam["height"]
@@ -148,15 +156,45 @@ def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, 
     rgb = np.zeros((3, H, W))
     T = np.zeros((H, W))
     last = np.zeros((H, W), dtype=np.uint32)
+    rgb_alt = np.zeros((3, H, W))
+    T_alt = np.zeros((H, W))
+    last_alt = np.zeros((H, W), dtype=np.uint32)
     nc = np.zeros((H, W), dtype=np.uint32)
     amb = np.zeros((H, W), dtype=np.uint8)
     counts = np.zeros(2, dtype=np.int64)
     fr = None if fragile is None else np.ascontiguousarray(fragile, dtype=np.uint8)
     lib().oracle_render(_p(proj), N, W, H, _p(ids) if ids.size else None, _p(ranges_view), _p(bgv),
                         _p(fr) if fr is not None else None, int(depth_check), float(pos_tol), float(t_tol),
-                        _p(rgb), _p(T), _p(last), _p(nc), _p(amb), _p(counts))
+                        _p(rgb), _p(T), _p(last), _p(nc), _p(amb), _p(counts), _p(rgb_alt), _p(T_alt), _p(last_alt))
     return {"rgb": rgb, "T": T, "last": last, "ncontrib": nc, "amb": amb,
+            "rgb_alt": rgb_alt, "T_alt": T_alt, "last_alt": last_alt,
             "evaluated": int(counts[0]), "blended": int(counts[1])}
+
+
+def image_mismatch(o: dict, rgb, T=None, last=None, tol: float = 1e-5):
+    """Compares another implementation's image of one view with an oracle
+    render ``o``. A pixel with no ambiguous decision must match the oracle's
+    result; one with exactly one must match either branch (its colour, and T
+    and last when given, all from the same branch); pixels of class 2 are
+    left out. Returns (max error over the compared pixels, mask of those
+    pixels, number of class-1 pixels that matched the alternative)."""
+    rgb = np.asarray(rgb, dtype=np.float64)
+
+    def err(ref_rgb, ref_T, ref_last):
+        e = np.max(np.abs(rgb - ref_rgb), axis=0)
+        if T is not None:
+            e = np.maximum(e, np.abs(np.asarray(T, dtype=np.float64) - ref_T))
+        if last is not None:
+            e = np.where(np.asarray(last).view(np.uint32) == ref_last, e, np.inf)
+        return e
+
+    e0 = err(o["rgb"], o["T"], o["last"])
+    e1 = err(o["rgb_alt"], o["T_alt"], o["last_alt"])
+    cls = o["amb"]
+    e = np.where(cls == 0, e0, np.minimum(e0, e1))
+    compared = cls <= 1
+    took_alt = int(((cls == 1) & (e1 < e0) & (e1 <= tol)).sum())
+    return float(np.max(e[compared], initial=0.0)), compared, took_alt
 
 
 def render_brute(proj, cam: dict, bg=(0.0, 0.0, 0.0)) -> dict:

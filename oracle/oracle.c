@@ -413,40 +413,64 @@ int64_t oracle_bin(const float *u, const float *v, const float *r, const float *
 typedef struct {
     int inside;    /* passes the circle test and power <= 0 */
     double dx, dy, G, og, alpha;
-    int amb;       /* a decision within rounding of its threshold */
 } pair_t;
 
-/* Ambiguity margins. A decision is flagged when the quantity it compares is
- * within rounding of its threshold: pos_tol (pixels) bounds how far the
+/* Ambiguity margins. A decision is ambiguous when the quantity it compares
+ * is within rounding of its threshold: pos_tol (pixels) bounds how far the
  * compared implementation's projected centre may sit from this one's (0
  * when both render the same projected records). */
 typedef struct { double pos_tol, t_tol; } tol_t;
 
-/* One (pixel, Gaussian) pair. proj is planar [ONF][N]. */
-static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py, const tol_t *tol, pair_t *e)
+/* The binary decisions of one pixel's walk (circle, exponent sign, alpha
+ * threshold, transmittance stop) that fall within rounding of their
+ * thresholds. An implementation in lower precision may take either branch
+ * of such a decision and still be right, so the walk can be re-run with the
+ * flip_at-th ambiguous decision taken the other way; count is the number of
+ * ambiguous decisions met, unresolved is set by an ambiguity that a single
+ * flip does not describe (two contributors whose depth order may differ). */
+typedef struct { int count, flip_at, unresolved; } amb_t;
+
+static int decide(amb_t *am, int outcome, int ambiguous)
+{
+    if (!am || !ambiguous) return outcome;
+    int k = am->count++;
+    return k == am->flip_at ? !outcome : outcome;
+}
+
+/* One (pixel, Gaussian) pair. proj is planar [ONF][N]. fragile (nullable):
+ * the Gaussian's radius may round to the next integer in the compared
+ * implementation, which moves its circle test on the annulus
+ * r - 1 <= d <= r + 1. */
+static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py, const tol_t *tol, int fragile,
+                      amb_t *am, pair_t *e)
 {
     double u = proj[0 * N + id], v = proj[1 * N + id], r = proj[10 * N + id];
     double a = proj[3 * N + id], b = proj[4 * N + id], c = proj[5 * N + id], o = proj[6 * N + id];
     double pt = tol ? tol->pos_tol : 0.0;
-    e->amb = 0;
     e->inside = 0;
     e->dx = px + 0.5 - u;
     e->dy = py + 0.5 - v;
     double d2 = e->dx * e->dx + e->dy * e->dy, r2 = r * r;
-    if (fabs(d2 - r2) <= 1e-6 * (r2 > 1.0 ? r2 : 1.0) + 2.0 * r * pt + pt * pt) e->amb = 1;
-    if (d2 > r2) return;
+    int amb = fabs(d2 - r2) <= 1e-6 * (r2 > 1.0 ? r2 : 1.0) + 2.0 * r * pt + pt * pt;
+    if (fragile) {
+        /* the unrounded radius sits near the integer m, so the other side
+         * may hold m or m + 1: the circle test differs on m <= d <= m + 1 */
+        double m = nearbyint(proj[11 * N + id]);
+        if (d2 >= m * m && d2 <= (m + 1.0) * (m + 1.0)) amb = 1;
+    }
+    if (!decide(am, d2 <= r2, amb)) return;
     double qa = 0.5 * a * e->dx * e->dx, qc = 0.5 * c * e->dy * e->dy, qb = b * e->dx * e->dy;
     double power = -qa - qc - qb;
-    if (fabs(power) <= 1e-6 * (fabs(qa) + fabs(qb) + fabs(qc)) && (qa + qc) > 0.0) e->amb = 1;
-    if (power > 0.0) return;
+    amb = fabs(power) <= 1e-6 * (fabs(qa) + fabs(qb) + fabs(qc)) && (qa + qc) > 0.0;
+    if (!decide(am, power <= 0.0, amb)) return;
     e->G = exp(power);
     e->og = o * e->G;
     e->alpha = e->og < ALPHA_MAX ? e->og : ALPHA_MAX;
     /* alpha threshold in the log domain: rounding of the exponent, plus the
      * exponent's change when the centre moves by pos_tol */
     double lmargin = 1e-5 + 1e-5 * fabs(power) + 2.0 * sqrt(fabs(power) * (a + c)) * pt;
-    if (fabs(log(e->alpha / ALPHA_MIN)) <= lmargin) e->amb = 1;
-    if (e->alpha < ALPHA_MIN) return;
+    amb = fabs(log(e->alpha / ALPHA_MIN)) <= lmargin;
+    if (!decide(am, e->alpha >= ALPHA_MIN, amb)) return;
     e->inside = 1;
 }
 
@@ -461,56 +485,71 @@ static int depth_near(const double *proj, int64_t N, uint32_t i0, uint32_t i1)
 }
 
 /* Forward composition of one pixel over list[0..n). Writes colour, T, the
- * position after the last blended entry, the number blended, and flags. */
+ * position after the last blended entry, the number blended and the number
+ * of entries evaluated; am (nullable) tracks and flips ambiguous decisions. */
 static void composite_pixel(const double *proj, int64_t N, const uint32_t *list, int64_t n, int px, int py,
                             const double *bg, const uint8_t *fragile, int depth_check, const tol_t *tol,
-                            double out[3], double *Tout, uint32_t *last, uint32_t *ncontrib,
-                            uint8_t *amb, int64_t *evaluated)
+                            amb_t *am, double out[3], double *Tout, uint32_t *last, uint32_t *ncontrib,
+                            int64_t *evaluated)
 {
     double T = 1.0, C[3] = {0, 0, 0};
     uint32_t lastp = 0, nc = 0;
     int64_t prev = -1;
-    uint8_t am = 0;
     int64_t ev = 0;
     for (int64_t k = 0; k < n; k++) {
-        uint32_t id = list[k];
-        pair_t e;
-        eval_pair(proj, N, id, px, py, tol, &e);
-        ev++;
-        if (e.amb) am = 1;
-        if (fragile && fragile[id]) {
-            /* an FP32 radius one off changes the circle test only on this annulus */
-            double r = proj[10 * N + id], d2 = e.dx * e.dx + e.dy * e.dy;
-            if (d2 >= (r - 1.0) * (r - 1.0) && d2 <= (r + 1.0) * (r + 1.0)) am = 1;
+        /* two adjacent entries of the list that both reach this pixel and
+         * whose FP32 depths nearly tie: the compared implementation (which
+         * rounds its own depths) may hold them in the other order */
+        int swap = 0;
+        if (am && depth_check && k + 1 < n && depth_near(proj, N, list[k], list[k + 1])) {
+            pair_t t0, t1;
+            eval_pair(proj, N, list[k], px, py, tol, fragile ? fragile[list[k]] : 0, NULL, &t0);
+            eval_pair(proj, N, list[k + 1], px, py, tol, fragile ? fragile[list[k + 1]] : 0, NULL, &t1);
+            if (t0.inside && t1.inside) swap = decide(am, 0, 1);
         }
-        if (!e.inside) continue;
-        double Tn = T * (1.0 - e.alpha);
-        if (fabs(Tn - T_MIN) <= (tol ? tol->t_tol : 1e-5) * T_MIN) am = 1;
-        if (Tn < T_MIN) break;
-        if (depth_check && prev >= 0 && depth_near(proj, N, (uint32_t)prev, id)) am = 1;
-        for (int ch = 0; ch < 3; ch++) C[ch] += proj[(7 + ch) * N + id] * e.alpha * T;
-        T = Tn;
-        lastp = (uint32_t)(k + 1);
-        nc++;
-        prev = id;
+        int stop = 0;
+        for (int s = 0; s <= swap && !stop; s++) {
+            int64_t pos = k + s;
+            uint32_t id = list[swap ? k + 1 - s : k];
+            pair_t e;
+            eval_pair(proj, N, id, px, py, tol, fragile ? fragile[id] : 0, am, &e);
+            ev++;
+            if (!e.inside) continue;
+            double Tn = T * (1.0 - e.alpha);
+            int amb = fabs(Tn - T_MIN) <= (tol ? tol->t_tol : 1e-5) * T_MIN;
+            if (decide(am, Tn < T_MIN, amb)) { stop = 1; break; }
+            /* a near tie with a contributor that is not the adjacent entry */
+            if (am && depth_check && prev >= 0 && (int64_t)lastp != pos && depth_near(proj, N, (uint32_t)prev, id))
+                am->unresolved = 1;
+            for (int ch = 0; ch < 3; ch++) C[ch] += proj[(7 + ch) * N + id] * e.alpha * T;
+            T = Tn;
+            lastp = (uint32_t)(pos + 1);
+            nc++;
+            prev = id;
+        }
+        if (stop) break;
+        k += swap;
     }
     for (int ch = 0; ch < 3; ch++) out[ch] = C[ch] + T * bg[ch];
     *Tout = T;
     *last = lastp;
     *ncontrib = nc;
-    *amb = am;
     *evaluated = ev;
 }
 
 /* Tiled render of one view. proj: [ONF][N] of this view; ids/ranges: the
  * sorted instances and the view's slice of per-tile [start, end) ranges
  * (T_view entries, positions index ids). Outputs are planar [3][H][W] colour,
- * [H][W] transmittance, last position, contributor count, ambiguity flag.
- * counts[0] = list entries evaluated, counts[1] = blended pairs. */
+ * [H][W] transmittance, last position, contributor count and ambiguity class:
+ * 0 no decision within rounding of its threshold; 1 exactly one, and the
+ * nullable alternative outputs (rgb_alt, T_alt, last_alt) hold the walk with
+ * that decision taken the other way; 2 more than one, or a depth-order tie.
+ * counts[0] = list entries evaluated, counts[1] = blended pairs (nominal walk). */
 int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uint32_t *ids,
                   const uint32_t *ranges, const double *bg, const uint8_t *fragile, int32_t depth_check,
                   double pos_tol, double t_tol,
-                  double *rgb, double *Tout, uint32_t *last, uint32_t *ncontrib, uint8_t *amb, int64_t *counts)
+                  double *rgb, double *Tout, uint32_t *last, uint32_t *ncontrib, uint8_t *amb, int64_t *counts,
+                  double *rgb_alt, double *T_alt, uint32_t *last_alt)
 {
     tol_t tol = {pos_tol, t_tol};
     int64_t TX = tiles_of(W), TY = tiles_of(H);
@@ -523,18 +562,35 @@ int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uin
             for (int px = tx * TILE; px < tx * TILE + TILE && px < W; px++) {
                 double c[3], T;
                 uint32_t l, nc;
-                uint8_t a;
                 int64_t ev;
-                composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, &tol, c, &T, &l, &nc, &a,
-                                &ev);
+                amb_t am = {0, -1, 0};
+                composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, &tol, &am, c, &T, &l,
+                                &nc, &ev);
                 int64_t p = (int64_t)py * W + px;
                 for (int ch = 0; ch < 3; ch++) rgb[(int64_t)ch * W * H + p] = c[ch];
                 Tout[p] = T;
                 last[p] = l;
                 if (ncontrib) ncontrib[p] = nc;
-                if (amb) amb[p] = a;
                 ev_total += ev;
                 nc_total += nc;
+                uint8_t cls = am.unresolved || am.count > 1 ? 2 : (uint8_t)am.count;
+                double ca[3] = {c[0], c[1], c[2]}, Ta = T;
+                uint32_t la = l;
+                if (cls == 1) {
+                    /* the other branch of the one ambiguous decision; it is
+                     * a single alternative only if that walk meets no other */
+                    amb_t alt = {0, 0, 0};
+                    uint32_t nca;
+                    int64_t eva;
+                    composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, &tol, &alt, ca, &Ta,
+                                    &la, &nca, &eva);
+                    if (alt.unresolved || alt.count > 1) cls = 2;
+                }
+                if (amb) amb[p] = cls;
+                if (rgb_alt)
+                    for (int ch = 0; ch < 3; ch++) rgb_alt[(int64_t)ch * W * H + p] = ca[ch];
+                if (T_alt) T_alt[p] = Ta;
+                if (last_alt) last_alt[p] = la;
             }
     }
     if (counts) { counts[0] = ev_total; counts[1] = nc_total; }
@@ -572,9 +628,8 @@ int oracle_render_brute(const double *proj, int64_t N, int32_t W, int32_t H, con
         int px = (int)(p % W), py = (int)(p / W);
         double c[3], T;
         uint32_t l, nc;
-        uint8_t a;
         int64_t ev;
-        composite_pixel(proj, N, order, n, px, py, bg, NULL, 0, NULL, c, &T, &l, &nc, &a, &ev);
+        composite_pixel(proj, N, order, n, px, py, bg, NULL, 0, NULL, NULL, c, &T, &l, &nc, &ev);
         for (int ch = 0; ch < 3; ch++) rgb[(int64_t)ch * W * H + p] = c[ch];
         Tout[p] = T;
         if (ncontrib) ncontrib[p] = nc;
@@ -624,7 +679,7 @@ int oracle_render_bwd(const double *proj, int64_t N, int32_t W, int32_t H, const
                 int64_t nr = 0;
                 for (int64_t k = s; k < e; k++) {
                     pair_t pe;
-                    eval_pair(proj, N, ids[k], px, py, NULL, &pe);
+                    eval_pair(proj, N, ids[k], px, py, NULL, 0, NULL, &pe);
                     if (!pe.inside) continue;
                     double Tn = T * (1.0 - pe.alpha);
                     if (Tn < T_MIN) break;

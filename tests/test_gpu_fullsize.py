@@ -75,14 +75,16 @@ def test_fullsize_bins_and_images_of_sampled_views(batch):
         assert (rv[nonempty] - start == ranges_o[nonempty]).all()
         assert (rv[~nonempty, 1] == rv[~nonempty, 0]).all()
         assert (ids_g[start:start + ids_o.size] == ids_o).all()
-        # image at the pixels the oracle does not flag as a threshold near-tie
+        # image, T and last at every pixel (one near-threshold decision: either branch)
         o = oracle.render(oracle_proj_from_gpu(pf, v), cam, ids_o, ranges_o, tr.cfg.bg)
-        ok = o["amb"] == 0
         img = rgb[sl3[v][0]:sl3[v][1]].reshape(3, H, W)
-        assert np.max(np.abs(img - o["rgb"])[:, ok]) <= 1e-5
-        assert np.max(np.abs(T[sl1[v][0]:sl1[v][1]].reshape(H, W) - o["T"])[ok]) <= 1e-5
-        assert (last[sl1[v][0]:sl1[v][1]].reshape(H, W)[ok] == o["last"][ok]).all()
-        assert (~ok).sum() <= max(4, 2e-3 * ok.size), (~ok).sum()
+        err, compared, took_alt = oracle.image_mismatch(o, img, T[sl1[v][0]:sl1[v][1]].reshape(H, W),
+                                                        last[sl1[v][0]:sl1[v][1]].reshape(H, W))
+        one = int((o["amb"] == 1).sum())
+        print(f"1080p view {v}: max err {err:.2e}; one near-threshold decision {one} ({one / compared.size:.2e}, "
+              f"{took_alt} matched its other branch), excluded {int((~compared).sum())}", flush=True)
+        assert err <= 1e-5
+        assert (~compared).sum() <= 1e-4 * compared.size, (~compared).sum()
         # image gradient of the fused loss: sign(rgb - target) / (3 H W views), in FP32
         wgt = np.float32(1.0 / (3.0 * H * W * len(cams)))
         d = img.reshape(-1) - tgt[sl3[v][0]:sl3[v][1]]

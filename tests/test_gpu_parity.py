@@ -3,10 +3,12 @@
 Tolerances (FP32 kernels against the FP64 oracle):
   - binning: keys (tile << 32 | FP32 depth bits), ids and ranges bit-exact,
     the oracle binning the GPU's own FP32 (u, v, radius, depth);
-  - images: max |difference| <= 1e-5 over pixels the oracle does not flag as
-    ambiguous (a threshold decision within rounding distance), flagged pixels
-    at most 2e-3 of all with the GPU's own projection (render-only), 4% end
-    to end (10% for the needle scene);
+  - images: max |difference| <= 1e-5 at every pixel whose walk has at most
+    one decision within rounding of its threshold (against the oracle's
+    result with that decision taken either way); pixels with more (class 2)
+    are left out, counted and printed: none may remain when both sides
+    render the GPU's projection (render-only), at most 1e-3 of the pixels end
+    to end, where the two sides render different projections;
   - gradients: ||g - g_oracle|| / ||g_oracle|| <= 1e-3 per parameter group.
 """
 import math
@@ -160,24 +162,26 @@ def test_bin_sort_bit_exact_many_tiles_per_view(w, h):
 
 
 # ----------------------------------------------------------------------------- render forward
-def _render_parity(f, P, cams, gp):
+def _render_parity(f, P, cams, gp, name):
     pf = gp.proj_fields(f["proj"])
     keys_o, ids_o, ranges_o = gp.bins_numpy(f)
     base = oracle.tile_base(cams)
     rgb_g = gp.split_views(f["rgb"], cams, 3)
     T_g = gp.split_views(f["T"], cams, 1)
     last_g = gp.split_views(f["last"], cams, 1)
-    amb_total = pix_total = 0
+    excluded = one = alt = pix_total = 0
     for v, cam in enumerate(cams):
         pr = oracle_proj_from_gpu(pf, v)
         o = oracle.render(pr, cam, ids_o, ranges_o[base[v]:base[v + 1]], BG)
-        ok = o["amb"] == 0
-        amb_total += (~ok).sum()
-        pix_total += ok.size
-        assert np.max(np.abs(rgb_g[v] - o["rgb"])[:, ok]) <= 1e-5
-        assert np.max(np.abs(T_g[v] - o["T"])[ok]) <= 1e-5
-        assert (last_g[v].view(np.uint32)[ok] == o["last"][ok]).all()
-    assert amb_total <= max(4, 2e-3 * pix_total), (amb_total, pix_total)
+        err, compared, took_alt = oracle.image_mismatch(o, rgb_g[v], T_g[v], last_g[v])
+        assert err <= 1e-5, (v, err)
+        excluded += int((~compared).sum())
+        one += int((o["amb"] == 1).sum())
+        alt += took_alt
+        pix_total += compared.size
+    print(f"render-only {name}: {pix_total} px, one near-threshold decision {one} ({one / pix_total:.2e}, "
+          f"{alt} matched its other branch), excluded {excluded} ({excluded / pix_total:.2e})", flush=True)
+    assert excluded == 0
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
@@ -185,7 +189,7 @@ def test_render_fwd_matches_oracle(name):
     gp = _gp()
     P, cams = WORKLOADS[name]()
     f = gp.forward(gp.to_dev(P), cams, BG)
-    _render_parity(f, P, cams, gp)
+    _render_parity(f, P, cams, gp, name)
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
@@ -194,26 +198,26 @@ def test_end_to_end_images_match_oracle(name):
     gp = _gp()
     P, cams = WORKLOADS[name]()
     f = gp.forward(gp.to_dev(P), cams, BG)
-    # flags widened by the FP32 projection's error (centres within 5e-7 of
-    # the image size, transmittance threshold to 1e-3 relative)
+    # margins widened by the FP32 projection's error (centres within 5e-7 of
+    # the image size, transmittance threshold to 1e-3 relative, radii within
+    # 1e-5 of an integer, FP32 depths within 2 ulps)
     o = oracle.forward(P.double(), cams, BG, fragile_tol=1e-5, pos_rel=5e-7, t_tol=1e-3)
     rgb_g = gp.split_views(f["rgb"], cams, 3)
-    amb = 0
+    excluded = one = alt = 0
     for v in range(len(cams)):
-        ok = o["views"][v]["amb"] == 0
-        amb += (~ok).sum()
-        err = np.abs(rgb_g[v] - o["views"][v]["rgb"])
-        assert np.max(err[:, ok]) <= 1e-5
-        # flagged pixels: one Gaussian may switch on or off at its alpha or
-        # radius threshold, so they still agree to within a small blend
-        assert np.max(err, initial=0.0) <= 0.05
-    # flagged: pixels on the rim of a Gaussian whose FP64 radius is within 1e-5
-    # of an integer, with two consecutive contributors <= 2 FP32 ulps apart in
-    # depth, or with a decision within the projection's error of a threshold:
-    # about 1-3% of the pixels of these small, dense views; thin needle
-    # footprints are the worst conditioned (a centre offset moves a whole edge)
-    frac = 0.10 if name == "needles" else 0.04
-    assert amb <= max(8, frac * sum(c["width"] * c["height"] for c in cams)), amb
+        ov = o["views"][v]
+        err, compared, took_alt = oracle.image_mismatch(ov, rgb_g[v])
+        assert err <= 1e-5, (v, err)
+        # excluded pixels: two or more near-ties, each of which moves the
+        # pixel by at most one Gaussian's blend
+        assert np.max(np.abs(rgb_g[v] - ov["rgb"]), initial=0.0) <= 0.05
+        excluded += int((~compared).sum())
+        one += int((ov["amb"] == 1).sum())
+        alt += took_alt
+    total = sum(c["width"] * c["height"] for c in cams)
+    print(f"end-to-end {name}: {total} px, one near-threshold decision {one} ({one / total:.2e}, {alt} matched its "
+          f"other branch), excluded {excluded} ({excluded / total:.2e})", flush=True)
+    assert excluded <= max(4, 1e-3 * total), excluded
 
 
 # ----------------------------------------------------------------------------- backward
@@ -248,10 +252,14 @@ def test_render_bwd_matches_oracle(name):
     for v, cam in enumerate(cams):
         go_iso += oracle.project_bwd(P.double(), cam, dpg[v][:, :9].T.astype(np.float64))
     gi = g_iso.double().cpu().numpy()
-    # thin needles make the conic's derivative cancel in FP32
+    kappa = footprint_condition(pf)
+    well = kappa <= 20.0
+    print(f"{name}: footprint condition max {kappa.max():.1f}, {int((~well).sum())} Gaussians above 20", flush=True)
     iso_tol = 3e-3 if name == "needles" else 1e-4
     for k, sl in GROUPS.items():
         err = np.linalg.norm(gi[sl] - go_iso[sl]) / max(np.linalg.norm(go_iso[sl]), 1e-30)
+        errw = np.linalg.norm((gi[sl] - go_iso[sl])[:, well]) / max(np.linalg.norm(go_iso[sl][:, well]), 1e-30)
+        print(f"{name} transformation backward {k}: {err:.2e} (condition <= 20: {errw:.2e})", flush=True)
         assert err <= iso_tol, ("transformation backward", k, err)
     # parameter gradients: the oracle's whole FP64 backward from its own projection.
     # Thin needle footprints flip about 1% of pixel decisions between FP32 and
@@ -262,7 +270,19 @@ def test_render_bwd_matches_oracle(name):
     gg = grad.double().cpu().numpy()
     for k, sl in GROUPS.items():
         err = np.linalg.norm(gg[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        print(f"{name} end-to-end gradient {k}: {err:.2e}", flush=True)
         assert err <= tol, (k, err)
+
+
+def footprint_condition(pf: dict) -> np.ndarray:
+    """Per Gaussian, the largest ratio of the screen covariance's eigenvalues
+    over the views that see it (1 when none does)."""
+    a, b, c = (pf[k].astype(np.float64) for k in ("a", "b", "c"))
+    mid, hd = 0.5 * (a + c), 0.5 * (a - c)
+    root = np.sqrt(hd * hd + b * b)
+    lo = np.maximum(mid - root, 1e-30)
+    k = np.where(pf["tiles"] > 0, (mid + root) / lo, 1.0)
+    return k.max(axis=0)
 
 
 def test_diff_check_1080p_gradients_match_oracle():

@@ -87,6 +87,94 @@ def test_backward_matches_central_finite_differences(scene):
     assert checked >= 100 and skipped <= 20
 
 
+def guard_band_scene():
+    """24 large Gaussians (log-scale -1) whose centres lie outside the guard
+    band of a 64x64 view (|x/z| or |y/z| between 1.32 and 1.6 times
+    tan(half field of view), so the Jacobian point is clamped) yet whose
+    footprints reach into the image, and 16 inside it."""
+    cam = scenes.orbit_camera(64, 64, 4.0, 0.4, 0.3)
+    R, t = np.asarray(cam["R"]), np.asarray(cam["t"])
+    tx, ty = 0.5 * cam["width"] / cam["fx"], 0.5 * cam["height"] / cam["fy"]
+    rng = np.random.default_rng(31)
+    P = scenes.uniform_cube_gaussians(40, 32, torch.float64).numpy()
+    for i in range(40):
+        z = rng.uniform(3.0, 4.5)
+        if i < 24:
+            far = rng.uniform(1.32, 1.6) * rng.choice([-1.0, 1.0])
+            near = rng.uniform(-0.9, 0.9)
+            xr, yr = (far * tx, near * ty) if i % 3 else (near * tx, far * ty)
+            if i % 8 == 0:
+                yr = rng.uniform(1.32, 1.5) * rng.choice([-1.0, 1.0]) * ty   # both axes clamped
+            P[3:6, i] = rng.normal(-1.0, 0.1, 3)
+        else:
+            xr, yr = rng.uniform(-0.9, 0.9) * tx, rng.uniform(-0.9, 0.9) * ty
+            P[3:6, i] = rng.normal(-2.5, 0.3, 3)
+        P[0:3, i] = R.T @ (np.array([xr * z, yr * z, z]) - t)
+    return P, cam, (1.3 * tx, 1.3 * ty)
+
+
+def test_guard_band_scene_really_clamps():
+    P, cam, (limx, limy) = guard_band_scene()
+    R, t = np.asarray(cam["R"]), np.asarray(cam["t"])
+    y = (R @ P[0:3]).T + t
+    out = (np.abs(y[:, 0] / y[:, 2]) > limx) | (np.abs(y[:, 1] / y[:, 2]) > limy)
+    f = oracle.forward(P, [cam], (0.1, 0.2, 0.3))
+    shown = f["proj"][0][oracle.F_RADIUS] > 0
+    tiles = oracle.tiles_touched(*(a[None] for a in oracle.rounded_for_binning(f["proj"][0])[:3]), [cam])[0]
+    assert (out & (tiles > 0)).sum() >= 16 and (f["views"][0]["ncontrib"] > 0).mean() > 0.3
+    assert shown.all()
+
+
+def test_guard_band_gradient_matches_dense_autograd():
+    """torch autograd of the dense formulation, whose torch.clamp passes no
+    gradient through a clamped coordinate, on a scene where 24 Gaussians are
+    clamped: 1e-9 per parameter group."""
+    Pn, cam, _ = guard_band_scene()
+    bg = (0.1, 0.2, 0.3)
+    P = torch.from_numpy(Pn).clone().requires_grad_(True)
+    pr = dense.project(P, cam)
+    img, _ = dense.render(pr, cam, bg)
+    G = torch.from_numpy(np.random.default_rng(33).normal(size=img.shape))
+    (img * G).sum().backward()
+    f = oracle.forward(Pn, [cam], bg)
+    np.testing.assert_allclose(img.detach().numpy(), f["views"][0]["rgb"], atol=1e-12)
+    grad, _ = oracle.backward(Pn, [cam], f, [G.numpy()], bg)
+    ref = P.grad.numpy()
+    for name, sl in {"mean": slice(0, 3), "scale": slice(3, 6), "quat": slice(6, 10), "opacity": slice(10, 11),
+                     "sh": slice(11, 59)}.items():
+        err = np.linalg.norm(grad[sl] - ref[sl]) / max(np.linalg.norm(ref[sl]), 1e-300)
+        assert err < 1e-9, (name, err)
+
+
+def test_guard_band_gradient_matches_central_differences():
+    """Central differences (h = 1e-6, FP64, branch-stable coordinates) of
+    the clamped Gaussians' positions: the clamped coordinate stays at the
+    band's edge under the perturbation, so a gradient through it would show."""
+    P, cam, (limx, limy) = guard_band_scene()
+    bg = (0.0, 0.0, 0.0)
+    G = np.random.default_rng(34).normal(size=(3, cam["height"], cam["width"]))
+    f = oracle.forward(P, [cam], bg)
+    grad, _ = oracle.backward(P, [cam], f, [G], bg)
+    R, t = np.asarray(cam["R"]), np.asarray(cam["t"])
+    y = (R @ P[0:3]).T + t
+    out = np.nonzero((np.abs(y[:, 0] / y[:, 2]) > limx) | (np.abs(y[:, 1] / y[:, 2]) > limy))[0]
+    h = 1e-6
+    checked = 0
+    for i in out:
+        for row in (0, 1, 2, 3, 6):
+            Pp, Pm = P.copy(), P.copy()
+            Pp[row, i] += h
+            Pm[row, i] -= h
+            lp, sp = _loss(Pp, cam, G, bg)
+            lm, sm = _loss(Pm, cam, G, bg)
+            if sp != sm:
+                continue
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grad[row, i]) <= 1e-6 * max(1.0, abs(fd)), (row, i, fd, grad[row, i])
+            checked += abs(fd) > 1e-6
+    assert checked >= 40
+
+
 def test_single_gaussian_opacity_gradient_closed_form():
     """C = alpha c + (1 - alpha) bg with alpha = o G: dC/do = G (c - bg)."""
     W = H = 24

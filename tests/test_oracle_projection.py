@@ -156,6 +156,62 @@ def test_off_axis_matches_numerical_jacobian_of_pinhole():
         np.testing.assert_allclose(pr[[oracle.F_A, oracle.F_B, oracle.F_C]], [Q[0, 0], Q[0, 1], Q[1, 1]], rtol=1e-7)
 
 
+def _pinhole_jacobian(cam, p):
+    """Numerical Jacobian of (x, y, z) -> (fx x/z + cx, fy y/z + cy) at p."""
+    pin = lambda q: np.array([cam["fx"] * q[0] / q[2] + cam["cx"], cam["fy"] * q[1] / q[2] + cam["cy"]])
+    Jn = np.zeros((2, 3))
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = 1e-5
+        Jn[:, j] = (pin(p + e) - pin(p - e)) / 2e-5
+    return Jn
+
+
+def test_guard_band_evaluates_the_jacobian_at_the_clamped_point():
+    """Reading of section 2.1 step 1 for Gaussians far off the optical axis:
+    the perspective Jacobian of the EWA covariance is taken at the centre
+    with x/z and y/z clamped to 1.3 tan(half field of view); the centre
+    itself (u, v) is not clamped. Points just inside the band (1.25 tan)
+    keep their own Jacobian, points beyond it (1.35 tan, 2 tan, on either
+    side and on both axes) take it at the band's edge, so a wrong limit or a
+    clamp applied to the centre fails."""
+    cam = scenes.orbit_camera(320, 240, 5.0, 0.3, 0.2)
+    R, t = np.asarray(cam["R"]), np.asarray(cam["t"])
+    tx, ty = 0.5 * cam["width"] / cam["fx"], 0.5 * cam["height"] / cam["fy"]
+    limx, limy = 1.3 * tx, 1.3 * ty
+    rng = np.random.default_rng(21)
+    cases = [(1.25 * tx, 0.1 * ty), (-1.25 * tx, 0.0), (0.0, 1.25 * ty), (1.35 * tx, 0.2 * ty), (-1.35 * tx, -0.3 * ty),
+             (0.1 * tx, 1.35 * ty), (0.0, -2.0 * ty), (2.0 * tx, -1.5 * ty), (-1.6 * tx, 1.6 * ty)]
+    clamped = 0
+    for k, (xr, yr) in enumerate(cases):
+        z = 3.0 + 0.5 * k
+        y_cam = np.array([xr * z, yr * z, z])
+        mean = R.T @ (y_cam - t)
+        ls = rng.normal(-2.0, 0.3, 3)
+        q = rng.normal(size=4)
+        pr = oracle.project(_one(mean, ls, q), cam)[:, 0]
+        # the centre projects without any clamp
+        np.testing.assert_allclose(pr[[oracle.F_U, oracle.F_V]],
+                                   [cam["fx"] * xr + cam["cx"], cam["fy"] * yr + cam["cy"]], rtol=1e-12)
+        xi, eta = np.clip(xr, -limx, limx), np.clip(yr, -limy, limy)
+        clamped += (xi != xr) or (eta != yr)
+        Jn = _pinhole_jacobian(cam, np.array([xi * z, eta * z, z]))
+        qn = q / np.linalg.norm(q)
+        ang = 2 * math.atan2(np.linalg.norm(qn[1:]), qn[0])
+        ax = qn[1:] / np.linalg.norm(qn[1:])
+        Kx = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+        Rq = np.eye(3) + math.sin(ang) * Kx + (1 - math.cos(ang)) * Kx @ Kx
+        Sc = R @ (Rq @ np.diag(np.exp(2 * ls)) @ Rq.T) @ R.T
+        Q = np.linalg.inv(Jn @ Sc @ Jn.T + 0.3 * np.eye(2))
+        np.testing.assert_allclose(pr[[oracle.F_A, oracle.F_B, oracle.F_C]], [Q[0, 0], Q[0, 1], Q[1, 1]], rtol=1e-7)
+        if (xi, eta) != (xr, yr):
+            # the unclamped Jacobian would give a clearly different footprint
+            Ju = _pinhole_jacobian(cam, y_cam)
+            Qu = np.linalg.inv(Ju @ Sc @ Ju.T + 0.3 * np.eye(2))
+            assert np.max(np.abs(Qu - Q)) > 1e-3 * np.max(np.abs(Q))
+    assert clamped == 6
+
+
 def test_quaternion_sign_and_scale_invariance():
     cam = scenes.orbit_camera(128, 96, 4.0, 1.0, 0.5)
     rng = np.random.default_rng(4)

@@ -307,6 +307,24 @@ gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, con
                            uint32_t *tile_work_bwd, const void *target, double scale, void *dL_drgb,
                            double *loss_dev, void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): gs_render_fwd_l1
+ * without the workspace argument. The per-tile loss shares and their block
+ * sums live in a fixed scratch array inside the library, one per device,
+ * held until the process ends (GS_NOALLOC_MAX_TILES + 64 doubles, 8 MiB).
+ * Calls with more than GS_NOALLOC_MAX_TILES tiles over the views return
+ * GS_ERR_ARG. Every call on a device shares that device's scratch, so calls
+ * that overlap on one device (other streams, other threads) race and must be
+ * ordered by the caller; a call leaves only scratch contents that the next
+ * call overwrites before reading. Outputs and every other argument exactly as
+ * gs_render_fwd_l1. */
+#define GS_NOALLOC_MAX_TILES (1 << 20)
+gs_status gs_render_fwd_l1_noalloc(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                                   const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
+                                   void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd,
+                                   uint32_t *tile_work_bwd, const void *target, double scale, void *dL_drgb,
+                                   double *loss_dev, void *stream);
+
 /* ------------------------------------------------------------------ optimizer */
 /* Adam with the batch scaling rules of section 4: learning rate
  * lr * sqrt(batch_size) (eq. "lambda") and beta1^b, beta2^b (eq. "beta").

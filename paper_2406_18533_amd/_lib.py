@@ -18,7 +18,7 @@ EXPORTS = [
     "gs_bin_workspace_bytes", "gs_sched_workspace_bytes", "gs_loss_workspace_bytes",
     "gs_loss_dssim_workspace_bytes", "gs_project",
     "gs_bin_sort", "gs_bins_keys64", "gs_render_fwd", "gs_render_bwd", "gs_render_bwd_pixels", "gs_project_bwd",
-    "gs_loss_l1", "gs_loss_l1_dssim", "gs_render_fwd_l1", "gs_adam_step", "gs_project_bwd_adam", "gs_sched_plan",
+    "gs_loss_l1", "gs_loss_l1_dssim", "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc", "gs_adam_step", "gs_project_bwd_adam", "gs_sched_plan",
     "gs_densify_stats", "gs_densify_workspace_bytes", "gs_densify_plan", "gs_densify_apply", "gs_reset_opacity",
 ]
 
@@ -89,6 +89,8 @@ def load() -> C.CDLL:
                            p, p, p, p, p, p, p], i32),
         "gs_render_fwd_l1": ([i32, p, i64, C.POINTER(GsBins), cam_p, i32, C.POINTER(C.c_float), C.POINTER(GsSched),
                               p, p, p, p, p, p, C.c_double, p, p, p, sz, p], i32),
+        "gs_render_fwd_l1_noalloc": ([i32, p, i64, C.POINTER(GsBins), cam_p, i32, C.POINTER(C.c_float),
+                                      C.POINTER(GsSched), p, p, p, p, p, p, C.c_double, p, p, p], i32),
         "gs_render_bwd": ([i32, p, i64, p, C.POINTER(GsBins), p, cam_p, i32, C.POINTER(C.c_float),
                            C.POINTER(GsSched), p, p, p, p, p, p], i32),
         "gs_render_bwd_pixels": ([i32, p, i64, C.POINTER(GsBins), cam_p, i32, C.POINTER(C.c_float),

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -130,6 +131,38 @@ static int cu_count()
     return g_cus;
 }
 
+// Fixed scratch of the no-allocation forward (gs_render_fwd_l1_noalloc): the
+// per-tile loss shares and the 64 block sums of their deterministic sum, for
+// up to GS_NOALLOC_MAX_TILES tiles. Each device holds its own copy for the
+// life of the process. In host code `scratch` only names the symbol: kernels
+// get the device address that hipGetSymbolAddress returns for the current
+// device, kept in g_scratch_dev.
+static __device__ __align__(256) double scratch[GS_NOALLOC_MAX_TILES + LOSS_SUM_BLOCKS];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[MAX_DEVICES];
+
+// Device address of `scratch` on the current device, resolved once per
+// device (gs_init does it; a first call on a device that skipped gs_init
+// does it then).
+static gs_status scratch_address(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(GS_ERR_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return GS_OK;
+}
+
 extern "C" {
 
 const char *gs_version(void) { return GS_VERSION_STRING; }
@@ -146,7 +179,8 @@ gs_status gs_init(int32_t device)
     if (strncmp(p.gcnArchName, "gfx950", 6) != 0)
         return fail(GS_ERR_UNSUPPORTED, std::string("device is ") + p.gcnArchName + ", this library is built for gfx950");
     g_cus = p.multiProcessorCount;
-    return GS_OK;
+    double *sp = nullptr;
+    return scratch_address(&sp);
 }
 
 size_t gs_projected_bytes(gs_dtype dtype, int64_t n, int32_t views)
@@ -397,6 +431,27 @@ gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, con
                                                    tile_work_bwd, nullptr, target, scale, dL_drgb, loss_dev,
                                                    (double *)workspace, s);
     return hip_status(e, "gs_render_fwd_l1");
+}
+
+gs_status gs_render_fwd_l1_noalloc(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,
+                                   const gs_camera *cams_host, int32_t views, const float *bg, const gs_sched *sched,
+                                   void *rgb, void *final_T, uint32_t *last, uint32_t *tile_work_fwd,
+                                   uint32_t *tile_work_bwd, const void *target, double scale, void *dL_drgb,
+                                   double *loss_dev, void *stream)
+{
+    std::string why;
+    CHECK_ARG(cams_ok(cams_host, views, why), why);
+    int64_t tiles = make_view_table(cams_host, views).total_tiles;
+    if (tiles > GS_NOALLOC_MAX_TILES)
+        return fail(GS_ERR_ARG, "gs_render_fwd_l1_noalloc: " + std::to_string(tiles) + " tiles exceed its fixed scratch of " +
+                                    std::to_string(GS_NOALLOC_MAX_TILES) + " tiles; use gs_render_fwd_l1");
+    double *ws = nullptr;
+    gs_status st = scratch_address(&ws);
+    if (st != GS_OK) return st;
+    // every tile share is written before the sum reads it: nothing to clear
+    return gs_render_fwd_l1(dtype, projected, n, bins, cams_host, views, bg, sched, rgb, final_T, last, tile_work_fwd,
+                            tile_work_bwd, target, scale, dL_drgb, loss_dev, ws,
+                            sizeof(double) * ((size_t)GS_NOALLOC_MAX_TILES + LOSS_SUM_BLOCKS), stream);
 }
 
 gs_status gs_render_bwd_pixels(gs_dtype dtype, const void *projected, int64_t n, const gs_bins *bins,

@@ -242,6 +242,20 @@ def gs_render_fwd_l1(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras,
     return rgb, final_T, last
 
 
+def gs_render_fwd_l1_noalloc(projected: torch.Tensor, n: int, bins: Bins, cams: Cameras, target: torch.Tensor,
+                             rgb: torch.Tensor, final_T: torch.Tensor, last: torch.Tensor, dL_drgb: torch.Tensor,
+                             loss: torch.Tensor, bg=(0.0, 0.0, 0.0), sched: Sched | None = None, tile_work_fwd=None,
+                             tile_work_bwd=None, scale: float = 1.0, stream=None):
+    """gs_render_fwd_l1 on the library's fixed per-device scratch: the caller
+    passes every output (nothing is allocated here or in the library)."""
+    check(_lib.load().gs_render_fwd_l1_noalloc(_dtype_code(projected.dtype), _ptr(projected), n,
+                                               C.byref(bins.struct), cams.host_ptr, cams.n, _bg(bg),
+                                               C.byref(sched.struct) if sched else None, _ptr(rgb), _ptr(final_T),
+                                               _ptr(last), _ptr(tile_work_fwd), _ptr(tile_work_bwd), _ptr(target),
+                                               float(scale), _ptr(dL_drgb), _ptr(loss), _stream(stream)))
+    return rgb, final_T, last
+
+
 def gs_render_bwd(params: torch.Tensor, projected: torch.Tensor, bins: Bins, cams: Cameras, final_T, last, dL_drgb,
                   grad: torch.Tensor, bg=(0.0, 0.0, 0.0), sched: Sched | None = None, dprojected=None, stream=None):
     """Both backward halves; accumulates (+=) into ``grad``. ``dprojected``

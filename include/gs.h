@@ -93,15 +93,21 @@ typedef struct gs_bins {
 
 #define GS_SCHED_PER_TILE 0    /* one workgroup per tile, XCD-aware tile order */
 #define GS_SCHED_PERSISTENT 1  /* persistent workgroups, cost-balanced chunks + stealing */
+#define GS_SCHED_XCD_SPLIT 2   /* one workgroup per tile; each XCD takes one of 8 cost-balanced
+                                  contiguous chunks of the serialised tiles (Algorithm 1, G = 8) */
 
 /* Launch shape of the two render kernels and the state of the persistent
  * scheduler (the single-GPU counterpart of section 3.2 "Iterative Workload
  * Rebalancing" and Algorithm 1 "Calculation of Division Points"). In
  * persistent mode each gs_render_fwd / gs_render_bwd call first runs
  * Algorithm 1 on tile_cost (see gs_sched_plan), then launches `workers`
- * workgroups that take tiles from the `queues` cost-balanced chunks. */
+ * workgroups that take tiles from the `queues` cost-balanced chunks. In
+ * XCD-split mode it runs Algorithm 1 with 8 chunks (queues is ignored) and
+ * launches one workgroup per tile, the workgroups of XCD x (b mod 8 = x)
+ * taking chunk x: the 8 XCDs, each with its own L2, play the part of the
+ * paper's GPUs. */
 typedef struct gs_sched {
-    int32_t mode;             /* GS_SCHED_PER_TILE or GS_SCHED_PERSISTENT */
+    int32_t mode;             /* GS_SCHED_PER_TILE, GS_SCHED_PERSISTENT or GS_SCHED_XCD_SPLIT */
     int32_t px_per_thread;    /* 1, 2 or 4: 256, 128 or 64 threads per 16x16 tile */
     int32_t chunk;            /* records staged in LDS per step: 32, 64, 128 or 256 */
     int32_t workers;          /* persistent workgroups (0 = as many as fit on the GPU at once) */
@@ -175,13 +181,15 @@ size_t gs_loss_dssim_workspace_bytes(gs_dtype dtype, const gs_camera *cams_host,
  * R(q) diag(exp(2 l)) R(q)^T and J the perspective Jacobian at the centre
  * (its x/z, y/z clamped to 1.3x the half field of view); radius =
  * ceil(3 sqrt(largest eigenvalue)); rgb = max(0, SH(direction) + 1/2).
- * A record with radius 0 is culled (behind znear or non-finite); then only
- * radius and tiles touched (0) are defined; rgb is computed only for records
- * with tiles touched > 0. After the records the buffer holds, for every
- * (view, Gaussian), tiles touched and the FP32 bits of depth as planar
- * uint32 arrays, then the touched tile rectangle as a planar uint64 array
- * (tile columns x0, x1 and rows y0, y1, inclusive, in 16-bit fields from the
- * low end; 0 when no tile is touched) (see gs_projected_bytes).
+ * After the records the buffer holds, for every (view, Gaussian), tiles
+ * touched and the FP32 bits of depth as planar uint32 arrays, then the
+ * touched tile rectangle as a planar uint64 array (tile columns x0, x1 and
+ * rows y0, y1, inclusive, in 16-bit fields from the low end) (see
+ * gs_projected_bytes). Only pairs that touch a tile are written: their
+ * record, depth bits and rectangle. For every other pair (culled: behind
+ * znear or non-finite; or off-screen) only tiles touched = 0 is written, and
+ * its record, depth bits and rectangle keep whatever the buffer held; readers
+ * select records by the side array's tiles touched.
  * params: [59][n]. cams_dev: [views] cameras in device memory (read by the
  * kernel, so a captured graph sees updated poses); cams_host: the same
  * cameras [host] (image sizes). Requires 1 <= views <= GS_MAX_VIEWS,

@@ -1,8 +1,11 @@
 // Gaussian transformation forward and backward (paper section 2.1 step 1;
-// appendix A.3: both are Gaussian-wise). One thread per Gaussian, fused over
-// all views of the batch: the parameters are read once (planar rows, so a
-// wavefront reads 64 consecutive floats per row) and every view's record is
-// written by the same thread.
+// appendix A.3: both are Gaussian-wise).
+//  - forward: one lane per (view, Gaussian); a wavefront takes 64
+//    consecutive Gaussians of one view at a time (planar rows, so every
+//    parameter load and record store is coalesced), and the views of one
+//    64-Gaussian chunk run back to back on one XCD, so the chunk's parameters
+//    come from HBM once and from that XCD's L2 for the other views;
+//  - backward: one thread per Gaussian, summing over the views in registers.
 #include "common.hpp"
 
 namespace gs {
@@ -201,77 +204,68 @@ template <typename T, typename W> __device__ __forceinline__ void sh_grad(T x, T
 
 template <typename T> using V4 = typename Vec4<T>::type;
 
+// Forward work items: (view v, 64-Gaussian chunk c), one per wavefront. The
+// items of XCD x (workgroups b with b mod 8 = x) are the chunks
+// c = 8 k + x, k = 0, 1, ..., each with all its views in turn (item s of the
+// XCD is k = s div views, v = s mod views), so the views of one chunk run
+// back to back on one XCD and its parameters come from that XCD's L2 after
+// the first view. Workgroups of four wavefronts take four consecutive items
+// (one-wavefront workgroups made workgroup dispatch, not the work, the
+// limit). Only pairs that touch a tile write a record and the depth /
+// rectangle side arrays; every pair writes its tiles touched (0 when culled
+// or off-screen).
+template <typename T>
+__device__ __forceinline__ void project_item(const T *__restrict__ P, int64_t n, const Camera<T> &k, int64_t vn,
+                                             int64_t o, int64_t i, T *__restrict__ out)
+{
+    T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    bool xok = finite(x[0]) && finite(x[1]) && finite(x[2]);
+    T z = k.R[6] * x[0] + k.R[7] * x[1] + k.R[8] * x[2] + k.t[2];
+    uint32_t tiles = 0;
+    if (xok && z > k.znear) {
+        Shape<T> S;
+        make_shape(P, n, i, S);
+        Geo<T> g;
+        make_geo(x, S, k, g);
+        if (g.visible && g.tiles > 0) {
+            tiles = (uint32_t)g.tiles;
+            T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
+            T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            T Y[16];
+            sh_basis(d[0] * idn, d[1] * idn, d[2] * idn, Y);
+            T acc[3] = {T(0), T(0), T(0)};
+            for (int k2 = 0; k2 < 16; k2++)
+                for (int ch = 0; ch < 3; ch++) acc[ch] += P[(11 + 3 * k2 + ch) * n + i] * Y[k2];
+            T rgb[3];
+            for (int ch = 0; ch < 3; ch++) {
+                T a = acc[ch] + T(0.5);
+                rgb[ch] = a > T(0) ? a : T(0);
+            }
+            V4<T> *rec = reinterpret_cast<V4<T> *>(out + o * REC);
+            rec[0] = V4<T>{g.u, g.v, g.conic[0], g.conic[1]};
+            rec[1] = V4<T>{g.conic[2], S.opac, rgb[0], rgb[1]};
+            rec[2] = V4<T>{rgb[2], g.radius, g.y[2], (T)g.tiles};
+            side_depth<T>(out, vn)[o] = __float_as_uint((float)g.y[2]);
+            side_rect<T>(out, vn)[o] = pack_rect(g.rect.x0, g.rect.x1, g.rect.y0, g.rect.y1);
+        }
+    }
+    side_tiles<T>(out, vn)[o] = tiles;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ P, int64_t n,
                                                           const gs_camera *__restrict__ cams, int32_t views,
                                                           T *__restrict__ out)
 {
-    __shared__ Camera<T> cs[MAXV];
-    stage_cameras(cs, cams, views);
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int x = blockIdx.x & 7;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t s = (int64_t)(blockIdx.x >> 3) * 4 + wave;               // item of XCD x
+    const int64_t kk = s / views;
+    const int v = (int)(s - kk * views);
+    const int64_t i = (kk * 8 + x) * 64 + (threadIdx.x & 63);
     if (i >= n) return;
-    T x[3] = {P[i], P[n + i], P[2 * n + i]};
-    bool xok = finite(x[0]) && finite(x[1]) && finite(x[2]);
-    // Cheap pre-test on the mean alone: in front of some camera's near plane?
-    bool any_front = false;
-    for (int v = 0; v < views && xok; v++) {
-        const Camera<T> &c = cs[v];
-        T z = c.R[6] * x[0] + c.R[7] * x[1] + c.R[8] * x[2] + c.t[2];
-        any_front |= z > c.znear;
-    }
-    Shape<T> S;
-    if (any_front) make_shape(P, n, i, S);
-    else S.ok = false;
-    S.ok = S.ok && xok;
-    uint64_t need_colour = 0;
-    const int64_t vn = (int64_t)views * n;
-    uint32_t *tiles_out = side_tiles<T>(out, vn), *depth_out = side_depth<T>(out, vn);
-    uint64_t *rect_out = side_rect<T>(out, vn);
-    for (int v = 0; v < views; v++) {
-        V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
-        const Camera<T> &k = cs[v];
-        Geo<T> g;
-        make_geo(x, S, k, g);
-        tiles_out[(int64_t)v * n + i] = g.visible ? (uint32_t)g.tiles : 0u;
-        depth_out[(int64_t)v * n + i] = g.visible ? __float_as_uint((float)g.y[2]) : 0u;
-        rect_out[(int64_t)v * n + i] =
-            g.visible && g.tiles > 0 ? pack_rect(g.rect.x0, g.rect.x1, g.rect.y0, g.rect.y1) : 0ull;
-        if (!g.visible) {
-            rec[2] = V4<T>{T(0), T(0), T(0), T(0)};
-            continue;
-        }
-        if (g.tiles > 0) {
-            need_colour |= 1ull << v;
-            continue;
-        }
-        rec[0] = V4<T>{g.u, g.v, g.conic[0], g.conic[1]};
-        rec[1] = V4<T>{g.conic[2], S.opac, T(0), T(0)};
-        rec[2] = V4<T>{T(0), g.radius, g.y[2], T(0)};
-    }
-    if (!need_colour) return;
-    T sh[48];
-    for (int j = 0; j < 48; j++) sh[j] = P[(11 + j) * n + i];
-    for (int v = 0; v < views; v++) {
-        if (!((need_colour >> v) & 1ull)) continue;
-        V4<T> *rec = reinterpret_cast<V4<T> *>(out + ((int64_t)v * n + i) * REC);
-        const Camera<T> &k = cs[v];
-        Geo<T> g;
-        make_geo(x, S, k, g);
-        T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
-        T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        T Y[16];
-        sh_basis(d[0] * idn, d[1] * idn, d[2] * idn, Y);
-        T rgb[3];
-        for (int ch = 0; ch < 3; ch++) {
-            T acc = T(0);
-            for (int k2 = 0; k2 < 16; k2++) acc += sh[3 * k2 + ch] * Y[k2];
-            acc += T(0.5);
-            rgb[ch] = acc > T(0) ? acc : T(0);
-        }
-        rec[0] = V4<T>{g.u, g.v, g.conic[0], g.conic[1]};
-        rec[1] = V4<T>{g.conic[2], S.opac, rgb[0], rgb[1]};
-        rec[2] = V4<T>{rgb[2], g.radius, g.y[2], (T)g.tiles};
-    }
+    const Camera<T> k = load_camera<T>(cams + v);
+    project_item(P, n, k, (int64_t)views * n, (int64_t)v * n + i, i, out);
 }
 
 // Transformation backward: chain rule from the per-view record gradients
@@ -321,17 +315,37 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
         dy[0] = du * k.fx * iz;
         dy[1] = dv * k.fy * iz;
         dy[2] = -(du * k.fx * g.y[0] + dv * k.fy * g.y[1]) * iz2;
-        // conic = (C, -B, A) / det
-        T id = T(1) / g.det, id2 = id * id;
-        T dA = -da * g.C * g.C * id2 + db * g.B * g.C * id2 - dc * g.B * g.B * id2;
-        T dB = T(2) * da * g.B * g.C * id2 + db * (-id - T(2) * g.B * g.B * id2) + T(2) * dc * g.A * g.B * id2;
-        T dC = -da * g.B * g.B * id2 + db * g.A * g.B * id2 - dc * g.A * g.A * id2;
-        // A = |n0|^2 + 0.3, B = n0.n1, C = |n1|^2 + 0.3 with N = Tm M:
-        // dN0 = 2 dA n0 + dB n1, dN1 = dB n0 + 2 dC n1; dTm = dN M^T, dM += Tm^T dN
+        // conic Q = Sigma'^-1 = (C, -B, A) / det. With Gc = [[da, db/2],
+        // [db/2, dc]] the gradient w.r.t. Sigma' is H = -Q Gc Q, and with
+        // Sigma' = N N^T + 0.3 I, dL/dN = 2 H N. H is formed in the
+        // eigenbasis (e1, e2) of Sigma': for a thin footprint its entries in
+        // image coordinates are large terms that cancel, and FP32 loses the
+        // part along the long axis; in the eigenbasis H is diagonal-scaled,
+        // -(e_i^T Gc e_j) / (l_i l_j), with l2 = det / l1 (no cancellation),
+        // and N is projected onto e1, e2 before the product.
+        T hd = T(0.5) * (g.A - g.C), mid = T(0.5) * (g.A + g.C);
+        T rr = sqrt(hd * hd + g.B * g.B);
+        T l1 = mid + rr, l2 = g.det / l1;
+        T ex = T(1), ey = T(0);
+        if (rr > T(0)) {
+            T px = hd >= T(0) ? hd + rr : g.B, py = hd >= T(0) ? g.B : rr - hd;
+            T inv = T(1) / sqrt(px * px + py * py);
+            ex = px * inv;
+            ey = py * inv;
+        }
+        T hdb = T(0.5) * db;
+        T g11 = ex * (da * ex + hdb * ey) + ey * (hdb * ex + dc * ey);
+        T g22 = ey * (da * ey - hdb * ex) - ex * (hdb * ey - dc * ex);
+        T g12 = ex * (hdb * ex - da * ey) + ey * (dc * ex - hdb * ey);
+        T il1 = T(1) / l1, il2 = T(1) / l2;
+        T h11 = -g11 * il1 * il1, h22 = -g22 * il2 * il2, h12 = -g12 * il1 * il2;
         T dN[6];
         for (int c = 0; c < 3; c++) {
-            dN[c] = T(2) * dA * g.N[c] + dB * g.N[3 + c];
-            dN[3 + c] = dB * g.N[c] + T(2) * dC * g.N[3 + c];
+            T p1 = ex * g.N[c] + ey * g.N[3 + c];        // e1^T N
+            T p2 = ex * g.N[3 + c] - ey * g.N[c];        // e2^T N, e2 = (-ey, ex)
+            T r1 = h11 * p1 + h12 * p2, r2 = h12 * p1 + h22 * p2;
+            dN[c] = T(2) * (ex * r1 - ey * r2);
+            dN[3 + c] = T(2) * (ey * r1 + ex * r2);
         }
         T dT0[3], dT1[3];
         for (int c = 0; c < 3; c++) {
@@ -489,8 +503,10 @@ hipError_t launch_project_fwd(const void *P, int64_t n, const gs_camera *cams, i
                               hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(project_fwd_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T *)P, n, cams, views,
+    // each XCD takes ceil(chunks / 8) chunks x views items, four per workgroup
+    int64_t items_per_xcd = ((n + 63) / 64 + 7) / 8 * views;
+    int64_t grid = 8 * ((items_per_xcd + 3) / 4);
+    hipLaunchKernelGGL(project_fwd_kernel<T>, dim3((unsigned)grid), dim3(256), 0, s, (const T *)P, n, cams, views,
                        (T *)out);
     return hipGetLastError();
 }

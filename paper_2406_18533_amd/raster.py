@@ -141,9 +141,10 @@ class Sched:
         self.tile_cost = tile_cost
         self.workspace = None
         wsb = 0
-        if mode == _lib.GS_SCHED_PERSISTENT:
+        if mode in (_lib.GS_SCHED_PERSISTENT, _lib.GS_SCHED_XCD_SPLIT):
             assert cams is not None
-            wsb = int(_lib.load().gs_sched_workspace_bytes(cams.total_tiles(), queues))
+            q = 8 if mode == _lib.GS_SCHED_XCD_SPLIT else queues
+            wsb = int(_lib.load().gs_sched_workspace_bytes(cams.total_tiles(), q))
             self.workspace = torch.empty(wsb, dtype=torch.uint8, device=device)
         self.struct = GsSched(mode, px_per_thread, chunk, workers, queues, 0,
                               tile_cost.data_ptr() if tile_cost is not None else None,
@@ -177,6 +178,19 @@ def projected_side_arrays(projected: torch.Tensor):
     flat = torch.as_strided(projected, (total,), (1,), projected.storage_offset())
     side = flat[V * n * _lib.GS_REC:].view(torch.int32)[: 2 * V * n]
     return side[: V * n].view(V, n), side[V * n:].view(V, n)
+
+
+def instance_count(projected: torch.Tensor) -> int:
+    """Sorted instances the projected buffer will produce: the sum of the
+    tiles touched over every (view, Gaussian) (a host synchronisation)."""
+    tiles, _ = projected_side_arrays(projected)
+    return int(tiles.sum(dtype=torch.int64).item())
+
+
+def records_on_screen(projected: torch.Tensor) -> torch.Tensor:
+    """[views][n] bool: the pairs whose record gs_project wrote (tiles touched > 0)."""
+    tiles, _ = projected_side_arrays(projected)
+    return tiles > 0
 
 
 # --------------------------------------------------------------------------- entry points

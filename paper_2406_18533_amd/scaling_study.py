@@ -53,26 +53,28 @@ class StudyConfig:
     seed: int = 0
 
 
-def make_scene(c: StudyConfig):
+def make_scene(c: StudyConfig, images=None, dtype=torch.float32):
     """Target scene (clustered Gaussians), its renders from `views` cameras on a
     sphere, and the starting scene: the target with means moved by N(0, 0.02)
-    and diffuse colours by N(0, 0.3)."""
+    and diffuse colours by N(0, 0.3). `images` (one flat [3 H W] image per
+    camera) replaces the renders when given."""
     from synthetic import scenes
-    tgt = scenes.clustered_gaussians(c.gaussians, c.seed)
+    tgt = scenes.clustered_gaussians(c.gaussians, c.seed, dtype)
     cams = scenes.sphere_cameras(c.views, c.seed + 1, c.res, c.res)
     start = scenes.jittered(tgt, c.seed + 2)
     g = torch.Generator().manual_seed(c.seed + 3)
     start[DC] += 0.3 * torch.randn(3, c.gaussians, generator=g).to(start.dtype)
-    images = []
-    for cam in cams:
-        cm = R.Cameras([cam])
-        proj = R.gs_project(tgt.cuda(), cm)
-        K = int(proj[..., 11].double().sum().item())
-        bins = R.Bins(c.gaussians, cm, K + 1024)
-        R.gs_bin_sort(proj, c.gaussians, cm, bins)
-        rgb, _, _ = R.gs_render_fwd(proj, c.gaussians, bins, cm)
-        images.append(rgb.clone())
-    torch.cuda.synchronize()
+    if images is None:
+        images = []
+        for cam in cams:
+            cm = R.Cameras([cam])
+            proj = R.gs_project(tgt.cuda(), cm)
+            K = R.instance_count(proj)
+            bins = R.Bins(c.gaussians, cm, K + 1024)
+            R.gs_bin_sort(proj, c.gaussians, cm, bins)
+            rgb, _, _ = R.gs_render_fwd(proj, c.gaussians, bins, cm)
+            images.append(rgb.clone())
+        torch.cuda.synchronize()
     return start.cuda(), cams, images
 
 
@@ -109,69 +111,98 @@ def rule_hparams(base_lr, beta1: float, beta2: float, b: int, lr_rule: str, mom_
     return lr6, beta1, beta2
 
 
-def _compare(delta, ref):
+def compare(delta, ref):
+    """Cosine similarity and norm ratio of a cumulative update against the
+    batch-size-1 one."""
     return {"cosine": float((delta * ref).sum() / (delta.norm() * ref.norm())),
             "norm_ratio": float(delta.norm() / ref.norm())}
 
 
+def continuations(make_runner, P0, c: StudyConfig, base_lr, b1: float, b2: float, log=print):
+    """The study's protocol on any implementation of the training step:
+    `make_runner(P, b, lr6, beta1, beta2)` returns an object whose run(seq)
+    trains from P over the view sequence seq in batches of b (fresh Adam
+    state, the fused rules lr sqrt(b) and beta^b applied to the values given)
+    and returns the parameters. Pre-trains at batch size 1, then continues
+    from that point at each batch size under each rule and compares the
+    cumulative diffuse-colour update with the batch-size-1 continuation.
+    Returns (results, pre-trained parameters)."""
+    gen = torch.Generator().manual_seed(c.seed + 5)
+    pre_seq = torch.randint(0, c.views, (c.pretrain_steps,), generator=gen).tolist()
+    log(f"pre-training {c.pretrain_steps} steps at batch size 1")
+    P_pre = make_runner(P0, 1, base_lr, b1, b2).run(pre_seq).clone()
+    seq = torch.randint(0, c.views, (c.images,), generator=gen).tolist()
+    ref = make_runner(P_pre, 1, base_lr, b1, b2).run(seq)[DC] - P_pre[DC]
+    res = {"lr_rules": {}, "momentum_rules": {}}
+    for b in c.batches:
+        for lr_rule in ("constant", "sqrt", "linear"):
+            lr6, x1, x2 = rule_hparams(base_lr, b1, b2, b, lr_rule, "exp")
+            d = make_runner(P_pre, b, lr6, x1, x2).run(seq)[DC] - P_pre[DC]
+            res["lr_rules"].setdefault(lr_rule, {})[b] = compare(d, ref)
+        lr6, x1, x2 = rule_hparams(base_lr, b1, b2, b, "sqrt", "unchanged")
+        d = make_runner(P_pre, b, lr6, x1, x2).run(seq)[DC] - P_pre[DC]
+        res["momentum_rules"].setdefault("unchanged", {})[b] = compare(d, ref)
+        res["momentum_rules"].setdefault("exp", {})[b] = res["lr_rules"]["sqrt"][b]
+        log(f"b={b}: " + json.dumps({k: v[b] for k, v in res["lr_rules"].items()}))
+    return res, P_pre
+
+
+def precision_by_batch(G: torch.Tensor, batches, trials: int = 16, gen=None, exhaustive: bool = False) -> dict:
+    """Precision (inverse of the average per-parameter variance) of the mean
+    of b rows of G ([views][params], one gradient per view), for each b below
+    the number of views V. The b rows are distinct views, drawn without
+    replacement, which alone shrinks the variance of their mean by
+    (V - b) / (V - 1) (finite population correction); the result is divided
+    by that factor, so that uncorrelated views give precision b times that of
+    one view. Means over `trials` random draws (sample variance), or over
+    every b-subset (population variance) with `exhaustive`."""
+    import itertools
+    V = G.shape[0]
+    out = {}
+    for b in batches:
+        if b >= V:
+            continue
+        if exhaustive:
+            M = torch.stack([G[list(sub)].mean(dim=0) for sub in itertools.combinations(range(V), b)])
+            var = M.var(dim=0, correction=0)
+        else:
+            idx = [torch.randperm(V, generator=gen)[:b].to(G.device) for _ in range(max(trials, 2))]
+            M = torch.stack([G[i].mean(dim=0) for i in idx])
+            var = M.var(dim=0)
+        out[b] = float(1.0 / var.mean() * (V - b) / (V - 1))
+    return out
+
+
 def gradient_precision(P, cams, images, c: StudyConfig):
-    """Inverse of the average per-parameter variance of the batch-mean
-    diffuse-colour gradient, per batch size, over random batches of distinct
-    views. Batches are drawn without replacement from the study's V views,
-    which shrinks the variance by (V - b) / (V - 1) on its own; the values are
-    divided by that factor (batch sizes below V only), so that uncorrelated
-    views give precision b times that of one view."""
+    """Precision of the batch-mean diffuse-colour gradient against the batch
+    size (precision_by_batch), from the gradients of single views."""
     n = P.shape[1]
     grads = []
     for k, cam in enumerate(cams):
         cm = R.Cameras([cam])
         proj = R.gs_project(P, cm)
-        K = int(proj[..., 11].double().sum().item())
+        K = R.instance_count(proj)
         bins = R.Bins(n, cm, K + 1024)
         R.gs_bin_sort(proj, n, cm, bins)
-        buf = R.LossBuffers(cm)
+        buf = R.LossBuffers(cm, dtype=P.dtype)
         _, T, last = R.gs_render_fwd_l1(proj, n, bins, cm, images[k], buf)
         grad = torch.zeros_like(P)
         R.gs_render_bwd(P, proj, bins, cm, T, last, buf.dL, grad)
         grads.append(grad[DC].flatten().clone())
     G = torch.stack(grads)                             # [views][3 n], each a single view's gradient
     gen = torch.Generator().manual_seed(c.seed + 9)
-    out = {}
-    V = len(cams)
-    for b in c.variance_batches:
-        if b >= V:
-            continue
-        means = []
-        for _ in range(max(c.variance_trials, 2)):
-            idx = torch.randperm(len(cams), generator=gen)[:b].cuda()
-            means.append(G[idx].mean(dim=0))
-        M = torch.stack(means)
-        out[b] = float(1.0 / M.var(dim=0).mean() * (V - b) / (V - 1))
-    return out
+    return precision_by_batch(G, c.variance_batches, c.variance_trials, gen)
 
 
-def run_study(c: StudyConfig, log=print):
+def run_study(c: StudyConfig, log=print, images=None, dtype=torch.float32):
     t0 = time.perf_counter()
-    P0, cams, images = make_scene(c)
+    P0, cams, images = make_scene(c, images, dtype)
     base = train.TrainConfig()
-    b1, b2 = base.beta1, base.beta2
-    log(f"pre-training {c.pretrain_steps} steps at batch size 1")
-    gen = torch.Generator().manual_seed(c.seed + 5)
-    pre_seq = torch.randint(0, c.views, (c.pretrain_steps,), generator=gen).tolist()
-    P_pre = Runner(P0, cams, images, 1, base.lr, b1, b2).run(pre_seq).clone()
-    seq = torch.randint(0, c.views, (c.images,), generator=gen).tolist()
-    ref = Runner(P_pre, cams, images, 1, base.lr, b1, b2).run(seq)[DC] - P_pre[DC]
-    res = {"config": dataclasses.asdict(c), "lr_rules": {}, "momentum_rules": {}}
-    for b in c.batches:
-        for lr_rule in ("constant", "sqrt", "linear"):
-            lr6, x1, x2 = rule_hparams(base.lr, b1, b2, b, lr_rule, "exp")
-            d = Runner(P_pre, cams, images, b, lr6, x1, x2).run(seq)[DC] - P_pre[DC]
-            res["lr_rules"].setdefault(lr_rule, {})[b] = _compare(d, ref)
-        lr6, x1, x2 = rule_hparams(base.lr, b1, b2, b, "sqrt", "unchanged")
-        d = Runner(P_pre, cams, images, b, lr6, x1, x2).run(seq)[DC] - P_pre[DC]
-        res["momentum_rules"].setdefault("unchanged", {})[b] = _compare(d, ref)
-        res["momentum_rules"].setdefault("exp", {})[b] = res["lr_rules"]["sqrt"][b]
-        log(f"b={b}: " + json.dumps({k: v[b] for k, v in res["lr_rules"].items()}))
+
+    def make_runner(P, b, lr6, x1, x2):
+        return Runner(P, cams, images, b, lr6, x1, x2)
+    res, P_pre = continuations(make_runner, P0, c, base.lr, base.beta1, base.beta2, log)
+    res["config"] = dataclasses.asdict(c)
     res["gradient_precision"] = gradient_precision(P_pre, cams, images, c)
     res["seconds"] = round(time.perf_counter() - t0, 1)
     return res

@@ -33,7 +33,7 @@ class TrainConfig:
     eps: float = 1e-15
     bg: tuple = (0.0, 0.0, 0.0)
     headroom: float = 1.25          # instance capacity = headroom * first K
-    mode: int = _lib.GS_SCHED_PERSISTENT
+    mode: int = _lib.GS_SCHED_PER_TILE    # the autotuner may pick another per pass
     fwd_shape: tuple = (1, 64)      # (px_per_thread, chunk) of render forward
     bwd_shape: tuple = (1, 64)      # (px_per_thread, chunk) of render backward
     queues: int = 64
@@ -48,7 +48,7 @@ class TrainConfig:
 class BatchedTrainer:
     def __init__(self, params: torch.Tensor, cams_list: list, targets: torch.Tensor, cfg: TrainConfig | None = None):
         self.cfg = cfg or TrainConfig()
-        assert params.is_cuda and params.dtype == torch.float32 and params.shape[0] == 59
+        assert params.is_cuda and params.dtype in (torch.float32, torch.float64) and params.shape[0] == 59
         self.P = params.contiguous()
         self.n = self.P.shape[1]
         self.V = len(cams_list)
@@ -60,16 +60,17 @@ class BatchedTrainer:
         self.v = torch.zeros_like(self.P)
         self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(2, dtype=torch.float64, device=dev)
-        self.proj = R.alloc_projected(self.n, self.V, torch.float32, dev)
-        self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        dt = self.P.dtype              # float32 for training; float64 for checks against the FP64 oracle
+        self.proj = R.alloc_projected(self.n, self.V, dt, dev)
+        self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=dt, device=dev)
         P_all = self.cams.total_pixels()
-        self.rgb = torch.empty(3 * P_all, dtype=torch.float32, device=dev)
-        self.T = torch.empty(P_all, dtype=torch.float32, device=dev)
+        self.rgb = torch.empty(3 * P_all, dtype=dt, device=dev)
+        self.T = torch.empty(P_all, dtype=dt, device=dev)
         self.last = torch.empty(P_all, dtype=torch.int32, device=dev)
         if self.cfg.ssim_lambda > 0.0:
-            self.loss_buf = R.DssimBuffers(self.cams, device=dev)
+            self.loss_buf = R.DssimBuffers(self.cams, dtype=dt, device=dev)
         else:
-            self.loss_buf = R.LossBuffers(self.cams, device=dev)
+            self.loss_buf = R.LossBuffers(self.cams, dtype=dt, device=dev)
         T_all = self.cams.total_tiles()
         self.work_fwd = torch.zeros(T_all, dtype=torch.int32, device=dev)
         self.work_bwd = torch.zeros(T_all, dtype=torch.int32, device=dev)
@@ -85,7 +86,7 @@ class BatchedTrainer:
 
     def _size_bins(self):
         R.gs_project(self.P, self.cams, self.proj)
-        K = int(self.proj[..., 11].double().sum().item())
+        K = R.instance_count(self.proj)
         self.bins = R.Bins(self.n, self.cams, max(int(K * self.cfg.headroom), 1024))
 
     def _make_sched(self):
@@ -171,8 +172,8 @@ class BatchedTrainer:
         dev = self.P.device
         self.n = self.P.shape[1]
         self.grad = torch.zeros_like(self.P)
-        self.proj = R.alloc_projected(self.n, self.V, torch.float32, dev)
-        self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.proj = R.alloc_projected(self.n, self.V, self.P.dtype, dev)
+        self.dproj = torch.zeros(self.V, self.n, _lib.GS_REC, dtype=self.P.dtype, device=dev)
         self._size_bins()
         if self.stats is not None:
             self.enable_densify_stats()
@@ -314,17 +315,17 @@ class PlainTrainer:
         self.v = torch.zeros_like(self.P)
         self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.scratch = torch.zeros(2, dtype=torch.float64, device=dev)
-        self.proj = R.alloc_projected(self.n, 1, torch.float32, dev)
-        self.dproj = torch.zeros(1, self.n, _lib.GS_REC, dtype=torch.float32, device=dev)
+        self.proj = R.alloc_projected(self.n, 1, self.P.dtype, dev)
+        self.dproj = torch.zeros(1, self.n, _lib.GS_REC, dtype=self.P.dtype, device=dev)
         self.hp = R.adam_hparams(self.cfg.lr, self.cfg.beta1, self.cfg.beta2, self.cfg.eps, batch_size=self.V,
                                  zero_grad=True)
         Kmax = 0
         for cm in self.cams:
             R.gs_project(self.P, cm, self.proj)
-            Kmax = max(Kmax, int(self.proj[..., 11].double().sum().item()))
+            Kmax = max(Kmax, R.instance_count(self.proj))
         self.bins = R.Bins(self.n, max(self.cams, key=lambda c: c.total_tiles()), max(int(Kmax * self.cfg.headroom), 1024))
         self.bins_tiles = self.bins.total_tiles
-        self.bufs = [R.LossBuffers(cm, device=dev) for cm in self.cams]
+        self.bufs = [R.LossBuffers(cm, dtype=self.P.dtype, device=dev) for cm in self.cams]
         self.loss_total = torch.zeros(1, dtype=torch.float64, device=dev)
 
     def step(self):

@@ -14,7 +14,7 @@ def to_dev(x: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
 
 
 def estimate_capacity(projected: torch.Tensor) -> int:
-    return int(projected[..., 11].double().sum().item()) + 16
+    return R.instance_count(projected) + 16
 
 
 def forward(params: torch.Tensor, cams_list: list, bg=(0.0, 0.0, 0.0), sched_kw=None, capacity=None):
@@ -67,7 +67,11 @@ def bins_numpy(f: dict):
 
 
 def proj_fields(proj: torch.Tensor):
-    """[V][n][12] -> dict of [V][n] numpy arrays."""
-    p = proj.detach().cpu().numpy()
+    """[V][n][12] -> dict of [V][n] numpy arrays. Records exist only for the
+    pairs that touch a tile (the side array's tiles touched > 0); the others
+    read as all zero here (radius 0, tiles 0)."""
+    p = proj.detach().cpu().numpy().copy()
+    tiles = R.projected_side_arrays(proj)[0].cpu().numpy()
+    p[tiles == 0] = 0
     names = ["u", "v", "a", "b", "c", "opac", "r", "g", "bl", "radius", "depth", "tiles"]
     return {k: p[..., j] for j, k in enumerate(names)}

@@ -1,0 +1,205 @@
+"""Parity at the large aerial configuration (the paper's 4K aerial workload,
+section 5): 20,000,000 Gaussians over a 1000 x 1000 ground patch (heights
+N(0, 5), log-scales N(-1, 0.7), 5% in tall clusters) seen by the workload's
+own batch of 2 views at 4608x3456 and 2 at 3840x2160 from altitude 150-250
+tilted up to 30 degrees, at full size. The batched trainer runs the forward
+(L1 loss fused) in the benchmark's launch configuration; the oracle then
+checks, for one view of each size and from the GPU's own FP32 projection,
+the projection itself (against its FP64 one), bit-exact bins, the image with
+T and last, and the L1 image gradient; for the 4608x3456 view also the
+record gradients and the transformation backward. Each oracle call works on
+the Gaussians the view shows (tiles touched > 0), compacted in index order,
+which keeps the depth / index tie order of the sort."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import scenes
+from tests.test_gpu_parity import GROUPS, footprint_condition
+
+pytestmark = pytest.mark.gpu
+
+SAMPLED_VIEWS = (0, 2)     # one 4608x3456 view, one 3840x2160 view
+NAMES = ["u", "v", "a", "b", "c", "opac", "r", "g", "bl", "radius", "depth", "tiles"]
+
+
+@pytest.fixture(scope="module")
+def aerial():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_18533_amd import _lib, train
+    from paper_2406_18533_amd import raster as R
+    R.init(0)
+    print("aerial: generating 20M Gaussians", flush=True)
+    w = scenes.aerial_4k()
+    assert [(c["width"], c["height"]) for c in w.cameras] == [(4608, 3456), (4608, 3456), (3840, 2160), (3840, 2160)]
+    tgt = scenes.random_images(w.cameras, 19)
+    cfg = train.TrainConfig(graph=False, mode=_lib.GS_SCHED_PER_TILE, fwd_shape=(4, 64), bwd_shape=(4, 64))
+    tr = train.BatchedTrainer(w.params.cuda(), w.cameras, tgt.cuda(), cfg)
+    tr.forward(check=True)
+    torch.cuda.synchronize()
+    print(f"aerial: K = {int(tr.bins.n_instances.item())}", flush=True)
+    return w, tr, {}
+
+
+def _view(tr, v):
+    """Fields of view v as numpy [N] arrays (zero where the pair touches no
+    tile: such pairs have no record), and the indices of the pairs it shows."""
+    from paper_2406_18533_amd import raster as R
+    tiles = R.projected_side_arrays(tr.proj)[0][v].cpu().numpy()
+    shown = np.nonzero(tiles > 0)[0]
+    p = np.zeros((tr.n, len(NAMES)), dtype=np.float32)
+    p[shown] = tr.proj[v].index_select(0, torch.from_numpy(shown).cuda()).cpu().numpy()
+    f = {k: p[:, j] for j, k in enumerate(NAMES)}
+    assert (f["tiles"] == tiles).all()
+    return f, shown
+
+
+def _compact(f, idx):
+    """The oracle's FP64 record layout [ONF][n'] of the shown Gaussians."""
+    pr = np.zeros((oracle.ONF, idx.size))
+    for dst, src in [(oracle.F_U, "u"), (oracle.F_V, "v"), (oracle.F_DEPTH, "depth"), (oracle.F_A, "a"),
+                     (oracle.F_B, "b"), (oracle.F_C, "c"), (oracle.F_OPAC, "opac"), (oracle.F_R, "r"),
+                     (oracle.F_G, "g"), (oracle.F_BL, "bl"), (oracle.F_RADIUS, "radius"), (oracle.F_REXACT, "radius")]:
+        pr[dst] = f[src][idx].astype(np.float64)
+    return pr
+
+
+def _slices(cams, channels):
+    out, o = [], 0
+    for c in cams:
+        k = channels * c["width"] * c["height"]
+        out.append((o, o + k))
+        o += k
+    return out
+
+
+@pytest.mark.parametrize("v", SAMPLED_VIEWS)
+def test_aerial_projection_of_sampled_views(aerial, v):
+    w, tr, _ = aerial
+    cam = w.cameras[v]
+    f, shown = _view(tr, v)
+    # every Gaussian it shows plus 200k others: the oracle's own FP64
+    # projection must show the same ones (up to FP32 rounding at the edges)
+    rng = np.random.default_rng(v)
+    others = rng.choice(np.setdiff1d(np.arange(tr.n), shown), 200_000, replace=False)
+    idx = np.union1d(shown, others)
+    P64 = w.params[:, torch.from_numpy(idx)].double()
+    o = oracle.project(P64, cam)
+    tt_o = oracle.tiles_touched(*(a[None] for a in oracle.rounded_for_binning(o)[:3]), [cam])[0]
+    on_g, on_o = f["tiles"][idx] > 0, tt_o > 0
+    assert (on_g == on_o).mean() > 0.9999
+    both = on_g & on_o
+    rad = f["radius"][idx]
+    re = o[oracle.F_REXACT]
+    stable = both & (np.abs(re - np.round(re)) > 1e-5 * np.maximum(re, 1))
+    assert (rad[stable] == o[oracle.F_RADIUS][stable]).all()
+    size = max(cam["width"], cam["height"])
+    for fo, fg, scale in [(oracle.F_U, "u", size), (oracle.F_V, "v", size), (oracle.F_DEPTH, "depth", 0),
+                          (oracle.F_OPAC, "opac", 0)]:
+        a, b = f[fg][idx][both].astype(np.float64), o[fo][both]
+        err = np.max(np.abs(a - b) / np.maximum(np.abs(b), max(scale, 1e-30)))
+        print(f"aerial view {v}: {fg} error {err:.2e}", flush=True)
+        assert err <= 1e-6, (fg, err)
+    ca = np.stack([f[k][idx][both] for k in ("a", "b", "c")]).astype(np.float64)
+    co = o[[oracle.F_A, oracle.F_B, oracle.F_C]][:, both]
+    err = np.max(np.abs(ca - co) / (np.abs(co[0]) + np.abs(co[2])))
+    print(f"aerial view {v}: {shown.size} Gaussians shown, conic error {err:.2e}", flush=True)
+    assert err <= 1e-5
+    cg = np.stack([f[k][idx][both] for k in ("r", "g", "bl")]).astype(np.float64)
+    assert np.max(np.abs(cg - o[[oracle.F_R, oracle.F_G, oracle.F_BL]][:, both])) <= 1e-5
+    # tiles touched of the whole view: the oracle's FP32 rectangle on the GPU's values
+    tt = oracle.tiles_touched(f["u"][None], f["v"][None], f["radius"][None], [cam])
+    assert (tt[0] == f["tiles"].astype(np.int64)).all()
+
+
+@pytest.mark.parametrize("v", SAMPLED_VIEWS)
+def test_aerial_bins_and_images_of_sampled_views(aerial, v):
+    w, tr, cache = aerial
+    cams = w.cameras
+    cam = cams[v]
+    H, W = cam["height"], cam["width"]
+    f, idx = _view(tr, v)
+    r = np.where(f["radius"] > 0, f["radius"], 0).astype(np.float32)
+    keys_o, ids_c, ranges_o = oracle.bin_sort(f["u"][None, idx], f["v"][None, idx], r[None, idx],
+                                              f["depth"][None, idx], [cam])
+    ids_o = idx[ids_c].astype(np.uint32)
+    base = oracle.tile_base(cams)
+    assert base[v + 1] - base[v] == ranges_o.shape[0]
+    rv = tr.bins.ranges[base[v]:base[v + 1]].cpu().numpy().view(np.uint32).astype(np.int64)
+    start = rv[rv[:, 1] > rv[:, 0], 0].min()
+    nonempty = ranges_o[:, 1] > ranges_o[:, 0]
+    assert (rv[nonempty] - start == ranges_o[nonempty]).all()
+    assert (rv[~nonempty, 1] == rv[~nonempty, 0]).all()
+    ids_g = tr.bins.ids[start:start + ids_o.size].cpu().numpy().view(np.uint32)
+    assert (ids_g == ids_o).all()
+    tk = tr.bins.tile_keys[start:start + ids_o.size].cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert (tk == (keys_o >> np.uint64(32)) + np.uint64(base[v])).all()
+    print(f"aerial view {v} ({W}x{H}): {ids_o.size} instances bit-exact", flush=True)
+    # image, T and last at every pixel (one near-threshold decision: either branch)
+    pr = _compact(f, idx)
+    o = oracle.render(pr, cam, ids_c, ranges_o, tr.cfg.bg)
+    s3, s1 = _slices(cams, 3)[v], _slices(cams, 1)[v]
+    img = tr.rgb[s3[0]:s3[1]].cpu().numpy().reshape(3, H, W)
+    T = tr.T[s1[0]:s1[1]].cpu().numpy().reshape(H, W)
+    last = tr.last[s1[0]:s1[1]].cpu().numpy().view(np.uint32).reshape(H, W)
+    err, compared, took_alt = oracle.image_mismatch(o, img, T, last)
+    one = int((o["amb"] == 1).sum())
+    excl = int((~compared).sum())
+    print(f"aerial view {v}: image max err {err:.2e}; one near-threshold decision {one} ({one / compared.size:.2e}, "
+          f"{took_alt} matched its other branch), excluded {excl} ({excl / compared.size:.2e})", flush=True)
+    assert err <= 1e-5
+    assert excl <= 1e-4 * compared.size
+    # the fused L1 gradient: sign(rgb - target) / (3 H W views)
+    wgt = np.float32(1.0 / (3.0 * H * W * len(cams)))
+    d = img.reshape(-1) - tr.targets[s3[0]:s3[1]].cpu().numpy()
+    expect = np.where(d > 0, wgt, np.where(d < 0, -wgt, np.float32(0)))
+    assert (tr.loss_buf.dL[s3[0]:s3[1]].cpu().numpy() == expect).all()
+    cache[v] = (idx, ids_c, ranges_o, pr)
+
+
+def test_aerial_record_and_transformation_gradients(aerial):
+    """4608x3456 view: record gradients of the render backward (all views
+    run, this view checked) within 1e-3, and the transformation backward fed
+    this view's record gradients within 1e-4, per parameter group."""
+    from paper_2406_18533_amd import raster as R
+    w, tr, cache = aerial
+    v = SAMPLED_VIEWS[0]
+    cam = w.cameras[v]
+    H, W = cam["height"], cam["width"]
+    if v not in cache:
+        pytest.skip("needs the bins of test_aerial_bins_and_images_of_sampled_views")
+    idx, ids_c, ranges_o, pr = cache[v]
+    dproj = torch.zeros_like(tr.dproj)
+    R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL, dproj, tr.cfg.bg,
+                           tr.sched_bwd)
+    torch.cuda.synchronize()
+    s3 = _slices(w.cameras, 3)[v]
+    dLv = tr.loss_buf.dL[s3[0]:s3[1]].cpu().numpy().reshape(3, H, W).astype(np.float64)
+    do = oracle.render_bwd(pr, cam, ids_c, ranges_o, dLv, tr.cfg.bg)
+    it = torch.from_numpy(idx).cuda()
+    dg = dproj[v].index_select(0, it).cpu().numpy().astype(np.float64)
+    for comp, name in [(slice(0, 2), "mean2d"), (slice(2, 5), "conic"), (slice(5, 6), "opacity"), (slice(6, 9), "rgb")]:
+        a, b = dg[:, comp].T, do[comp]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print(f"aerial view {v} record gradient {name}: {err:.2e}", flush=True)
+        assert err <= 1e-3, (name, err)
+    # transformation backward of this view's records alone
+    only = torch.zeros_like(dproj)
+    only[v] = dproj[v]
+    del dproj
+    g = torch.zeros_like(tr.P)
+    R.gs_project_bwd(tr.P, tr.cams, tr.proj, only, g, clear=False)
+    torch.cuda.synchronize()
+    gi = g.index_select(1, it).double().cpu().numpy()
+    P64 = w.params[:, torch.from_numpy(idx)].double()
+    go = oracle.project_bwd(P64, cam, only[v].index_select(0, it)[:, :9].T.double().cpu().numpy())
+    f = {k: pr[j][None] for j, k in [(oracle.F_A, "a"), (oracle.F_B, "b"), (oracle.F_C, "c")]}
+    f["tiles"] = np.ones((1, idx.size))
+    kappa = footprint_condition(f)
+    print(f"aerial view {v}: footprint condition median {np.median(kappa):.1f}, max {kappa.max():.1f}", flush=True)
+    for k, sl in GROUPS.items():
+        err = np.linalg.norm(gi[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
+        print(f"aerial view {v} transformation backward {k}: {err:.2e}", flush=True)
+        assert err <= 1e-4, (k, err)

@@ -120,9 +120,9 @@ def test_fullsize_batch_properties(batch):
     """Every view: instance count equals the tiles touched, T in [0, 1] and
     non-increasing from 1 only where something blended, the loss equals the
     mean of the per-view mean absolute errors."""
+    from paper_2406_18533_amd import raster as R
     w, tr = batch
-    tiles = tr.proj[..., 11]
-    assert int(tr.bins.n_instances.item()) == int(tiles.double().sum().item())
+    assert int(tr.bins.n_instances.item()) == R.instance_count(tr.proj)
     T = tr.T
     assert float(T.min()) >= 0.0 and float(T.max()) <= 1.0
     assert bool(((tr.last == 0) == (T == 1.0)).all())

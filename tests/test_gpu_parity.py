@@ -89,8 +89,13 @@ def test_project_matches_oracle(name):
     n_checked = 0
     for v, cam in enumerate(cams):
         o = oracle.project(P64, cam)
-        both = (o[oracle.F_RADIUS] > 0) & (pf["radius"][v] > 0)
-        assert ((o[oracle.F_RADIUS] > 0) == (pf["radius"][v] > 0)).mean() > 0.9999
+        # records exist for the pairs that touch a tile; the oracle's own
+        # FP64 projection must show the same pairs (up to FP32 rounding at
+        # the rectangle's edges)
+        tt_o = oracle.tiles_touched(*(a[None] for a in oracle.rounded_for_binning(o)[:3]), [cam])[0]
+        on_g, on_o = pf["tiles"][v] > 0, tt_o > 0
+        assert (on_g == on_o).mean() > 0.9999
+        both = on_g & on_o
         re = o[oracle.F_REXACT]
         stable = both & (np.abs(re - np.round(re)) > 1e-5 * np.maximum(re, 1))
         assert (pf["radius"][v][stable] == o[oracle.F_RADIUS][stable]).all()
@@ -105,10 +110,8 @@ def test_project_matches_oracle(name):
         co = o[[oracle.F_A, oracle.F_B, oracle.F_C]][:, both]
         scale = np.abs(co[0]) + np.abs(co[2])
         assert np.max(np.abs(ca - co) / scale) <= 1e-5
-        # colour where the GPU computed it (tiles touched > 0)
-        col = both & (pf["tiles"][v] > 0)
-        cg = np.stack([pf[k][v][col] for k in ("r", "g", "bl")]).astype(np.float64)
-        assert np.max(np.abs(cg - o[[oracle.F_R, oracle.F_G, oracle.F_BL]][:, col])) <= 1e-5
+        cg = np.stack([pf[k][v][both] for k in ("r", "g", "bl")]).astype(np.float64)
+        assert np.max(np.abs(cg - o[[oracle.F_R, oracle.F_G, oracle.F_BL]][:, both])) <= 1e-5
         n_checked += both.sum()
     # tiles touched: bit-exact against the oracle's FP32 rectangle on the GPU's values
     tt = oracle.tiles_touched(pf["u"], pf["v"], np.where(pf["radius"] > 0, pf["radius"], 0), cams)
@@ -255,23 +258,19 @@ def test_render_bwd_matches_oracle(name):
     kappa = footprint_condition(pf)
     well = kappa <= 20.0
     print(f"{name}: footprint condition max {kappa.max():.1f}, {int((~well).sum())} Gaussians above 20", flush=True)
-    iso_tol = 3e-3 if name == "needles" else 1e-4
     for k, sl in GROUPS.items():
         err = np.linalg.norm(gi[sl] - go_iso[sl]) / max(np.linalg.norm(go_iso[sl]), 1e-30)
         errw = np.linalg.norm((gi[sl] - go_iso[sl])[:, well]) / max(np.linalg.norm(go_iso[sl][:, well]), 1e-30)
         print(f"{name} transformation backward {k}: {err:.2e} (condition <= 20: {errw:.2e})", flush=True)
-        assert err <= iso_tol, ("transformation backward", k, err)
-    # parameter gradients: the oracle's whole FP64 backward from its own projection.
-    # Thin needle footprints flip about 1% of pixel decisions between FP32 and
-    # FP64 (see the end-to-end image test), which moves these sums by ~1e-3.
-    tol = 2e-3 if name == "needles" else 1e-3
+        assert err <= 1e-4, ("transformation backward", k, err)
+    # parameter gradients: the oracle's whole FP64 backward from its own projection
     fo = oracle.forward(P.double(), cams, BG)
     go, _ = oracle.backward(P.double(), cams, fo, dLv, BG)
     gg = grad.double().cpu().numpy()
     for k, sl in GROUPS.items():
         err = np.linalg.norm(gg[sl] - go[sl]) / max(np.linalg.norm(go[sl]), 1e-30)
         print(f"{name} end-to-end gradient {k}: {err:.2e}", flush=True)
-        assert err <= tol, (k, err)
+        assert err <= 1e-3, (k, err)
 
 
 def footprint_condition(pf: dict) -> np.ndarray:
@@ -461,9 +460,14 @@ def test_image_identical_across_launch_shapes_and_schedulers():
     P, cams = small_multiview()
     Pd = gp.to_dev(P)
     ref = gp.forward(Pd, cams, BG)
+    # a cost history that puts most of the estimated work into a few tiles
+    skewed = ref["work_fwd"].clone()
+    skewed[: skewed.numel() // 10] *= 50
     for kw in [dict(px_per_thread=2, chunk=32), dict(px_per_thread=4, chunk=256), dict(px_per_thread=1, chunk=128),
                dict(mode=_lib.GS_SCHED_PERSISTENT, px_per_thread=1, chunk=64, queues=16),
-               dict(mode=_lib.GS_SCHED_PERSISTENT, px_per_thread=4, chunk=128, queues=64, workers=64)]:
+               dict(mode=_lib.GS_SCHED_PERSISTENT, px_per_thread=4, chunk=128, queues=64, workers=64),
+               dict(mode=_lib.GS_SCHED_XCD_SPLIT, px_per_thread=4, chunk=64),
+               dict(mode=_lib.GS_SCHED_XCD_SPLIT, px_per_thread=2, chunk=128, tile_cost=skewed)]:
         f = gp.forward(Pd, cams, BG, sched_kw=kw)
         assert torch.equal(f["rgb"], ref["rgb"]) and torch.equal(f["T"], ref["T"]), kw
         assert torch.equal(f["last"], ref["last"]), kw
@@ -490,8 +494,9 @@ def test_side_arrays_agree_with_records():
     tiles, depth = R.projected_side_arrays(proj)
     torch.cuda.synchronize()
     rec = proj.cpu()
-    assert torch.equal(tiles.cpu(), rec[..., 11].to(torch.int32))
-    vis = rec[..., 11] > 0
+    vis = tiles.cpu() > 0        # the pairs with a record
+    assert vis.sum() > 1000
+    assert torch.equal(tiles.cpu()[vis], rec[..., 11][vis].to(torch.int32))
     assert torch.equal(depth.cpu()[vis], rec[..., 10][vis].contiguous().view(torch.int32))
 
 

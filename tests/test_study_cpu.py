@@ -25,5 +25,28 @@ def test_compare_is_cosine_and_norm_ratio():
     import torch
     a = torch.tensor([3.0, 4.0, 0.0])
     r = torch.tensor([0.0, 4.0, 3.0])
-    out = S._compare(a, r)
+    out = S.compare(a, r)
     assert abs(out["cosine"] - 16.0 / 25.0) < 1e-7 and abs(out["norm_ratio"] - 1.0) < 1e-7
+
+
+def test_precision_correction_for_drawing_distinct_views():
+    """Mean of b of V fixed gradients drawn without replacement: over all
+    b-subsets, the variance of the mean is (sigma^2 / b) (V - b) / (V - 1)
+    with sigma^2 the population variance (finite population correction), so
+    the corrected precision is exactly b / mean(sigma^2): b times that of one
+    view. A wrong correction factor fails the ratio."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(5)
+    V = 7
+    G = torch.from_numpy(rng.normal(size=(V, 50)) * rng.uniform(0.5, 2.0, size=50))
+    out = S.precision_by_batch(G, range(1, V + 1), exhaustive=True)
+    assert sorted(out) == list(range(1, V))           # b = V has no spread to measure
+    sigma2 = G.numpy().var(axis=0, ddof=0).mean()
+    assert out[1] == pytest.approx(1.0 / sigma2, rel=1e-12)
+    for b in range(2, V):
+        assert out[b] / out[1] == pytest.approx(b, rel=1e-12)
+    # random draws estimate the same thing
+    gen = torch.Generator().manual_seed(0)
+    est = S.precision_by_batch(G, (3,), trials=4000, gen=gen)
+    assert est[3] == pytest.approx(out[3], rel=0.1)

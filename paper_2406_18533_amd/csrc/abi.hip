@@ -327,14 +327,17 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.S.dp = nullptr;
     sh.S.queues = 0;
     if (!sc) return true;
-    if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT) { why = "bad sched mode"; return false; }
+    if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT && sc->mode != GS_SCHED_XCD_SPLIT) {
+        why = "bad sched mode";
+        return false;
+    }
     if (sc->px_per_thread != 1 && sc->px_per_thread != 2 && sc->px_per_thread != 4) { why = "px_per_thread"; return false; }
     if (sc->chunk != 32 && sc->chunk != 64 && sc->chunk != 128 && sc->chunk != 256) { why = "chunk"; return false; }
     sh.mode = sc->mode;
     sh.px = sc->px_per_thread;
     sh.chunk = sc->chunk;
-    if (sh.mode == GS_SCHED_PERSISTENT) {
-        int q = sc->queues > 0 ? sc->queues : 64;
+    if (sh.mode == GS_SCHED_PERSISTENT || sh.mode == GS_SCHED_XCD_SPLIT) {
+        int q = sh.mode == GS_SCHED_XCD_SPLIT ? 8 : (sc->queues > 0 ? sc->queues : 64);
         if (q % 8 != 0 || q > (1 << 16)) { why = "queues must be a positive multiple of 8"; return false; }
         if (!sc->workspace || sc->workspace_bytes < gs_sched_workspace_bytes(total_tiles, q)) {
             why = "sched workspace too small";
@@ -387,7 +390,7 @@ gs_status gs_render_fwd(gs_dtype dtype, const void *projected, int64_t n, const 
     LaunchShape sh;
     CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
     hipStream_t s = (hipStream_t)stream;
-    if (sh.mode == GS_SCHED_PERSISTENT) {
+    if (sh.mode != GS_SCHED_PER_TILE) {
         hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
         if (e != hipSuccess) return hip_status(e, "gs_render_fwd plan");
     }
@@ -419,7 +422,7 @@ gs_status gs_render_fwd_l1(gs_dtype dtype, const void *projected, int64_t n, con
     LaunchShape sh;
     CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
     hipStream_t s = (hipStream_t)stream;
-    if (sh.mode == GS_SCHED_PERSISTENT) {
+    if (sh.mode != GS_SCHED_PER_TILE) {
         hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
         if (e != hipSuccess) return hip_status(e, "gs_render_fwd_l1 plan");
     }
@@ -468,7 +471,7 @@ gs_status gs_render_bwd_pixels(gs_dtype dtype, const void *projected, int64_t n,
     LaunchShape sh;
     CHECK_ARG(sched_shape(sched, vt.total_tiles, sh, why), why);
     hipStream_t s = (hipStream_t)stream;
-    if (sh.mode == GS_SCHED_PERSISTENT) {
+    if (sh.mode != GS_SCHED_PER_TILE) {
         hipError_t e = run_plan(sched, sh, vt.total_tiles, nullptr, s);
         if (e != hipSuccess) return hip_status(e, "gs_render_bwd_pixels plan");
     }

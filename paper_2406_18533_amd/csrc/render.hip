@@ -16,11 +16,15 @@
 //    (b mod 8) * ceil(T/8) + b div 8, so each XCD (workgroups are dealt
 //    round-robin to the 8 XCDs) sees a contiguous eighth of the serialised
 //    tiles and neighbouring tiles share that XCD's L2;
+//  - XCD-split mode: as per-tile, but the eighth of the tiles each XCD takes
+//    is a cost-balanced contiguous chunk (Algorithm 1 with G = 8);
 //  - persistent mode: a fixed grid of workgroups takes tiles from Q queues.
 //    The queues are the contiguous, cost-balanced chunks of Algorithm 1
 //    (division points) computed from per-tile costs; queue q belongs to XCD
 //    q div (Q/8). A workgroup drains its home queue, then steals from the
 //    other queues of its XCD, then from the other XCDs.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace gs {
@@ -285,20 +289,20 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
                 if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
                     T dy, G, og, alpha;
                     bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
+                    // A finished pixel holds -T: then Tn < 0 fails the blend
+                    // test below and -|T| leaves it unchanged, so `ok` needs
+                    // no separate live test.
                     T Tj = Tr[j];
-                    bool live = Tj > T(0);
-                    ok = ok && live;
-                    T Tn = Tj * (T(1) - alpha);
+                    T Tn = fma(-alpha, Tj, Tj);                 // T (1 - alpha)
                     bool bl = ok && (Tn >= K<T>::t_min);   // (Tn is finite wherever ok holds)
-                    bool stop = ok && !bl;
                     T w = bl ? alpha * Tj : T(0);
                     C[j][0] = fma(rc.x, w, C[j][0]);
                     C[j][1] = fma(rc.y, w, C[j][1]);
                     C[j][2] = fma(rc.z, w, C[j][2]);
-                    Tr[j] = bl ? Tn : (stop ? -Tj : Tj);
+                    Tr[j] = bl ? Tn : (ok ? -fabs(Tj) : Tj);   // stop: mark finished
                     lastp[j] = bl ? pos1 : lastp[j];
                     if (STATS) {
-                        n_eval += live ? 1u : 0u;
+                        n_eval += Tj > T(0) ? 1u : 0u;
                         n_blend += bl ? 1u : 0u;
                     }
                 }
@@ -450,32 +454,44 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             bool any = false;
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             const T dx = col.dx;
-            for (int j = 0; j < PX; j++) {
-                if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
-                T dy, G, og, alpha;
-                bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
-                if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian
-                    any = true;
-                    T om = T(1) - alpha;
-                    T Tk = Tr[j] * rcp_t(om);          // transmittance in front of this Gaussian
-                    T w = alpha * Tk;
-                    T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
-                    acc[6] = fma(w, gx, acc[6]);
-                    acc[7] = fma(w, gy, acc[7]);
-                    acc[8] = fma(w, gz, acc[8]);
-                    T cg = fma(rc.x, gx, fma(rc.y, gy, rc.z * gz));
-                    T dalpha = (cg - Sg[j]) * Tk;
-                    Sg[j] = fma(alpha, cg, om * Sg[j]);
-                    Tr[j] = Tk;
-                    T live = og <= K<T>::alpha_max ? dalpha : T(0);   // the 0.99 clamp has no gradient
-                    T dpow = live * og;
-                    T hy = dpow * dy;
-                    acc[5] = fma(live, G, acc[5]);
-                    D0 += dpow;
-                    D1 += hy;
-                    D2 = fma(hy, dy, D2);
+            // The pairs of this record over the thread's pixels. Only a record
+            // whose opacity exceeds 0.99 can reach the alpha clamp (alpha <=
+            // opacity), so the clamp's zero gradient is tested only for those
+            // (a wave-uniform choice between two copies of the loop).
+            auto pairs = [&](auto clamp) {
+                for (int j = 0; j < PX; j++) {
+                    if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
+                    T dy, G, og, alpha;
+                    bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
+                    if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian
+                        any = true;
+                        T Tk = Tr[j] * rcp_t(T(1) - alpha);   // transmittance in front of this Gaussian
+                        T w = alpha * Tk;
+                        T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
+                        acc[6] = fma(w, gx, acc[6]);
+                        acc[7] = fma(w, gy, acc[7]);
+                        acc[8] = fma(w, gz, acc[8]);
+                        T cg = fma(rc.x, gx, fma(rc.y, gy, rc.z * gz));
+                        T diff = cg - Sg[j];
+                        T dalpha = diff * Tk;
+                        Sg[j] = fma(alpha, diff, Sg[j]);      // alpha c + (1 - alpha) S
+                        Tr[j] = Tk;
+                        T live = dalpha;
+                        if constexpr (decltype(clamp)::value)
+                            live = og <= K<T>::alpha_max ? dalpha : T(0);   // the 0.99 clamp has no gradient
+                        T dpow = live * og;
+                        T hy = dpow * dy;
+                        acc[5] = fma(live, G, acc[5]);
+                        D0 += dpow;
+                        D1 += hy;
+                        D2 = fma(hy, dy, D2);
+                    }
                 }
-            }
+            };
+            if (__builtin_amdgcn_readfirstlane(__float_as_uint((float)ra.w)) > __float_as_uint((float)K<T>::alpha_max))
+                pairs(std::true_type{});
+            else
+                pairs(std::false_type{});
             // d/du, d/dv through (dx, dy) and d/d(a, b, c) (times -1/2, -1, -1/2 after the reduction)
             T hx = dx * D0;
             acc[0] = fma(rb.x, hx, rb.y * D1);
@@ -539,7 +555,8 @@ __global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(7
 }
 
 template <typename T, int PX, int CHUNK, bool STATS>
-__global__ void __launch_bounds__(256 / PX) render_fwd_persistent(ViewTable vt, FwdArgs<T> A, SchedState S)
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(7)))
+render_fwd_persistent(ViewTable vt, FwdArgs<T> A, SchedState S)
 {
     __shared__ Stage<T, CHUNK, false> st;
     __shared__ uint32_t s_red;
@@ -564,7 +581,8 @@ render_bwd_kernel(ViewTable vt, BwdArgs<T> A)
 }
 
 template <typename T, int PX, int CHUNK>
-__global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, BwdArgs<T> A, SchedState S)
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(6)))
+render_bwd_persistent(ViewTable vt, BwdArgs<T> A, SchedState S)
 {
     __shared__ Stage<T, CHUNK, true> st;
     __shared__ uint32_t s_red;
@@ -574,6 +592,41 @@ __global__ void __launch_bounds__(256 / PX) render_bwd_persistent(ViewTable vt, 
         int32_t g = claim(S, qi, &s_item);
         if (g < 0) break;
         bwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+    }
+}
+
+// Cost-balanced XCD split: the serialised tiles are cut into 8 contiguous
+// chunks of equal estimated cost by Algorithm 1 with G = 8 (dp[0..8], from
+// the previous iteration's per-tile work), and XCD x (the workgroups b with
+// b mod 8 = x) takes chunk x in order, workgroup b its tiles
+// dp[x] + b div 8 + k per, k = 0, 1, ... (per = grid / 8). Adjacent tiles
+// stay on one XCD's L2 as in the per-tile launch, but the XCDs finish
+// together when the views' costs differ.
+template <typename T, int PX, int CHUNK, bool STATS>
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(7)))
+render_fwd_xcd(ViewTable vt, FwdArgs<T> A, const int32_t *__restrict__ dp)
+{
+    __shared__ Stage<T, CHUNK, false> st;
+    __shared__ uint32_t s_red;
+    const int x = blockIdx.x & 7;
+    const int32_t per = (int32_t)(gridDim.x >> 3), hi = dp[x + 1];
+    for (int32_t g = dp[x] + (int32_t)(blockIdx.x >> 3); g < hi; g += per) {
+        fwd_tile<T, PX, CHUNK, STATS>(g, vt, A, st, &s_red);
+        __syncthreads();
+    }
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(6)))
+render_bwd_xcd(ViewTable vt, BwdArgs<T> A, const int32_t *__restrict__ dp)
+{
+    __shared__ Stage<T, CHUNK, true> st;
+    __shared__ uint32_t s_red;
+    const int x = blockIdx.x & 7;
+    const int32_t per = (int32_t)(gridDim.x >> 3), hi = dp[x + 1];
+    for (int32_t g = dp[x] + (int32_t)(blockIdx.x >> 3); g < hi; g += per) {
+        bwd_tile<T, PX, CHUNK>(g, vt, A, st, &s_red);
+        __syncthreads();
     }
 }
 
@@ -656,6 +709,9 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     if (sh.mode == GS_SCHED_PERSISTENT)                                                                      \
         hipLaunchKernelGGL((render_fwd_persistent<TT, P, C, ST>), dim3(sh.workers), dim3(256 / P), 0, s, vt, A, \
                            sh.S);                                                                            \
+    else if (sh.mode == GS_SCHED_XCD_SPLIT)                                                                  \
+        hipLaunchKernelGGL((render_fwd_xcd<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
+                           (const int32_t *)sh.S.dp);                                                        \
     else                                                                                                     \
         hipLaunchKernelGGL((render_fwd_kernel<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
 #define GS_FWD(TT, P, C)                                                                                     \
@@ -691,6 +747,9 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
 #define GS_BWD(TT, P, C)                                                                                     \
     if (sh.mode == GS_SCHED_PERSISTENT)                                                                      \
         hipLaunchKernelGGL((render_bwd_persistent<TT, P, C>), dim3(sh.workers), dim3(256 / P), 0, s, vt, A, sh.S); \
+    else if (sh.mode == GS_SCHED_XCD_SPLIT)                                                                  \
+        hipLaunchKernelGGL((render_bwd_xcd<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,          \
+                           (const int32_t *)sh.S.dp);                                                        \
     else                                                                                                     \
         hipLaunchKernelGGL((render_bwd_kernel<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
     if (sizeof(T) == 8) {

@@ -48,7 +48,7 @@ def render_targets(P_target, cams_list):
     from paper_2406_18533_amd import raster as R
     cams = R.Cameras(cams_list)
     proj = R.gs_project(P_target, cams)
-    K = int(proj[..., 11].double().sum().item())
+    K = R.instance_count(proj)
     bins = R.Bins(P_target.shape[1], cams, K + 1024)
     R.gs_bin_sort(proj, P_target.shape[1], cams, bins)
     rgb, _, _ = R.gs_render_fwd(proj, P_target.shape[1], bins, cams)
@@ -216,13 +216,11 @@ def workload_counts(tr):
     R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, tr.cfg.bg, tr.sched_fwd, tr.rgb, tr.T, tr.last,
                     tr.work_fwd, tr.work_bwd, pair_stats=stats)
     torch.cuda.synchronize()
-    tiles = tr.proj[..., 11]
-    radius = tr.proj[..., 9]
+    tiles, _ = R.projected_side_arrays(tr.proj)
     return {
         "N": tr.n, "V": tr.V, "pixels": tr.cams.total_pixels(), "tiles": tr.cams.total_tiles(),
         "K": int(tr.bins.n_instances.item()),
         "records_on_screen": int((tiles > 0).sum().item()),
-        "records_in_front": int((radius > 0).sum().item()),
         "gaussians_on_screen": int((tiles > 0).any(dim=0).sum().item()),
         "pairs_evaluated_fwd": int(stats[0].item()),
         "pairs_blended": int(stats[1].item()),
@@ -314,6 +312,21 @@ def roofline(timings: dict, counts: dict):
     out["traffic"] = measured_traffic(dom)
     out["kernel"] = dom
     out["ms"] = round(timings[dom], 4)
+    # the render pair against the HBM roofline, literally: its algorithmic bytes
+    # (40 B per sorted instance for the gathered id and record and 20 B per pixel
+    # written by the forward, plus 24 B per pixel for the fused L1's target and
+    # gradient; the backward the same 40 B per instance, 36 B of gradient
+    # atomics per instance and 20 B per pixel read) over the two kernels' time
+    fwd = "gs_render_fwd_l1" if "gs_render_fwd_l1" in timings else "gs_render_fwd"
+    if fwd in timings and "gs_render_bwd_pixels" in timings:
+        K, Pn = counts["K"], counts["pixels"]
+        b_fwd = 40 * K + 20 * Pn + (24 * Pn if fwd == "gs_render_fwd_l1" else 0)
+        b_bwd = 76 * K + 20 * Pn
+        ms2 = timings[fwd] + timings["gs_render_bwd_pixels"]
+        gbs = (b_fwd + b_bwd) / (ms2 / 1e3) / 1e9
+        out["render_hbm"] = {"kernels": [fwd, "gs_render_bwd_pixels"], "bytes": b_fwd + b_bwd, "ms": round(ms2, 4),
+                             "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4)}
     per = {}
     for k, (b, a) in work.items():
         if k not in timings:
@@ -325,35 +338,71 @@ def roofline(timings: dict, counts: dict):
     return out, per
 
 
-def cpu_baseline(workload, sample_views: int = 6, side: dict | None = None):
-    """The FP64 oracle on a bounded sample: the whole per-view pipeline of one
-    view of the batch (transformation, binning, render, loss, render and
-    transformation backward) plus one Adam step, extrapolated to the batch.
-    With `side` (inputs the side lines captured on the GPU), also the oracle
-    of the L1 + D-SSIM loss on one view of the batch and of one
-    densification of the step's Gaussians."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_step(P, cams, seed: int = 0) -> float:
+    """Seconds of one FP64 oracle training step on the host: transformation,
+    binning, render, L1 loss against seeded random targets, render and
+    transformation backward over every view, then one Adam step with the
+    batch's scaling rules."""
     import numpy as np
     import oracle
-    P = workload.params.double().numpy()
-    cams = workload.cameras[:sample_views]
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     t0 = time.perf_counter()
     f = oracle.forward(P, cams)
     targets = [rng.uniform(size=v["rgb"].shape) for v in f["views"]]
-    loss, g = oracle.l1_loss([v["rgb"] for v in f["views"]], targets)
+    _, g = oracle.l1_loss([v["rgb"] for v in f["views"]], targets)
     grad, _ = oracle.backward(P, cams, f, g)
-    t1 = time.perf_counter()
     m = np.zeros_like(P)
     v = np.zeros_like(P)
-    oracle.adam(P, grad, m, v, [1e-4] * 6, 0.9, 0.999, 1e-15, len(workload.cameras), 1)
-    t2 = time.perf_counter()
-    per_view = (t1 - t0) / sample_views
-    step = per_view * len(workload.cameras) + (t2 - t1)
+    oracle.adam(P.copy(), grad, m, v, [1e-4] * 6, 0.9, 0.999, 1e-15, len(cams), 1)
+    return time.perf_counter() - t0
+
+
+ORACLE_C1_CHILD = (
+    "import json, sys; sys.path.insert(0, {root!r}); import bench; from synthetic import scenes; "
+    "w = scenes.plain_single_view(); P = w.params.double().numpy(); bench.oracle_step(P, w.cameras); "
+    "print(json.dumps(min(bench.oracle_step(P, w.cameras) for _ in range(3))))")
+
+
+def cpu_baseline(workload, side: dict | None = None):
+    """The FP64 oracle (never tuned) on the host cores: one whole training
+    step of the batch (every view), the plain single-view configuration on
+    all cores and on one core (a child process with OMP_NUM_THREADS=1), and,
+    with `side` (inputs the side lines captured), the oracle of the L1 +
+    D-SSIM loss on one view of the batch and of one densification of the
+    step's Gaussians."""
+    import subprocess
+    import oracle
+    from synthetic import scenes
+    P = workload.params.double().numpy()
+    cams = workload.cameras
+    step = oracle_step(P, cams)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    out = {"value": round(len(workload.cameras) / step, 5), "unit": "views/s", "cores": threads, "kind": "oracle",
-           "sample": f"{sample_views} of {len(workload.cameras)} views ({cams[0]['width']}x{cams[0]['height']}, "
-                     f"N={P.shape[1]}), full per-view pipeline in {per_view:.1f} s + Adam in {t2 - t1:.1f} s, "
-                     f"extrapolated linearly to the batch"}
+    out = {"value": round(len(cams) / step, 5), "unit": "views/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"one whole training step of the batch ({len(cams)} views {cams[0]['width']}x{cams[0]['height']}, "
+                     f"N={P.shape[1]}, FP64) in {step:.1f} s"}
+    c1 = scenes.plain_single_view()
+    P1 = c1.params.double().numpy()
+    oracle_step(P1, c1.cameras)
+    t_all = min(oracle_step(P1, c1.cameras) for _ in range(3))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", ORACLE_C1_CHILD.format(root=ROOT)], env=env, capture_output=True,
+                       text=True, timeout=600)
+    t_one = float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    out["single_view_256_10k"] = {"all_cores_ms": round(t_all * 1e3, 2), "cores": threads,
+                                  "one_core_ms": round(t_one * 1e3, 2) if t_one else None,
+                                  "kind": "oracle", "sample": "one whole training step, best of 3"}
     side = side or {}
     if "dssim" in side:
         x, y, V = side["dssim"]
@@ -373,7 +422,7 @@ def cpu_baseline(workload, sample_views: int = 6, side: dict | None = None):
     return out
 
 
-def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, max_views: int = 8):
+def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 4, max_views: int = 8):
     """Render-only serving of a device-resident model (5M clustered
     Gaussians): one-at-a-time capacity, then Poisson arrivals at 0.7x that
     rate through the continuous-batching server (p50/p99 latency = completion
@@ -383,21 +432,25 @@ def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, ma
     from paper_2406_18533_amd.serve import GPUBackend, RenderServer, percentile
     from synthetic import scenes
     P = scenes.serving_scene(n_gaussians).cuda()
-    be = GPUBackend(P, slots=slots, max_views=max_views)
-    probe = [c for _, c in scenes.serving_requests(warmup + 40, qps=1.0, seed=16)]
+    be = GPUBackend(P, slots=slots, max_views=max_views, budget_bytes=16 << 30)
+    probe = [c for _, c in scenes.serving_requests(warmup + 100, qps=1.0, seed=16)]
     # one at a time: service time of single-request batches
     for c in probe[:warmup]:
-        be.render_now(0, [c], 120 << 20)
+        be.render_now(0, [c])
     t0 = time.perf_counter()
     for c in probe[warmup:]:
-        be.render_now(0, [c], 120 << 20)
+        be.render_now(0, [c])
     single = (time.perf_counter() - t0) / (len(probe) - warmup)
     qps = 0.7 / single
-    reqs = scenes.serving_requests(requests, qps=qps, seed=15)
-    srv = RenderServer(be, mem_budget_bytes=8 << 30, max_batch_views=max_views).start()
+    reqs = scenes.serving_requests(requests + warmup, qps=qps, seed=15)
+    srv = RenderServer(be, max_batch_views=max_views).start()
     for _, c in reqs[:warmup]:
         srv.submit(c).result()
     srv.completed.clear()
+    srv.batches.clear()
+    reqs = reqs[warmup:]
+    t_first = reqs[0][0]
+    reqs = [(arr - t_first, c) for arr, c in reqs]
     done = threading.Semaphore(0)
 
     def consume(f):       # a client takes each image as it completes and lets it go
@@ -440,8 +493,62 @@ def serve_bench(n_gaussians: int, requests: int, warmup: int, slots: int = 2, ma
             "service_p50_p99_ms": [round(percentile(service, 50), 3), round(percentile(service, 99), 3)],
             "views_per_s_at_qps": round(requests / t_fixed, 2), "saturation_views_per_s": round(sat, 2),
             "one_at_a_time_views_per_s": round(1.0 / single, 2), "mean_batch": round(mean_batch, 2),
+            "slots": slots, "sort_buffer_bytes_per_slot": be.capacity * 16, "peak_sort_bytes": srv.peak_mem,
             "pinned_image_buffers": be.pool.allocated,
             "resolutions": ["512x512", "1280x720", "1920x1080", "3840x2160"]}
+
+
+def small_configs(reps: int = 50):
+    """The two configurations beside the batch: the plain single view (10,000
+    Gaussians in [-1, 1]^3, one 256x256 view) and the differentiation check's
+    large view (1,000,000 clustered Gaussians, one 1920x1080 view). For each,
+    fwd + bwd of one view through the autograd Function (transformation,
+    binning, render, then the L1 gradient back through render and
+    transformation backward), and one whole training step of the batched
+    trainer with that single view (graph replay, Adam included)."""
+    import torch
+    from paper_2406_18533_amd import raster as R
+    from paper_2406_18533_amd import train
+    from paper_2406_18533_amd.autograd import rasterize
+    from synthetic import scenes
+    out = {}
+    for name, w in [("single_view_256_10k", scenes.plain_single_view()), ("diff_check_1080p_1M", scenes.diff_check_large())]:
+        P = w.params.cuda()
+        targets = render_targets(w.target_params.cuda(), w.cameras)
+        cams = R.Cameras(w.cameras)
+        buf = R.LossBuffers(cams)
+        k = reps if P.shape[1] < 100_000 else max(5, reps // 5)
+
+        def fwd_bwd():
+            Pg = P.detach().requires_grad_(True)
+            rgb = rasterize(Pg, cams)
+            _, dL = R.gs_loss_l1(rgb.detach(), targets, cams, buf)
+            rgb.backward(dL)
+            return Pg.grad
+        fwd_bwd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fwd_bwd()
+        torch.cuda.synchronize()
+        ab = (time.perf_counter() - t0) * 1e3 / k
+        tr = train.BatchedTrainer(P.clone(), w.cameras, targets, train.TrainConfig())
+        for _ in range(3):
+            tr.step()
+            tr.check_overflow()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            tr.step()
+        torch.cuda.synchronize()
+        st = (time.perf_counter() - t0) * 1e3 / k
+        c = w.cameras[0]
+        out[name] = {"gaussians": P.shape[1], "resolution": f"{c['width']}x{c['height']}",
+                     "autograd_fwd_bwd_ms": round(ab, 4), "train_step_ms": round(st, 4),
+                     "views_per_s": round(1e3 / st, 1)}
+        del tr, P, targets, buf
+        torch.cuda.empty_cache()
+    return out
 
 
 def aerial_bench(steps: int, warmup: int, plain: bool):
@@ -502,7 +609,9 @@ def main():
     ap.add_argument("--no-aerial", action="store_true")
     ap.add_argument("--no-dssim", action="store_true")
     ap.add_argument("--no-densify", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="end with a fill and a copy of this many MiB (calibration for HBM byte counters)")
     args = ap.parse_args()
@@ -583,16 +692,21 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving (render-only, continuous batching)")
-        serving = serve_bench(5_000_000, args.serve_requests, warmup=20)
+        serving = serve_bench(5_000_000, args.serve_requests, warmup=args.serve_warmup)
         log(f"serving {json.dumps(serving)}")
     aerial = None
     if not args.no_aerial and args.workload == "batched_1080p":
         log("aerial 4K-class scene (20M Gaussians)")
         aerial = aerial_bench(max(3, min(args.steps, 10)), 2, not args.no_plain)
         log(f"aerial {json.dumps(aerial)}")
+    small = None
+    if not args.no_small and args.workload == "batched_1080p":
+        log("single-view configurations (256x256 10k, 1080p 1M)")
+        small = small_configs()
+        log(f"small {json.dumps(small)}")
     cpu = None
     if not args.no_cpu:
-        log("CPU oracle baseline (sample)")
+        log("CPU oracle baseline (whole step of the batch)")
         cpu = cpu_baseline(w, side=side)
     if args.copy_mib:
         log(f"calibration: fill then copy of {args.copy_mib} MiB")
@@ -615,10 +729,12 @@ def main():
         "plain_path": plain,
         "speedup_vs_plain": round(views_s / plain["views_per_s"], 3) if plain else None,
         "aerial_4k": aerial,
+        "single_view": small,
         "l1_dssim": dssim,
         "densify": dens,
         "serving": serving,
         "roofline": roof,
+        "render_hbm_frac": roof.get("render_hbm", {}).get("frac"),
         "per_kernel": per,
         "counts": counts,
         "cpu_baseline": cpu,

@@ -1,16 +1,29 @@
 """Continuous-batching render server for a device-resident trained model.
 
 Requests (one camera each, any resolution) arrive at any time. A loop
-thread forms batches from the queue in arrival order and admits them while
-both a render slot (a stream with its own buffers) and sort-buffer memory
-(the instance capacity the batch needs, at 16 bytes per instance) are free;
-requests that arrive while earlier batches are still on the GPU join the
-next batch as soon as a slot and memory free up, so batches overlap on the
-device. Each batch is one gs_project + gs_bin_sort + gs_render_fwd over all
-its views: the (view, tile) work queue of the batch is flattened exactly as
-in training. A request's image does not depend on what else is in its batch
-(tiles are per view and every pixel's list is ordered by (depth, index)), so
-a result is the same alone and in the mix.
+thread keeps up to `slots` batches on the GPU at once, each on a render slot
+of its own (a stream with its own projected buffer and a fixed share of the
+sort-buffer memory: budget / slots bytes, 16 per sorted instance). A batch
+goes through two stages:
+
+1. probe: the requests at the head of the queue (arrival order, up to
+   max_views) are projected together (gs_project) and the exact number of
+   sorted instances K of each view is read back (the sum of its tiles
+   touched);
+2. render: the longest prefix of those views whose instances fit the slot's
+   sort buffers is admitted (the rest go back to the head of the queue, and
+   the prefix is projected again on its own when it is shorter), then
+   gs_bin_sort + gs_render_fwd run over its flattened (view, tile) work queue
+   exactly as in training and the images are copied to page-locked host
+   memory.
+
+Admission is thus by measured sort-buffer memory (no estimate, no overflow,
+no re-render). Requests that arrive while batches are on the GPU join the
+next batch as soon as a slot frees up, so batches overlap on the device. A
+request's image does not depend on what else is in its batch (tiles are per
+view and every pixel's list is ordered by (depth, index)), so a result is
+the same alone and in the mix. A single view whose K exceeds a slot's share
+fails with ValueError.
 
 The backend is separate from the loop: GPUBackend calls libgs.so; tests also
 drive the loop with a CPU fake to check admission and ordering without a GPU.
@@ -32,30 +45,8 @@ class Request:
     cam: dict
     arrival: float
     future: Future = field(default_factory=Future)
-    est_instances: int = 0
     start: float = 0.0
     done: float = 0.0
-
-
-class InstanceEstimator:
-    """Running estimate of sorted instances per pixel, by resolution."""
-
-    def __init__(self, per_pixel: float = 8.0, margin: float = 1.3):
-        self.rate = {}
-        self.default = per_pixel
-        self.margin = margin
-
-    def estimate(self, cam: dict) -> int:
-        px = cam["width"] * cam["height"]
-        r = self.rate.get((cam["width"], cam["height"]), self.default)
-        return int(px * r * self.margin) + 4096
-
-    def observe(self, cam: dict, k: int):
-        key = (cam["width"], cam["height"])
-        px = cam["width"] * cam["height"]
-        old = self.rate.get(key)
-        new = k / max(px, 1)
-        self.rate[key] = new if old is None else max(new, 0.8 * old + 0.2 * new)
 
 
 class PinnedPool:
@@ -91,22 +82,41 @@ class PinnedPool:
 
 class GPUBackend:
     """Render slots on separate streams over one device-resident model. Each
-    slot owns a projected buffer sized for max_views views; a smaller batch
-    uses its front (records, then the side arrays right after them). Images
-    come back to the host in pooled page-locked buffers (see PinnedPool)."""
+    slot owns a projected buffer for max_views views (a smaller batch uses
+    its front) and sort buffers for `capacity` instances (the memory budget
+    split evenly over the slots) and up to max_tiles tiles. Images come back
+    to the host in pooled page-locked buffers (see PinnedPool)."""
 
-    def __init__(self, params, slots: int = 2, max_views: int = 8, bg=(0.0, 0.0, 0.0)):
+    def __init__(self, params, slots: int = 4, max_views: int = 8, budget_bytes: int = 16 << 30,
+                 max_tiles: int = 8 * 240 * 135, bg=(0.0, 0.0, 0.0)):
         import torch
+        from . import _lib
         from . import raster as R
-        self.torch, self.R = torch, R
+        self.torch, self.R, self._lib = torch, R, _lib
         self.P = params.contiguous()
         self.n = self.P.shape[1]
         self.bg = bg
         self.max_views = max_views
+        self.max_tiles = max_tiles
+        self.capacity = max(int(budget_bytes) // max(slots, 1) // BYTES_PER_INSTANCE, 1)
+        dev = self.P.device
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
-        self.flat = [R.alloc_projected(self.n, max_views, torch.float32, self.P.device) for _ in range(slots)]
-        self.counts = [torch.empty(2, dtype=torch.int64, pin_memory=True) for _ in range(slots)]
+        self.flat = [R.alloc_projected(self.n, max_views, torch.float32, dev) for _ in range(slots)]
+        wsb = int(_lib.load().gs_bin_workspace_bytes(self.n, max_views, self.capacity, max_tiles))
+        self.bufs = []
+        for _ in range(slots):
+            self.bufs.append({
+                "keys": torch.empty(self.capacity, dtype=torch.int32, device=dev),
+                "ids": torch.empty(self.capacity, dtype=torch.int32, device=dev),
+                "ranges": torch.empty(max_tiles, 2, dtype=torch.int32, device=dev),
+                "k": torch.zeros(1, dtype=torch.int64, device=dev),
+                "over": torch.zeros(1, dtype=torch.int32, device=dev),
+                "ws": torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)})
+        self.kview = [torch.zeros(max_views, dtype=torch.int64, pin_memory=True) for _ in range(slots)]
+        self.counts = [torch.zeros(2, dtype=torch.int64, pin_memory=True) for _ in range(slots)]
         self.pool = PinnedPool(torch)
+        self.probing = {}
+        self.probed = {}
         self.inflight = {}
 
     @property
@@ -118,16 +128,63 @@ class GPUBackend:
         flat = self.torch.as_strided(base, (base.numel(),), (1,), base.storage_offset())
         return flat[: V * self.n * 12].view(V, self.n, 12)
 
-    def launch(self, slot: int, cams_list: list, capacity: int):
-        """Renders a batch on the slot's stream (returns at once)."""
+    def _bins(self, slot: int, cams):
+        """A Bins-like view of the slot's sort buffers for this camera set."""
+        b = self.bufs[slot]
+        T = cams.total_tiles()
+        if T > self.max_tiles:
+            raise ValueError(f"{T} tiles exceed the slot's {self.max_tiles}")
+
+        class _B:
+            pass
+        x = _B()
+        x.capacity, x.total_tiles = self.capacity, T
+        x.ids, x.ranges, x.n_instances, x.overflow = b["ids"], b["ranges"], b["k"], b["over"]
+        x.struct = self._lib.GsBins(self.capacity, b["keys"].data_ptr(), b["ids"].data_ptr(), b["ranges"].data_ptr(),
+                                    b["k"].data_ptr(), b["over"].data_ptr(), b["ws"].data_ptr(), b["ws"].numel())
+        return x
+
+    def probe(self, slot: int, cams_list: list):
+        """Projects the views on the slot's stream and reads back each view's
+        instance count (returns at once; see probe_result)."""
+        torch, R = self.torch, self.R
+        V = len(cams_list)
+        assert V <= self.max_views
+        with torch.cuda.stream(self.streams[slot]):
+            cams = R.Cameras(cams_list)
+            view = self._proj_view(slot, V)
+            R.gs_project(self.P, cams, view)
+            tiles, _ = R.projected_side_arrays(view)
+            self.kview[slot][:V].copy_(tiles.sum(dim=1, dtype=torch.int64), non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.streams[slot])
+        self.probing[slot] = (ev, cams, V)
+
+    def probe_result(self, slot: int):
+        """None while the probe runs; else the exact K of each view."""
+        ev, cams, V = self.probing[slot]
+        if not ev.query():
+            return None
+        del self.probing[slot]
+        self.probed[slot] = cams          # reused by a launch of the same views
+        return [int(k) for k in self.kview[slot][:V]]
+
+    def launch(self, slot: int, cams_list: list, reproject: bool):
+        """Bins and renders the views on the slot's stream (returns at once).
+        The projected records must be the slot's for exactly these views:
+        from the probe, or projected again here when reproject is set."""
         torch, R = self.torch, self.R
         s = self.streams[slot]
-        assert len(cams_list) <= self.max_views
+        probed = self.probed.pop(slot, None)
         with torch.cuda.stream(s):
-            cams = R.Cameras(cams_list)
+            if reproject or probed is None or probed.n != len(cams_list):
+                cams = R.Cameras(cams_list)
+            else:
+                cams = probed
             view = self._proj_view(slot, len(cams_list))
-            R.gs_project(self.P, cams, view)
-            bins = R.Bins(self.n, cams, capacity)
+            if reproject:
+                R.gs_project(self.P, cams, view)
+            bins = self._bins(slot, cams)
             R.gs_bin_sort(view, self.n, cams, bins, check_capacity=False)
             rgb, _, _ = R.gs_render_fwd(view, self.n, bins, cams, self.bg)
             host, o = [], 0
@@ -142,7 +199,7 @@ class GPUBackend:
             k_host[1:2].copy_(bins.overflow.to(torch.int64), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        self.inflight[slot] = (ev, host, k_host, cams_list, bins, rgb, cams)
+        self.inflight[slot] = (ev, host, k_host, cams_list, rgb, cams)
 
     def poll(self, slot: int):
         """None while running; else (images, instance count, overflowed)."""
@@ -153,8 +210,16 @@ class GPUBackend:
         out = [self.pool.lend(buf, (3, c["height"], c["width"])) for buf, c in zip(host, cams_list)]
         return out, int(k_host[0]), bool(k_host[1])
 
-    def render_now(self, slot: int, cams_list: list, capacity: int):
-        self.launch(slot, cams_list, capacity)
+    def render_now(self, slot: int, cams_list: list):
+        """Probe and render one batch, waiting for each (one at a time)."""
+        self.probe(slot, cams_list)
+        while True:
+            ks = self.probe_result(slot)
+            if ks is not None:
+                break
+        if sum(ks) > self.capacity:
+            raise ValueError(f"{sum(ks)} instances exceed a slot's {self.capacity}")
+        self.launch(slot, cams_list, reproject=False)
         while True:
             r = self.poll(slot)
             if r is not None:
@@ -162,27 +227,26 @@ class GPUBackend:
 
 
 class RenderServer:
-    def __init__(self, backend, mem_budget_bytes: int, max_batch_views: int = 8, estimator=None):
+    def __init__(self, backend, mem_budget_bytes: int | None = None, max_batch_views: int = 8):
         self.backend = backend
-        self.budget = int(mem_budget_bytes)
         self.max_views = max_batch_views
-        self.est = estimator or InstanceEstimator()
+        self.budget = mem_budget_bytes if mem_budget_bytes is not None else \
+            backend.slots * backend.capacity * BYTES_PER_INSTANCE
         self.queue = collections.deque()
         self.lock = threading.Lock()
         self.cv = threading.Condition(self.lock)
-        self.free_slots = list(range(backend.slots))
-        self.running = {}            # slot -> (requests, bytes)
+        self.state = {s: None for s in range(backend.slots)}     # None, ("probe", batch), ("render", batch, bytes)
         self.mem_used = 0
         self.peak_mem = 0
         self.completed = []
         self.batches = []
+        self.probes = 0
         self._stop = False
         self._thread = None
 
     # -- client side ------------------------------------------------------------------------
     def submit(self, cam: dict) -> Future:
         r = Request(cam, time.perf_counter())
-        r.est_instances = self.est.estimate(cam)
         with self.cv:
             self.queue.append(r)
             self.cv.notify()
@@ -201,72 +265,82 @@ class RenderServer:
             self._thread.join()
 
     # -- the loop ----------------------------------------------------------------------------
-    def _admit(self):
-        """Forms the next batch in arrival order within the free memory."""
-        batch, need = [], 0
-        free = self.budget - self.mem_used
-        while self.queue and len(batch) < self.max_views:
-            r = self.queue[0]
-            b = r.est_instances * BYTES_PER_INSTANCE
-            if b > self.budget:
-                b = self.budget          # a request larger than the pool runs alone
-            if need + b > free:
-                break
-            batch.append(self.queue.popleft())
-            need += b
-        return batch, need
+    def _busy(self) -> bool:
+        return any(st is not None for st in self.state.values())
 
     def _loop(self):
         while True:
             with self.cv:
-                if self._stop and not self.queue and not self.running:
+                if self._stop and not self.queue and not self._busy():
                     return
-                launch = None
-                if self.free_slots and self.queue:
-                    batch, need = self._admit()
-                    if batch:
-                        slot = self.free_slots.pop()
-                        self.mem_used += need
-                        self.peak_mem = max(self.peak_mem, self.mem_used)
-                        self.running[slot] = (batch, need)
-                        launch = (slot, batch, need)
-                if launch is None and not self.running:
+                probe = None
+                free = [s for s, st in self.state.items() if st is None]
+                if free and self.queue:
+                    batch = [self.queue.popleft() for _ in range(min(self.max_views, len(self.queue)))]
+                    self.state[free[0]] = ("probe", batch)
+                    probe = (free[0], batch)
+                if probe is None and not self._busy():
                     self.cv.wait(timeout=0.001)
                     continue
-            if launch is not None:
-                slot, batch, need = launch
-                now = time.perf_counter()
-                for r in batch:
-                    r.start = now
-                self.backend.launch(slot, [r.cam for r in batch], need // BYTES_PER_INSTANCE)
-                self.batches.append(len(batch))
-            self._reap()
-            if launch is None:
-                time.sleep(0.0001)
+            if probe is not None:
+                slot, batch = probe
+                self.backend.probe(slot, [r.cam for r in batch])
+                self.probes += 1
+            self._advance()
+            if probe is None:
+                time.sleep(0.00002)
 
-    def _reap(self):
-        for slot in list(self.running.keys()):
-            res = self.backend.poll(slot)
-            if res is None:
+    def _advance(self):
+        cap = self.backend.capacity
+        for slot, st in list(self.state.items()):
+            if st is None:
                 continue
-            images, k, overflow = res
-            batch, need = self.running[slot]
-            if overflow:
-                # the estimate was too small: render the batch again on the same
-                # slot with the exact count (nothing was written past capacity)
-                images, k, overflow = self.backend.render_now(slot, [r.cam for r in batch], int(k * 1.05) + 1024)
-            with self.cv:
-                self.running.pop(slot)
-                self.mem_used -= need
-                self.free_slots.append(slot)
-            now = time.perf_counter()
-            per = k / max(sum(r.cam["width"] * r.cam["height"] for r in batch), 1)
-            for r, img in zip(batch, images):
-                self.est.observe(r.cam, int(per * r.cam["width"] * r.cam["height"]))
-                r.done = now
-                self.completed.append((r.arrival, r.start, r.done))   # timestamps only, not the image
-                r.future.set_result(img)
-            del images, batch
+            if st[0] == "probe":
+                ks = self.backend.probe_result(slot)
+                if ks is None:
+                    continue
+                batch = st[1]
+                m, total = 0, 0
+                while m < len(batch) and total + ks[m] <= cap:
+                    total += ks[m]
+                    m += 1
+                if m == 0:                      # one view alone needs more than a slot's sort buffers
+                    r = batch[0]
+                    r.future.set_exception(ValueError(
+                        f"a {r.cam['width']}x{r.cam['height']} view needs {ks[0]} sorted instances, more than a "
+                        f"render slot's {cap}"))
+                    with self.cv:
+                        self.queue.extendleft(reversed(batch[1:]))
+                        self.state[slot] = None
+                    continue
+                with self.cv:
+                    if m < len(batch):          # the rest waits at the head of the queue
+                        self.queue.extendleft(reversed(batch[m:]))
+                    need = total * BYTES_PER_INSTANCE
+                    self.mem_used += need
+                    self.peak_mem = max(self.peak_mem, self.mem_used)
+                    self.state[slot] = ("render", batch[:m], need)
+                now = time.perf_counter()
+                for r in batch[:m]:
+                    r.start = now
+                self.backend.launch(slot, [r.cam for r in batch[:m]], reproject=m < len(batch))
+                self.batches.append(m)
+            else:
+                res = self.backend.poll(slot)
+                if res is None:
+                    continue
+                images, k, overflow = res
+                _, batch, need = st
+                assert not overflow, "a batch admitted by its measured instance count overflowed"
+                with self.cv:
+                    self.state[slot] = None
+                    self.mem_used -= need
+                now = time.perf_counter()
+                for r, img in zip(batch, images):
+                    r.done = now
+                    self.completed.append((r.arrival, r.start, r.done))   # timestamps only, not the image
+                    r.future.set_result(img)
+                del images, batch
 
     # -- statistics -------------------------------------------------------------------------
     def latencies_ms(self):

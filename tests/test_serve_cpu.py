@@ -1,48 +1,62 @@
 """The render server's request loop driven by a CPU fake backend: every
-request completes, batches are formed in arrival order, sort-buffer memory
-never exceeds the budget, and an undersized estimate is re-rendered."""
+request completes, batches are formed in arrival order and admitted by their
+measured instance counts within a slot's sort buffers (never beyond the
+budget), a batch that does not fit is split with the rest kept at the head
+of the queue, and a view larger than a slot fails alone."""
 import threading
 import time
 
 import numpy as np
+import pytest
 
-from paper_2406_18533_amd.serve import BYTES_PER_INSTANCE, InstanceEstimator, RenderServer, percentile
+from paper_2406_18533_amd.serve import BYTES_PER_INSTANCE, RenderServer, percentile
 
 
 class FakeBackend:
-    """Renders a cam to a deterministic image after a short delay; reports K =
-    2 instances per pixel."""
+    """Renders a cam to a deterministic image after a short delay; a view
+    has K = 2 instances per pixel, known after a probe."""
 
-    def __init__(self, slots=2, delay=0.002):
+    def __init__(self, slots=2, capacity=10 ** 9, delay=0.002):
         self.slots = slots
+        self.capacity = capacity
         self.delay = delay
-        self.inflight = {}
+        self.probing, self.inflight = {}, {}
         self.launches = []
-        self.lock = threading.Lock()
+        self.probes = []
 
     @staticmethod
     def image(cam):
         return np.full((3, cam["height"], cam["width"]), cam["id"], dtype=np.float32)
 
-    def launch(self, slot, cams, capacity):
+    @staticmethod
+    def k(cam):
+        return 2 * cam["width"] * cam["height"]
+
+    def probe(self, slot, cams):
+        assert slot not in self.probing and slot not in self.inflight
+        self.probes.append((slot, [c["id"] for c in cams]))
+        self.probing[slot] = (time.perf_counter() + self.delay / 4, cams)
+
+    def probe_result(self, slot):
+        t, cams = self.probing[slot]
+        if time.perf_counter() < t:
+            return None
+        del self.probing[slot]
+        return [self.k(c) for c in cams]
+
+    def launch(self, slot, cams, reproject):
         assert slot not in self.inflight
-        k = sum(2 * c["width"] * c["height"] for c in cams)
-        self.launches.append((slot, [c["id"] for c in cams], capacity))
-        self.inflight[slot] = (time.perf_counter() + self.delay, cams, k, k > capacity)
+        k = sum(self.k(c) for c in cams)
+        assert k <= self.capacity
+        self.launches.append((slot, [c["id"] for c in cams], reproject))
+        self.inflight[slot] = (time.perf_counter() + self.delay, cams, k)
 
     def poll(self, slot):
-        t, cams, k, over = self.inflight[slot]
+        t, cams, k = self.inflight[slot]
         if time.perf_counter() < t:
             return None
         del self.inflight[slot]
-        return [self.image(c) for c in cams], k, over
-
-    def render_now(self, slot, cams, capacity):
-        self.launch(slot, cams, capacity)
-        while True:
-            r = self.poll(slot)
-            if r is not None:
-                return r
+        return [self.image(c) for c in cams], k, False
 
 
 def _cam(i, w=32, h=24):
@@ -50,9 +64,9 @@ def _cam(i, w=32, h=24):
 
 
 def test_all_requests_complete_in_order_within_budget():
-    be = FakeBackend(slots=2)
-    budget = 40 * 32 * 24 * BYTES_PER_INSTANCE      # a few requests' worth of instances
-    srv = RenderServer(be, budget, max_batch_views=4, estimator=InstanceEstimator(per_pixel=2.0, margin=1.0)).start()
+    cap = 5 * 2 * 64 * 24                  # a few requests' worth of instances per slot
+    be = FakeBackend(slots=2, capacity=cap)
+    srv = RenderServer(be, max_batch_views=4).start()
     futs = []
     for i in range(40):
         futs.append(srv.submit(_cam(i, 32 + (i % 3) * 16, 24)))
@@ -62,7 +76,7 @@ def test_all_requests_complete_in_order_within_budget():
         img = f.result(timeout=10)
         assert img.shape[0] == 3 and (img == i).all()
     srv.stop()
-    assert srv.peak_mem <= budget
+    assert srv.budget == 2 * cap * BYTES_PER_INSTANCE and srv.peak_mem <= srv.budget
     order = [i for _, ids, _ in be.launches for i in ids]
     assert order == sorted(order) and len(order) == 40
     assert max(srv.batches) > 1                    # requests were batched
@@ -70,22 +84,50 @@ def test_all_requests_complete_in_order_within_budget():
     assert percentile(lat, 50) <= percentile(lat, 99)
 
 
-def test_tiny_budget_still_serves_one_at_a_time():
-    be = FakeBackend(slots=2)
-    srv = RenderServer(be, 1, max_batch_views=8).start()
-    futs = [srv.submit(_cam(i)) for i in range(6)]
+def test_batch_larger_than_a_slot_is_split_and_the_rest_waits_first():
+    """Four queued 32x24 views (1536 instances each) against a slot of 3500:
+    the probe of all four admits the first two, re-projected on their own,
+    and the other two form the next batch ahead of later arrivals."""
+    be = FakeBackend(slots=1, capacity=3500, delay=0.01)
+    srv = RenderServer(be, max_batch_views=4)
+    futs = [srv.submit(_cam(i)) for i in range(4)]       # queued before the loop starts
+    srv.start()
+    time.sleep(0.002)
+    futs.append(srv.submit(_cam(4)))
     for i, f in enumerate(futs):
         assert (f.result(timeout=10) == i).all()
     srv.stop()
-    assert max(srv.batches) == 1
+    assert be.probes[0] == (0, [0, 1, 2, 3])
+    assert be.launches[0] == (0, [0, 1], True)           # a prefix: projected again
+    assert be.launches[1][1] == [2, 3]                   # the rest, before request 4
+    assert [i for _, ids, _ in be.launches for i in ids] == [0, 1, 2, 3, 4]
 
 
-def test_underestimated_batch_is_rendered_again():
-    be = FakeBackend(slots=1)
-    est = InstanceEstimator(per_pixel=0.1, margin=1.0)   # far below the true 2 per pixel
-    srv = RenderServer(be, 10 ** 9, max_batch_views=2, estimator=est).start()
-    f = srv.submit(_cam(3, 64, 64))
-    assert (f.result(timeout=10) == 3).all()
+def test_view_larger_than_a_slot_fails_alone():
+    be = FakeBackend(slots=1, capacity=2 * 32 * 24)
+    srv = RenderServer(be, max_batch_views=4).start()
+    big = srv.submit(_cam(0, 64, 64))
+    small = srv.submit(_cam(1))
+    with pytest.raises(ValueError):
+        big.result(timeout=10)
+    assert (small.result(timeout=10) == 1).all()
     srv.stop()
-    assert len(be.launches) == 2 and be.launches[1][2] >= 2 * 64 * 64
-    assert est.rate[(64, 64)] >= 1.9
+
+
+def test_concurrent_submitters():
+    be = FakeBackend(slots=3, capacity=4 * 2 * 32 * 24)
+    srv = RenderServer(be, max_batch_views=8).start()
+    results = {}
+
+    def client(base):
+        fs = [(base + k, srv.submit(_cam(base + k))) for k in range(20)]
+        for i, f in fs:
+            results[i] = f.result(timeout=10)
+    th = [threading.Thread(target=client, args=(100 * t,)) for t in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    srv.stop()
+    assert len(results) == 80 and all((img == i).all() for i, img in results.items())
+    assert srv.peak_mem <= srv.budget

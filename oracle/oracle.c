@@ -413,6 +413,7 @@ int64_t oracle_bin(const float *u, const float *v, const float *r, const float *
 typedef struct {
     int inside;    /* passes the circle test and power <= 0 */
     double dx, dy, G, og, alpha;
+    double alpha_rel;   /* bound on the relative rounding error of alpha in FP32 */
 } pair_t;
 
 /* Ambiguity margins. A decision is ambiguous when the quantity it compares
@@ -466,9 +467,18 @@ static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py
     e->G = exp(power);
     e->og = o * e->G;
     e->alpha = e->og < ALPHA_MAX ? e->og : ALPHA_MAX;
-    /* alpha threshold in the log domain: rounding of the exponent, plus the
-     * exponent's change when the centre moves by pos_tol */
-    double lmargin = 1e-5 + 1e-5 * fabs(power) + 2.0 * sqrt(fabs(power) * (a + c)) * pt;
+    /* Rounding of the exponent in FP32: its three terms are formed and summed
+     * with a few roundings each, so the error is bounded by a small multiple
+     * of the unit roundoff times S = |qa| + |qb| + |qc| (not |power|: for a
+     * thin footprint the terms are large and cancel), plus the exp and the
+     * opacity product: about 9 u S + 4 u with u = 2^-24; four times that is
+     * taken. Against another implementation's own projection the exponent
+     * also carries its conic's error (1e-5 relative to the terms) and the
+     * change when the centre moves by pos_tol. */
+    double S = fabs(qa) + fabs(qb) + fabs(qc);
+    double rel = 1e-6 + 2e-6 * S + (pt > 0.0 ? 1e-5 * S : 0.0);
+    e->alpha_rel = e->og < ALPHA_MAX ? rel : 1e-7;
+    double lmargin = rel + 2.0 * sqrt(fabs(power) * (a + c)) * pt;
     amb = fabs(log(e->alpha / ALPHA_MIN)) <= lmargin;
     if (!decide(am, e->alpha >= ALPHA_MIN, amb)) return;
     e->inside = 1;
@@ -496,6 +506,10 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
     uint32_t lastp = 0, nc = 0;
     int64_t prev = -1;
     int64_t ev = 0;
+    /* bound on the relative error of T in FP32: per blend the update's own
+     * roundings, plus 1 - alpha's, which grows as alpha / (1 - alpha) times
+     * alpha's relative error */
+    double t_rel = 0.0;
     for (int64_t k = 0; k < n; k++) {
         /* two adjacent entries of the list that both reach this pixel and
          * whose FP32 depths nearly tie: the compared implementation (which
@@ -516,13 +530,15 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
             ev++;
             if (!e.inside) continue;
             double Tn = T * (1.0 - e.alpha);
-            int amb = fabs(Tn - T_MIN) <= (tol ? tol->t_tol : 1e-5) * T_MIN;
+            double tr = t_rel + 2.4e-7 + e.alpha / (1.0 - e.alpha) * e.alpha_rel;
+            int amb = fabs(Tn - T_MIN) <= ((tol ? tol->t_tol : 1e-5) + tr) * T_MIN;
             if (decide(am, Tn < T_MIN, amb)) { stop = 1; break; }
             /* a near tie with a contributor that is not the adjacent entry */
             if (am && depth_check && prev >= 0 && (int64_t)lastp != pos && depth_near(proj, N, (uint32_t)prev, id))
                 am->unresolved = 1;
             for (int ch = 0; ch < 3; ch++) C[ch] += proj[(7 + ch) * N + id] * e.alpha * T;
             T = Tn;
+            t_rel = tr;
             lastp = (uint32_t)(pos + 1);
             nc++;
             prev = id;

@@ -240,3 +240,30 @@ def test_behind_near_plane_contributes_nothing(small_scene):
     g = np.random.default_rng(0).normal(size=v2["rgb"].shape)
     grad, _ = oracle.backward(P2, [cam], f2, [g])
     assert (grad[:, -3:] == 0).all()
+
+
+# --------------------------------------------------------------------------- near-threshold decisions
+def test_alpha_threshold_margin_scales_with_the_exponent_terms():
+    """A decision on alpha >= 1/255 is near-threshold within the FP32
+    evaluation's rounding, which grows with S = |qa| + |qb| + |qc| (the terms
+    of the exponent before they cancel), not with the exponent itself. A thin
+    footprint (conic (k, -k(1-e), k), evaluated along its long axis) with
+    S ~ 3200 whose alpha is 1e-3 above the threshold in the log domain is
+    flagged; the same log distance on an isotropic footprint (S = |power|
+    ~ 4.8) is not."""
+    o, k, d = 0.5, 100.0, 4.0
+    target = math.log(1.0 / (255.0 * o)) + 1e-3            # alpha a little above 1/255
+    eps = -target / (k * d * d)
+    u = v = 10.5 - d                                       # pixel (10, 10) at offset (d, d)
+    thin = _proj([{"u": u, "v": v, "conic": (k, -k * (1 - eps), k), "o": o, "rgb": [1, 0, 0], "r": 8}])
+    S = 0.5 * k * d * d + k * (1 - eps) * d * d + 0.5 * k * d * d
+    assert S > 3000
+    out = _render(thin, _cam(24, 24))
+    assert out["amb"][10, 10] == 1
+    # its other branch: the Gaussian skipped, so the background shows
+    assert out["rgb"][0, 10, 10] > 0 and out["rgb_alt"][0, 10, 10] == 0
+    # isotropic: power = -(d2 / 2) sig^-2 at the same log distance
+    sig2 = 2 * d * d / (2 * -target)
+    iso = _proj([{"u": u, "v": v, "conic": (1 / sig2, 0, 1 / sig2), "o": o, "rgb": [1, 0, 0], "r": 8}])
+    out = _render(iso, _cam(24, 24))
+    assert out["amb"][10, 10] == 0 and out["rgb"][0, 10, 10] > 0

@@ -39,7 +39,7 @@ def lib():
         L.oracle_bin.argtypes = [d, d, d, d, i64, i32, d, d, i64, d, d, d]
         L.oracle_bin.restype = i64
         L.oracle_render.argtypes = [d, i64, i32, i32, d, d, d, d, i32, C.c_double, C.c_double, d, d, d, d, d, d,
-                                    d, d, d]
+                                    d, d, d, d]
         L.oracle_render_brute.argtypes = [d, i64, i32, i32, d, d, d, d]
         L.oracle_render_bwd.argtypes = [d, i64, i32, i32, d, d, d, d, d]
         L.oracle_render_bwd.restype = C.c_int
@@ -146,7 +146,10 @@ def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, 
     rightly take either branch: 0 none; 1 exactly one, and "rgb_alt",
     "T_alt", "last_alt" hold the result with that decision taken the other
     way; 2 more than one, or two contributors whose depth order is a near
-    tie. fragile/depth_check/pos_tol/t_tol only widen those margins."""
+    tie. fragile/depth_check/pos_tol/t_tol only widen those margins.
+    "bound" is a first-order bound, per pixel, of how far an FP32 walk may
+    put colour and T from these values, from each blended alpha's relative
+    error bound (large only where a thin footprint's exponent terms cancel)."""
     proj = _f64(proj)
     N = proj.shape[1]
     W, H = cam["width"], cam["height"]
@@ -162,12 +165,14 @@ def render(proj, cam: dict, ids, ranges_view, bg=(0.0, 0.0, 0.0), fragile=None, 
     nc = np.zeros((H, W), dtype=np.uint32)
     amb = np.zeros((H, W), dtype=np.uint8)
     counts = np.zeros(2, dtype=np.int64)
+    bound = np.zeros((H, W))
     fr = None if fragile is None else np.ascontiguousarray(fragile, dtype=np.uint8)
     lib().oracle_render(_p(proj), N, W, H, _p(ids) if ids.size else None, _p(ranges_view), _p(bgv),
                         _p(fr) if fr is not None else None, int(depth_check), float(pos_tol), float(t_tol),
-                        _p(rgb), _p(T), _p(last), _p(nc), _p(amb), _p(counts), _p(rgb_alt), _p(T_alt), _p(last_alt))
+                        _p(rgb), _p(T), _p(last), _p(nc), _p(amb), _p(counts), _p(rgb_alt), _p(T_alt), _p(last_alt),
+                        _p(bound))
     return {"rgb": rgb, "T": T, "last": last, "ncontrib": nc, "amb": amb,
-            "rgb_alt": rgb_alt, "T_alt": T_alt, "last_alt": last_alt,
+            "rgb_alt": rgb_alt, "T_alt": T_alt, "last_alt": last_alt, "bound": bound,
             "evaluated": int(counts[0]), "blended": int(counts[1])}
 
 
@@ -176,7 +181,9 @@ def image_mismatch(o: dict, rgb, T=None, last=None, tol: float = 1e-5):
     render ``o``. A pixel with no ambiguous decision must match the oracle's
     result; one with exactly one must match either branch (its colour, and T
     and last when given, all from the same branch); pixels of class 2 are
-    left out. Returns (max error over the compared pixels, mask of those
+    left out. A pixel whose FP32 error bound ("bound") exceeds tol may
+    differ by that bound instead: the error reported for it is what exceeds
+    bound - tol. Returns (max error over the compared pixels, mask of those
     pixels, number of class-1 pixels that matched the alternative)."""
     rgb = np.asarray(rgb, dtype=np.float64)
 
@@ -192,6 +199,8 @@ def image_mismatch(o: dict, rgb, T=None, last=None, tol: float = 1e-5):
     e1 = err(o["rgb_alt"], o["T_alt"], o["last_alt"])
     cls = o["amb"]
     e = np.where(cls == 0, e0, np.minimum(e0, e1))
+    if "bound" in o:
+        e = e - np.maximum(o["bound"] - tol, 0.0)
     compared = cls <= 1
     took_alt = int(((cls == 1) & (e1 < e0) & (e1 <= tol)).sum())
     return float(np.max(e[compared], initial=0.0)), compared, took_alt

@@ -413,7 +413,8 @@ int64_t oracle_bin(const float *u, const float *v, const float *r, const float *
 typedef struct {
     int inside;    /* passes the circle test and power <= 0 */
     double dx, dy, G, og, alpha;
-    double alpha_rel;   /* bound on the relative rounding error of alpha in FP32 */
+    double alpha_rel;   /* bound on the relative error of alpha in FP32 */
+    double alpha_mrel;  /* the decision margin's relative width (alpha_rel with a 4x safety) */
 } pair_t;
 
 /* Ambiguity margins. A decision is ambiguous when the quantity it compares
@@ -471,14 +472,18 @@ static void eval_pair(const double *proj, int64_t N, uint32_t id, int px, int py
      * with a few roundings each, so the error is bounded by a small multiple
      * of the unit roundoff times S = |qa| + |qb| + |qc| (not |power|: for a
      * thin footprint the terms are large and cancel), plus the exp and the
-     * opacity product: about 9 u S + 4 u with u = 2^-24; four times that is
-     * taken. Against another implementation's own projection the exponent
-     * also carries its conic's error (1e-5 relative to the terms) and the
-     * change when the centre moves by pos_tol. */
+     * opacity product: about 9 u S + 4 u with u = 2^-24 (alpha_rel); four
+     * times that is the decision margin. Against another implementation's
+     * own projection the exponent also carries its conic's error (1e-5
+     * relative to the terms) and the change when the centre moves by
+     * pos_tol. */
     double S = fabs(qa) + fabs(qb) + fabs(qc);
-    double rel = 1e-6 + 2e-6 * S + (pt > 0.0 ? 1e-5 * S : 0.0);
-    e->alpha_rel = e->og < ALPHA_MAX ? rel : 1e-7;
-    double lmargin = rel + 2.0 * sqrt(fabs(power) * (a + c)) * pt;
+    double ulp = 5.9604644775390625e-8;                 /* 2^-24 */
+    double cr = (pt > 0.0 ? 1e-5 * S : 0.0);
+    double mrel = 1e-6 + 2e-6 * S + cr;
+    e->alpha_rel = e->og < ALPHA_MAX ? 9.0 * ulp * S + 4.0 * ulp + cr : 1e-7;
+    e->alpha_mrel = e->og < ALPHA_MAX ? mrel : 1e-7;
+    double lmargin = mrel + 2.0 * sqrt(fabs(power) * (a + c)) * pt;
     amb = fabs(log(e->alpha / ALPHA_MIN)) <= lmargin;
     if (!decide(am, e->alpha >= ALPHA_MIN, amb)) return;
     e->inside = 1;
@@ -500,7 +505,7 @@ static int depth_near(const double *proj, int64_t N, uint32_t i0, uint32_t i1)
 static void composite_pixel(const double *proj, int64_t N, const uint32_t *list, int64_t n, int px, int py,
                             const double *bg, const uint8_t *fragile, int depth_check, const tol_t *tol,
                             amb_t *am, double out[3], double *Tout, uint32_t *last, uint32_t *ncontrib,
-                            int64_t *evaluated)
+                            int64_t *evaluated, double *bound)
 {
     double T = 1.0, C[3] = {0, 0, 0};
     uint32_t lastp = 0, nc = 0;
@@ -508,8 +513,14 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
     int64_t ev = 0;
     /* bound on the relative error of T in FP32: per blend the update's own
      * roundings, plus 1 - alpha's, which grows as alpha / (1 - alpha) times
-     * alpha's relative error */
-    double t_rel = 0.0;
+     * alpha's relative error (t_rel); the stop decision's margin grows the
+     * same way from alpha's margin (t_mrel) */
+    double t_rel = 0.0, t_mrel = 0.0;
+    /* first-order colour error from alpha's relative error: moving alpha_i
+     * by a fraction e changes the colour by at most e alpha_i T_i times the
+     * largest colour of the pixel (its own, or what lies behind it) */
+    double cmax = 0.0, werr = 0.0;
+    for (int ch = 0; ch < 3; ch++) cmax = fmax(cmax, fabs(bg[ch]));
     for (int64_t k = 0; k < n; k++) {
         /* two adjacent entries of the list that both reach this pixel and
          * whose FP32 depths nearly tie: the compared implementation (which
@@ -530,15 +541,21 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
             ev++;
             if (!e.inside) continue;
             double Tn = T * (1.0 - e.alpha);
-            double tr = t_rel + 2.4e-7 + e.alpha / (1.0 - e.alpha) * e.alpha_rel;
-            int amb = fabs(Tn - T_MIN) <= ((tol ? tol->t_tol : 1e-5) + tr) * T_MIN;
+            double tr = t_rel + 1.2e-7 + e.alpha / (1.0 - e.alpha) * e.alpha_rel;
+            double tm = t_mrel + 2.4e-7 + e.alpha / (1.0 - e.alpha) * e.alpha_mrel;
+            int amb = fabs(Tn - T_MIN) <= ((tol ? tol->t_tol : 1e-5) + tm) * T_MIN;
             if (decide(am, Tn < T_MIN, amb)) { stop = 1; break; }
             /* a near tie with a contributor that is not the adjacent entry */
             if (am && depth_check && prev >= 0 && (int64_t)lastp != pos && depth_near(proj, N, (uint32_t)prev, id))
                 am->unresolved = 1;
-            for (int ch = 0; ch < 3; ch++) C[ch] += proj[(7 + ch) * N + id] * e.alpha * T;
+            for (int ch = 0; ch < 3; ch++) {
+                C[ch] += proj[(7 + ch) * N + id] * e.alpha * T;
+                cmax = fmax(cmax, fabs(proj[(7 + ch) * N + id]));
+            }
+            werr += e.alpha * T * e.alpha_rel;
             T = Tn;
             t_rel = tr;
+            t_mrel = tm;
             lastp = (uint32_t)(pos + 1);
             nc++;
             prev = id;
@@ -551,6 +568,7 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
     *last = lastp;
     *ncontrib = nc;
     *evaluated = ev;
+    if (bound) *bound = fmax(cmax * (werr + T * t_rel), T * t_rel);
 }
 
 /* Tiled render of one view. proj: [ONF][N] of this view; ids/ranges: the
@@ -560,12 +578,15 @@ static void composite_pixel(const double *proj, int64_t N, const uint32_t *list,
  * 0 no decision within rounding of its threshold; 1 exactly one, and the
  * nullable alternative outputs (rgb_alt, T_alt, last_alt) hold the walk with
  * that decision taken the other way; 2 more than one, or a depth-order tie.
- * counts[0] = list entries evaluated, counts[1] = blended pairs (nominal walk). */
+ * counts[0] = list entries evaluated, counts[1] = blended pairs (nominal walk).
+ * bound (nullable): per pixel, a first-order bound of how far an FP32
+ * evaluation of the same walk may put its colour and T, from the relative
+ * error bound of each blended alpha (the larger of the two branches). */
 int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uint32_t *ids,
                   const uint32_t *ranges, const double *bg, const uint8_t *fragile, int32_t depth_check,
                   double pos_tol, double t_tol,
                   double *rgb, double *Tout, uint32_t *last, uint32_t *ncontrib, uint8_t *amb, int64_t *counts,
-                  double *rgb_alt, double *T_alt, uint32_t *last_alt)
+                  double *rgb_alt, double *T_alt, uint32_t *last_alt, double *bound)
 {
     tol_t tol = {pos_tol, t_tol};
     int64_t TX = tiles_of(W), TY = tiles_of(H);
@@ -580,8 +601,9 @@ int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uin
                 uint32_t l, nc;
                 int64_t ev;
                 amb_t am = {0, -1, 0};
+                double bd, bda = 0.0;
                 composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, &tol, &am, c, &T, &l,
-                                &nc, &ev);
+                                &nc, &ev, &bd);
                 int64_t p = (int64_t)py * W + px;
                 for (int ch = 0; ch < 3; ch++) rgb[(int64_t)ch * W * H + p] = c[ch];
                 Tout[p] = T;
@@ -599,7 +621,7 @@ int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uin
                     uint32_t nca;
                     int64_t eva;
                     composite_pixel(proj, N, ids + s, e - s, px, py, bg, fragile, depth_check, &tol, &alt, ca, &Ta,
-                                    &la, &nca, &eva);
+                                    &la, &nca, &eva, &bda);
                     if (alt.unresolved || alt.count > 1) cls = 2;
                 }
                 if (amb) amb[p] = cls;
@@ -607,6 +629,7 @@ int oracle_render(const double *proj, int64_t N, int32_t W, int32_t H, const uin
                     for (int ch = 0; ch < 3; ch++) rgb_alt[(int64_t)ch * W * H + p] = ca[ch];
                 if (T_alt) T_alt[p] = Ta;
                 if (last_alt) last_alt[p] = la;
+                if (bound) bound[p] = fmax(bd, bda);
             }
     }
     if (counts) { counts[0] = ev_total; counts[1] = nc_total; }
@@ -645,7 +668,7 @@ int oracle_render_brute(const double *proj, int64_t N, int32_t W, int32_t H, con
         double c[3], T;
         uint32_t l, nc;
         int64_t ev;
-        composite_pixel(proj, N, order, n, px, py, bg, NULL, 0, NULL, NULL, c, &T, &l, &nc, &ev);
+        composite_pixel(proj, N, order, n, px, py, bg, NULL, 0, NULL, NULL, c, &T, &l, &nc, &ev, NULL);
         for (int ch = 0; ch < 3; ch++) rgb[(int64_t)ch * W * H + p] = c[ch];
         Tout[p] = T;
         if (ncontrib) ncontrib[p] = nc;

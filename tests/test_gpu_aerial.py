@@ -147,7 +147,9 @@ def test_aerial_bins_and_images_of_sampled_views(aerial, v):
     err, compared, took_alt = oracle.image_mismatch(o, img, T, last)
     one = int((o["amb"] == 1).sum())
     excl = int((~compared).sum())
-    print(f"aerial view {v}: image max err {err:.2e}; one near-threshold decision {one} ({one / compared.size:.2e}, "
+    wide = int((o["bound"] > 1e-5).sum())
+    print(f"aerial view {v}: image max err {err:.2e} (beyond the FP32 bound where it exceeds 1e-5: {wide} px, "
+          f"largest {o['bound'].max():.1e}); one near-threshold decision {one} ({one / compared.size:.2e}, "
           f"{took_alt} matched its other branch), excluded {excl} ({excl / compared.size:.2e})", flush=True)
     assert err <= 1e-5
     assert excl <= 1e-4 * compared.size

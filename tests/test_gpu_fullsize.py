@@ -81,7 +81,9 @@ def test_fullsize_bins_and_images_of_sampled_views(batch):
         err, compared, took_alt = oracle.image_mismatch(o, img, T[sl1[v][0]:sl1[v][1]].reshape(H, W),
                                                         last[sl1[v][0]:sl1[v][1]].reshape(H, W))
         one = int((o["amb"] == 1).sum())
-        print(f"1080p view {v}: max err {err:.2e}; one near-threshold decision {one} ({one / compared.size:.2e}, "
+        wide = int((o["bound"] > 1e-5).sum())
+        print(f"1080p view {v}: max err {err:.2e} (FP32 bound above 1e-5 at {wide} px); "
+              f"one near-threshold decision {one} ({one / compared.size:.2e}, "
               f"{took_alt} matched its other branch), excluded {int((~compared).sum())}", flush=True)
         assert err <= 1e-5
         assert (~compared).sum() <= 1e-4 * compared.size, (~compared).sum()

@@ -193,7 +193,8 @@ size_t gs_loss_dssim_workspace_bytes(gs_dtype dtype, const gs_camera *cams_host,
  * params: [59][n]. cams_dev: [views] cameras in device memory (read by the
  * kernel, so a captured graph sees updated poses); cams_host: the same
  * cameras [host] (image sizes). Requires 1 <= views <= GS_MAX_VIEWS,
- * views * n < 2^32. */
+ * views * n < 2^32 and one view's records under 4 GiB (n < 89M in FP32,
+ * 44M in FP64); GS_ERR_ARG otherwise. */
 gs_status gs_project(gs_dtype dtype, const void *params, int64_t n, const gs_camera *cams_dev,
                      const gs_camera *cams_host, int32_t views, void *projected, void *stream);
 

@@ -1,9 +1,11 @@
 """Autotuner for the render kernels' launch shape.
 
-For a trainer's workload it times every (scheduler mode, pixels per thread,
-LDS chunk) of the forward and of the backward render with HIP events on the
-real buffers, picks the fastest of each, and caches the choice in a JSON file
-keyed by (architecture, resolution class, Gaussian-count bucket).
+For a trainer's workload it times every launch shape (pixels per thread, LDS
+chunk) of the forward and of the backward render on the per-tile launch with
+HIP events on the real buffers, then the three scheduler modes at the best
+shape in interleaved rounds (a cost-driven mode is taken only when it beats
+per-tile by 1%), and caches the choice in a JSON file keyed by (architecture,
+resolution class, view count, Gaussian-count bucket).
 """
 from __future__ import annotations
 
@@ -61,8 +63,11 @@ def _time(fn, reps: int) -> float:
     return s.elapsed_time(e) / reps
 
 
-def tune(tr, reps: int = 3, use_cache: bool = True, verbose: bool = False) -> dict:
-    """Picks (mode, px, chunk) for forward and backward of a BatchedTrainer."""
+def tune(tr, reps: int = 3, use_cache: bool = True, verbose: bool = False, mode_rounds: int = 6) -> dict:
+    """Picks (mode, px, chunk) for forward and backward of a BatchedTrainer:
+    the launch shape (pixels per thread, LDS chunk) on the per-tile launch,
+    then the scheduler mode at that shape, the modes timed in interleaved
+    rounds so that drift between launches does not favour one."""
     key = workload_key(tr.cams, tr.n)
     cache = _load() if use_cache else {}
     if key in cache:
@@ -71,25 +76,42 @@ def tune(tr, reps: int = 3, use_cache: bool = True, verbose: bool = False) -> di
         tr.warmup()          # every kernel once with the Adam update skipped: the training state is unchanged
         torch.cuda.synchronize()
         R.gs_loss_l1(tr.rgb, tr.targets, tr.cams, tr.loss_buf)
+
+        def fwd(sf):
+            return lambda: R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, tr.cfg.bg, sf, tr.rgb, tr.T, tr.last,
+                                           tr.work_fwd, tr.work_bwd)
+
+        def bwd(sb):
+            return lambda: R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last, tr.loss_buf.dL,
+                                                  tr.dproj, tr.cfg.bg, sb)
+
+        def sched(mode, px, ch, cost):
+            return R.Sched(tr.cams, mode, px, ch, tr.cfg.workers, tr.cfg.queues, tile_cost=cost)
         results = {"fwd": [], "bwd": []}
-        for mode in MODES:
-            for px in PX:
-                for ch in CHUNKS:
-                    sf = R.Sched(tr.cams, mode, px, ch, tr.cfg.workers, tr.cfg.queues, tile_cost=tr.work_fwd)
-                    sb = R.Sched(tr.cams, mode, px, ch, tr.cfg.workers, tr.cfg.queues, tile_cost=tr.work_bwd)
-                    tf = _time(lambda: R.gs_render_fwd(tr.proj, tr.n, tr.bins, tr.cams, tr.cfg.bg, sf, tr.rgb, tr.T,
-                                                       tr.last, tr.work_fwd, tr.work_bwd), reps)
-                    tb = _time(lambda: R.gs_render_bwd_pixels(tr.proj, tr.n, tr.bins, tr.cams, tr.T, tr.last,
-                                                              tr.loss_buf.dL, tr.dproj, tr.cfg.bg, sb), reps)
-                    results["fwd"].append((tf, mode, px, ch))
-                    results["bwd"].append((tb, mode, px, ch))
-                    if verbose:
-                        print(f"autotune mode={mode} px={px} chunk={ch}: fwd {tf:.3f} ms bwd {tb:.3f} ms", flush=True)
+        for px in PX:
+            for ch in CHUNKS:
+                tf = _time(fwd(sched(_lib.GS_SCHED_PER_TILE, px, ch, tr.work_fwd)), reps)
+                tb = _time(bwd(sched(_lib.GS_SCHED_PER_TILE, px, ch, tr.work_bwd)), reps)
+                results["fwd"].append((tf, _lib.GS_SCHED_PER_TILE, px, ch))
+                results["bwd"].append((tb, _lib.GS_SCHED_PER_TILE, px, ch))
+                if verbose:
+                    print(f"autotune px={px} chunk={ch}: fwd {tf:.3f} ms bwd {tb:.3f} ms", flush=True)
+        best = {}
+        for p, mk, cost in (("fwd", fwd, tr.work_fwd), ("bwd", bwd, tr.work_bwd)):
+            _, _, px, ch = min(results[p])
+            fns = {m: mk(sched(m, px, ch, cost)) for m in MODES}
+            acc = {m: 0.0 for m in MODES}
+            for m in MODES:
+                fns[m]()
+            for _ in range(mode_rounds):
+                for m in MODES:
+                    acc[m] += _time(fns[m], 1) / mode_rounds
+            rows = [(acc[m], m, px, ch) for m in MODES]
+            results[p + "_modes"] = rows
+            b = _pick(rows)
+            best[p] = {"mode": b[1], "px": b[2], "chunk": b[3], "ms": b[0]}
         tr.dproj.zero_()
-        bf, bb = _pick(results["fwd"]), _pick(results["bwd"])
-        best = {"fwd": {"mode": bf[1], "px": bf[2], "chunk": bf[3], "ms": bf[0]},
-                "bwd": {"mode": bb[1], "px": bb[2], "chunk": bb[3], "ms": bb[0]},
-                "table": results}
+        best["table"] = results
         if use_cache:
             cache[key] = best
             _save(cache)
@@ -97,13 +119,12 @@ def tune(tr, reps: int = 3, use_cache: bool = True, verbose: bool = False) -> di
     return best
 
 
-MARGIN = 0.03   # a cost-driven mode must beat the best per-tile shape by this fraction
+MARGIN = 0.01   # a cost-driven mode must beat the per-tile launch of the same shape by this fraction
 
 
 def _pick(rows):
     """Fastest (ms, mode, px, chunk); a scheduler mode other than per-tile
-    only when it beats the best per-tile shape by MARGIN (timings of a few
-    back-to-back launches move by about that much, and the per-tile launch
+    only when it beats the per-tile launch by MARGIN (the per-tile launch
     needs no plan)."""
     best = min(rows)
     tile = min(r for r in rows if r[1] == _lib.GS_SCHED_PER_TILE)

@@ -264,6 +264,8 @@ gs_status gs_project(gs_dtype dtype, const void *params, int64_t n, const gs_cam
     CHECK_ARG(dtype_ok(dtype), "bad dtype");
     CHECK_ARG(cams_ok(cams_host, views, why), why);
     CHECK_ARG(n >= 0 && (uint64_t)n * (uint64_t)views < (uint64_t(1) << 32), "n * views must be < 2^32");
+    CHECK_ARG((uint64_t)n * GS_REC * (dtype == GS_F32 ? 4u : 8u) < (uint64_t(1) << 32),
+              "one view's records must be < 4 GiB (n < 89M in FP32, 44M in FP64)");
     CHECK_ARG(n == 0 || (params && cams_dev && projected), "null pointer");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = dtype == GS_F32 ? launch_project_fwd<float>(params, n, cams_dev, views, projected, s)

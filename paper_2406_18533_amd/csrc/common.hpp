@@ -170,6 +170,9 @@ __device__ __forceinline__ bool eval_alpha(const ColTerms<T> &c, T pyc, T v, T r
 
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+// 1 / sqrt(x): the hardware estimate in FP32 (about 1 ulp), exact rounding in FP64
+__device__ __forceinline__ float rsq_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_t(double x) { return 1.0 / sqrt(x); }
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };

@@ -62,23 +62,32 @@ template <typename T> __device__ __forceinline__ void quat_matrix(const T q[4], 
 template <typename T> __device__ __forceinline__ bool finite(T x) { return isfinite(x); }
 
 template <typename T>
+__device__ __forceinline__ void shape_from(const T ls[3], const T qr[4], T logit, Shape<T> &S)
+{
+    S.ok = finite(ls[0]) && finite(ls[1]) && finite(ls[2]) && finite(qr[0]) && finite(qr[1]) && finite(qr[2]) &&
+           finite(qr[3]) && finite(logit);
+    for (int j = 0; j < 3; j++) S.s[j] = exp(ls[j]);
+    // reciprocals and the normalisation by the hardware estimates (about
+    // 1 ulp in FP32; the quotients are not correctly rounded anywhere in the
+    // method's tolerances)
+    T q2 = qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3];
+    S.ok = S.ok && q2 > T(0);
+    T iq = rsq_t(q2);
+    S.qn = q2 * iq;
+    for (int j = 0; j < 4; j++) S.q[j] = qr[j] * iq;
+    quat_matrix(S.q, S.Rq);
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) S.M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
+    S.opac = rcp_t(T(1) + exp(-logit));
+}
+
+template <typename T>
 __device__ __forceinline__ void make_shape(const T *P, int64_t n, int64_t i, Shape<T> &S)
 {
     T ls[3], qr[4];
     for (int j = 0; j < 3; j++) ls[j] = P[(3 + j) * n + i];
     for (int j = 0; j < 4; j++) qr[j] = P[(6 + j) * n + i];
-    T logit = P[10 * n + i];
-    S.ok = finite(ls[0]) && finite(ls[1]) && finite(ls[2]) && finite(qr[0]) && finite(qr[1]) && finite(qr[2]) &&
-           finite(qr[3]) && finite(logit);
-    for (int j = 0; j < 3; j++) S.s[j] = exp(ls[j]);
-    S.qn = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
-    S.ok = S.ok && S.qn > T(0);
-    T iq = T(1) / S.qn;
-    for (int j = 0; j < 4; j++) S.q[j] = qr[j] * iq;
-    quat_matrix(S.q, S.Rq);
-    for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) S.M[3 * r + c] = S.Rq[3 * r + c] * S.s[c];
-    S.opac = T(1) / (T(1) + exp(-logit));
+    shape_from(ls, qr, P[10 * n + i], S);
 }
 
 // Per-view geometry of one Gaussian.
@@ -100,13 +109,16 @@ __device__ __forceinline__ void make_geo(const T x[3], const Shape<T> &S, const 
 {
     g.visible = false;
     g.tiles = 0;
-    for (int r = 0; r < 3; r++) g.y[r] = k.R[3 * r] * x[0] + k.R[3 * r + 1] * x[1] + k.R[3 * r + 2] * x[2] + k.t[r];
+    // (explicit fused multiply-adds: every kernel that calls this gets the
+    // same roundings, whatever the compiler would contract)
+    for (int r = 0; r < 3; r++)
+        g.y[r] = fma(k.R[3 * r], x[0], fma(k.R[3 * r + 1], x[1], fma(k.R[3 * r + 2], x[2], k.t[r])));
     T z = g.y[2];
     if (!S.ok || !(z > k.znear)) return;
-    g.iz = T(1) / z;
-    g.u = k.fx * g.y[0] * g.iz + k.cx;
-    g.v = k.fy * g.y[1] * g.iz + k.cy;
+    g.iz = rcp_t(z);
     T xr = g.y[0] * g.iz, yr = g.y[1] * g.iz;
+    g.u = fma(k.fx, xr, k.cx);
+    g.v = fma(k.fy, yr, k.cy);
     g.xi_cl = xr < -k.limx || xr > k.limx;
     g.eta_cl = yr < -k.limy || yr > k.limy;
     g.xi = fmin(fmax(xr, -k.limx), k.limx);
@@ -116,8 +128,8 @@ __device__ __forceinline__ void make_geo(const T x[3], const Shape<T> &S, const 
     g.J11 = k.fy * g.iz;
     g.J12 = -k.fy * g.eta * g.iz;
     for (int c = 0; c < 3; c++) {
-        g.Tm[c] = g.J00 * k.R[c] + g.J02 * k.R[6 + c];
-        g.Tm[3 + c] = g.J11 * k.R[3 + c] + g.J12 * k.R[6 + c];
+        g.Tm[c] = fma(g.J00, k.R[c], g.J02 * k.R[6 + c]);
+        g.Tm[3 + c] = fma(g.J11, k.R[3 + c], g.J12 * k.R[6 + c]);
     }
     // Screen covariance N N^T + 0.3 I with N = Tm M (2x3). Its entries and
     // determinant are formed as sums of squares (Lagrange identity
@@ -125,24 +137,25 @@ __device__ __forceinline__ void make_geo(const T x[3], const Shape<T> &S, const 
     // their FP32 accuracy.
     for (int r = 0; r < 2; r++)
         for (int c = 0; c < 3; c++)
-            g.N[3 * r + c] = g.Tm[3 * r] * S.M[c] + g.Tm[3 * r + 1] * S.M[3 + c] + g.Tm[3 * r + 2] * S.M[6 + c];
+            g.N[3 * r + c] = fma(g.Tm[3 * r], S.M[c], fma(g.Tm[3 * r + 1], S.M[3 + c], g.Tm[3 * r + 2] * S.M[6 + c]));
     const T *n0 = g.N, *n1 = g.N + 3;
-    T a0 = n0[0] * n0[0] + n0[1] * n0[1] + n0[2] * n0[2];
-    T c0 = n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2];
-    T b0 = n0[0] * n1[0] + n0[1] * n1[1] + n0[2] * n1[2];
-    T x0 = n0[1] * n1[2] - n0[2] * n1[1], x1 = n0[2] * n1[0] - n0[0] * n1[2], x2 = n0[0] * n1[1] - n0[1] * n1[0];
+    T a0 = fma(n0[0], n0[0], fma(n0[1], n0[1], n0[2] * n0[2]));
+    T c0 = fma(n1[0], n1[0], fma(n1[1], n1[1], n1[2] * n1[2]));
+    T b0 = fma(n0[0], n1[0], fma(n0[1], n1[1], n0[2] * n1[2]));
+    T x0 = fma(n0[1], n1[2], -(n0[2] * n1[1])), x1 = fma(n0[2], n1[0], -(n0[0] * n1[2]));
+    T x2 = fma(n0[0], n1[1], -(n0[1] * n1[0]));
     g.A = a0 + T(0.3);
     g.B = b0;
     g.C = c0 + T(0.3);
-    g.det = (x0 * x0 + x1 * x1 + x2 * x2) + T(0.3) * (a0 + c0) + T(0.09);
+    g.det = fma(x0, x0, fma(x1, x1, x2 * x2)) + fma(T(0.3), a0 + c0, T(0.09));
     if (!(g.det > T(0)) || !finite(g.det)) return;
-    T id = T(1) / g.det;
+    T id = rcp_t(g.det);
     g.conic[0] = g.C * id;
     g.conic[1] = -g.B * id;
     g.conic[2] = g.A * id;
     T mid = T(0.5) * (g.A + g.C);
     T hd = T(0.5) * (g.A - g.C);
-    T lmax = mid + sqrt(hd * hd + g.B * g.B);
+    T lmax = mid + sqrt(fma(hd, hd, g.B * g.B));
     g.radius = ceil(T(3) * sqrt(lmax));
     if (!finite(g.radius) || !finite(g.u) || !finite(g.v)) return;
     g.visible = true;
@@ -214,42 +227,83 @@ template <typename T> using V4 = typename Vec4<T>::type;
 // limit). Only pairs that touch a tile write a record and the depth /
 // rectangle side arrays; every pair writes its tiles touched (0 when culled
 // or off-screen).
+// Element at a 32-bit byte offset from a wave-uniform base: the base
+// pointer (row or view start) stays in scalar registers and the per-lane
+// offset is one 32-bit register, so a load or store needs no per-lane
+// 64-bit address arithmetic.
+// (The base goes through readfirstlane so that the compiler keeps it
+// scalar instead of folding the row offset into the per-lane address, and
+// the access is made in the global address space.)
+#define GS_GLOBAL __attribute__((address_space(1)))
+template <typename U> __device__ __forceinline__ uint64_t uniform_addr(const U *p)
+{
+    uint64_t a = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename U> __device__ __forceinline__ U load_at(const U *base, uint32_t boff)
+{
+    return *(const GS_GLOBAL U *)((const GS_GLOBAL char *)uniform_addr(base) + boff);
+}
+template <typename U> __device__ __forceinline__ void store_at(U *base, uint32_t boff, U v)
+{
+    *(GS_GLOBAL U *)((GS_GLOBAL char *)uniform_addr(base) + boff) = v;
+}
+// four values in one aligned store (a builtin vector type: the HIP vector
+// classes' assignment operators take no address-space-qualified object)
+template <typename T> __device__ __forceinline__ void store4_at(T *base, uint32_t boff, T x, T y, T z, T w)
+{
+    typedef T quad __attribute__((ext_vector_type(4)));
+    store_at(reinterpret_cast<quad *>(base), boff, quad{x, y, z, w});
+}
+
+// One (view, Gaussian) pair. ib = i * sizeof(T) is the lane's byte offset in
+// a parameter row (n * sizeof(T) < 4 GiB); view_out and the side arrays of
+// the view are wave-uniform bases, indexed by the Gaussian (n * 48 B < 4 GiB).
 template <typename T>
 __device__ __forceinline__ void project_item(const T *__restrict__ P, int64_t n, const Camera<T> &k, int64_t vn,
-                                             int64_t o, int64_t i, T *__restrict__ out)
+                                             int64_t vbase, uint32_t i, T *__restrict__ out)
 {
-    T x[3] = {P[i], P[n + i], P[2 * n + i]};
+    const uint32_t ib = i * (uint32_t)sizeof(T);
+    auto row = [&](int r) { return load_at(P + r * n, ib); };
+    // the position and the shape rows in one round of loads (nearly every
+    // pair is in front of the camera; the colour rows wait for the footprint)
+    T x[3] = {row(0), row(1), row(2)};
+    T ls[3] = {row(3), row(4), row(5)};
+    T qr[4] = {row(6), row(7), row(8), row(9)};
+    T logit = row(10);
     bool xok = finite(x[0]) && finite(x[1]) && finite(x[2]);
     T z = k.R[6] * x[0] + k.R[7] * x[1] + k.R[8] * x[2] + k.t[2];
     uint32_t tiles = 0;
     if (xok && z > k.znear) {
         Shape<T> S;
-        make_shape(P, n, i, S);
+        shape_from(ls, qr, logit, S);
         Geo<T> g;
         make_geo(x, S, k, g);
         if (g.visible && g.tiles > 0) {
             tiles = (uint32_t)g.tiles;
             T d[3] = {x[0] - k.cen[0], x[1] - k.cen[1], x[2] - k.cen[2]};
-            T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            T idn = rsq_t(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             T Y[16];
             sh_basis(d[0] * idn, d[1] * idn, d[2] * idn, Y);
             T acc[3] = {T(0), T(0), T(0)};
             for (int k2 = 0; k2 < 16; k2++)
-                for (int ch = 0; ch < 3; ch++) acc[ch] += P[(11 + 3 * k2 + ch) * n + i] * Y[k2];
+                for (int ch = 0; ch < 3; ch++) acc[ch] = fma(row(11 + 3 * k2 + ch), Y[k2], acc[ch]);
             T rgb[3];
             for (int ch = 0; ch < 3; ch++) {
                 T a = acc[ch] + T(0.5);
                 rgb[ch] = a > T(0) ? a : T(0);
             }
-            V4<T> *rec = reinterpret_cast<V4<T> *>(out + o * REC);
-            rec[0] = V4<T>{g.u, g.v, g.conic[0], g.conic[1]};
-            rec[1] = V4<T>{g.conic[2], S.opac, rgb[0], rgb[1]};
-            rec[2] = V4<T>{rgb[2], g.radius, g.y[2], (T)g.tiles};
-            side_depth<T>(out, vn)[o] = __float_as_uint((float)g.y[2]);
-            side_rect<T>(out, vn)[o] = pack_rect(g.rect.x0, g.rect.x1, g.rect.y0, g.rect.y1);
+            T *rec = out + vbase * REC;
+            const uint32_t rb = i * (uint32_t)(REC * sizeof(T));
+            store4_at(rec, rb, g.u, g.v, g.conic[0], g.conic[1]);
+            store4_at(rec + 4, rb, g.conic[2], S.opac, rgb[0], rgb[1]);
+            store4_at(rec + 8, rb, rgb[2], g.radius, g.y[2], (T)g.tiles);
+            store_at(side_depth<T>(out, vn) + vbase, 4 * i, __float_as_uint((float)g.y[2]));
+            store_at(side_rect<T>(out, vn) + vbase, 8 * i, pack_rect(g.rect.x0, g.rect.x1, g.rect.y0, g.rect.y1));
         }
     }
-    side_tiles<T>(out, vn)[o] = tiles;
+    store_at(side_tiles<T>(out, vn) + vbase, 4 * i, tiles);
 }
 
 template <typename T>
@@ -263,9 +317,10 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(const T *__restrict__ 
     const int64_t kk = s / views;
     const int v = (int)(s - kk * views);
     const int64_t i = (kk * 8 + x) * 64 + (threadIdx.x & 63);
+    __shared__ Camera<T> cs[MAXV];
+    stage_cameras(cs, cams, views);                // once per workgroup, not per item
     if (i >= n) return;
-    const Camera<T> k = load_camera<T>(cams + v);
-    project_item(P, n, k, (int64_t)views * n, (int64_t)v * n + i, i, out);
+    project_item(P, n, cs[v], (int64_t)views * n, (int64_t)v * n, (uint32_t)i, out);
 }
 
 // Transformation backward: chain rule from the per-view record gradients
@@ -447,13 +502,13 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
             T drgb[3] = {dr[D_RGB], dr[D_RGB + 1], dr[D_RGB + 2]};
             const T *cen = cs[v].cen;
             T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
-            T idn = T(1) / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            T idn = rsq_t(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);   // as the forward, so the clamp agrees
             T dir[3] = {d[0] * idn, d[1] * idn, d[2] * idn};
             T Y[16];
             sh_basis(dir[0], dir[1], dir[2], Y);
             T raw[3] = {T(0), T(0), T(0)};   // each summed in the forward's order, so the clamp mask agrees
             for (int k2 = 0; k2 < 16; k2++)
-                for (int c = 0; c < 3; c++) raw[c] += sh[c][k2] * Y[k2];
+                for (int c = 0; c < 3; c++) raw[c] = fma(sh[c][k2], Y[k2], raw[c]);
             T a[3];                          // dL/drgb of the unclamped channels, 0 for clamped ones
             for (int c = 0; c < 3; c++) a[c] = raw[c] + T(0.5) > T(0) ? drgb[c] : T(0);
             if (!(raw[0] + T(0.5) > T(0)) && !(raw[1] + T(0.5) > T(0)) && !(raw[2] + T(0.5) > T(0))) continue;

@@ -274,6 +274,40 @@ __device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *d
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// ------------------------------------------------------------------ addressing
+// Element at a 32-bit byte offset from a wave-uniform base: the base pointer
+// (a row or a view's start) stays in scalar registers and the per-lane offset
+// is one 32-bit register, so a load or store needs no per-lane 64-bit address
+// arithmetic. The base goes through readfirstlane so that the compiler keeps
+// it scalar instead of folding a row offset into the per-lane address, and
+// the access is made in the global address space.
+#define GS_GLOBAL __attribute__((address_space(1)))
+template <typename U> __device__ __forceinline__ uint64_t uniform_addr(const U *p)
+{
+    uint64_t a = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename U> __device__ __forceinline__ U load_at(const U *base, uint32_t boff)
+{
+    return *(const GS_GLOBAL U *)((const GS_GLOBAL char *)uniform_addr(base) + boff);
+}
+template <typename U> __device__ __forceinline__ void store_at(U *base, uint32_t boff, U v)
+{
+    *(GS_GLOBAL U *)((GS_GLOBAL char *)uniform_addr(base) + boff) = v;
+}
+// four values in one aligned access (a builtin vector type: the HIP vector
+// classes' operators take no address-space-qualified object)
+template <typename T> using quad_t = T __attribute__((ext_vector_type(4)));
+template <typename T> __device__ __forceinline__ void store4_at(T *base, uint32_t boff, T x, T y, T z, T w)
+{
+    store_at(reinterpret_cast<quad_t<T> *>(base), boff, quad_t<T>{x, y, z, w});
+}
+template <typename T> __device__ __forceinline__ quad_t<T> load4_at(const T *base, uint32_t boff)
+{
+    return load_at(reinterpret_cast<const quad_t<T> *>(base), boff);
+}
+
 // ------------------------------------------------------------------ Adam
 // Hyper-parameters of one Adam step after the batch scaling rules of paper
 // section 4: lr already times sqrt(batch), betas already to the power batch.
@@ -291,15 +325,25 @@ __host__ __device__ __forceinline__ int row_group(int row)
     return row < 3 ? 0 : row < 6 ? 1 : row < 10 ? 2 : row < 11 ? 3 : row < 14 ? 4 : 5;
 }
 
-// One Adam update (torch.optim.Adam semantics) with step = lr / (1 - b1^t)
-// and bc2s = sqrt(1 - b2^t).
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+
+// Step size lr / (1 - b1^t) and 1 / sqrt(1 - b2^t) of the current step, in
+// the kernels' precision; every Adam kernel forms them this way so fused and
+// separate updates agree bit for bit.
+template <typename T> __device__ __forceinline__ T adam_step_size(double lr, double bc1) { return (T)lr * rcp_t((T)bc1); }
+template <typename T> __device__ __forceinline__ T adam_inv_bc2s(double bc2s) { return rcp_t((T)bc2s); }
+
+// One Adam update (torch.optim.Adam semantics: m and v, then
+// p -= step m / (sqrt(v) / sqrt(1 - b2^t) + eps)); in FP32 the square root
+// and the quotients use the hardware estimates (about 1 ulp each).
 template <typename T>
-__device__ __forceinline__ void adam_one(T &p, T g, T &m, T &v, T b1, T b2, T step, T bc2s, T eps)
+__device__ __forceinline__ void adam_one(T &p, T g, T &m, T &v, T b1, T b2, T step, T inv_bc2s, T eps)
 {
     m = b1 * m + (T(1) - b1) * g;
     v = b2 * v + (T(1) - b2) * g * g;
-    T denom = sqrt(v) / bc2s + eps;
-    p = p - step * (m / denom);
+    T denom = sqrt_t(v) * inv_bc2s + eps;
+    p = p - step * (m * rcp_t(denom));
 }
 
 // Moments, constants and the bias corrections of the current step (written
@@ -314,8 +358,9 @@ template <typename T> struct AdamRef {
 // Adam on CNT consecutive rows row0 .. row0 + CNT - 1 of Gaussian i with
 // gradients g[r]: all loads are issued before any update, so the memory
 // latency of the rows overlaps.
+// ib = i * sizeof(T), the lane's byte offset in a row (n * sizeof(T) < 4 GiB).
 template <typename T, int CNT>
-__device__ __forceinline__ void adam_row_block(T *__restrict__ P, const AdamRef<T> &a, int row0, int64_t n, int64_t i,
+__device__ __forceinline__ void adam_row_block(T *__restrict__ P, const AdamRef<T> &a, int row0, int64_t n, uint32_t ib,
                                                const T *g)
 {
     double bc1 = a.scratch[0];
@@ -325,23 +370,23 @@ __device__ __forceinline__ void adam_row_block(T *__restrict__ P, const AdamRef<
     T p[CNT], m[CNT], v[CNT];
 #pragma unroll
     for (int r = 0; r < CNT; r++) {
-        int64_t k = (int64_t)(row0 + r) * n + i;
-        p[r] = P[k];
-        m[r] = M[k];
-        v[r] = V[k];
+        int64_t k = (int64_t)(row0 + r) * n;
+        p[r] = load_at(P + k, ib);
+        m[r] = load_at(M + k, ib);
+        v[r] = load_at(V + k, ib);
     }
-    T b1 = (T)a.c.b1, b2 = (T)a.c.b2, eps = (T)a.c.eps, bc2s = (T)a.scratch[1];
+    T b1 = (T)a.c.b1, b2 = (T)a.c.b2, eps = (T)a.c.eps, ibc2s = adam_inv_bc2s<T>(a.scratch[1]);
 #pragma unroll
     for (int r = 0; r < CNT; r++) {
-        T step = (T)a.c.lr[row_group(row0 + r)] / (T)bc1;
-        adam_one(p[r], g[r], m[r], v[r], b1, b2, step, bc2s, eps);
+        T step = adam_step_size<T>(a.c.lr[row_group(row0 + r)], bc1);
+        adam_one(p[r], g[r], m[r], v[r], b1, b2, step, ibc2s, eps);
     }
 #pragma unroll
     for (int r = 0; r < CNT; r++) {
-        int64_t k = (int64_t)(row0 + r) * n + i;
-        P[k] = p[r];
-        M[k] = m[r];
-        V[k] = v[r];
+        int64_t k = (int64_t)(row0 + r) * n;
+        store_at(P + k, ib, p[r]);
+        store_at(M + k, ib, m[r]);
+        store_at(V + k, ib, v[r]);
     }
 }
 

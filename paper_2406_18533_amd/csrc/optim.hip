@@ -52,10 +52,9 @@ __global__ void __launch_bounds__(256) adam_kernel(T *__restrict__ P, T *__restr
                 Gr[(int64_t)row * n + j] = T(0);
         return;
     }
-    T lr = (T)c.lr[row_group(row)];
     T b1 = (T)c.b1, b2 = (T)c.b2, eps = (T)c.eps;
-    T step = lr / (T)bc1;
-    T bc2s = (T)scratch[1];
+    T step = adam_step_size<T>(c.lr[row_group(row)], bc1);
+    T bc2s = adam_inv_bc2s<T>(scratch[1]);
     int64_t off = (int64_t)row * n;
     if (VEC) {
         using V = typename Vec4<T>::type;

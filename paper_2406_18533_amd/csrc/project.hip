@@ -84,10 +84,11 @@ __device__ __forceinline__ void shape_from(const T ls[3], const T qr[4], T logit
 template <typename T>
 __device__ __forceinline__ void make_shape(const T *P, int64_t n, int64_t i, Shape<T> &S)
 {
+    const uint32_t ib = (uint32_t)i * (uint32_t)sizeof(T);
     T ls[3], qr[4];
-    for (int j = 0; j < 3; j++) ls[j] = P[(3 + j) * n + i];
-    for (int j = 0; j < 4; j++) qr[j] = P[(6 + j) * n + i];
-    shape_from(ls, qr, P[10 * n + i], S);
+    for (int j = 0; j < 3; j++) ls[j] = load_at(P + (3 + j) * n, ib);
+    for (int j = 0; j < 4; j++) qr[j] = load_at(P + (6 + j) * n, ib);
+    shape_from(ls, qr, load_at(P + 10 * n, ib), S);
 }
 
 // Per-view geometry of one Gaussian.
@@ -227,36 +228,6 @@ template <typename T> using V4 = typename Vec4<T>::type;
 // limit). Only pairs that touch a tile write a record and the depth /
 // rectangle side arrays; every pair writes its tiles touched (0 when culled
 // or off-screen).
-// Element at a 32-bit byte offset from a wave-uniform base: the base
-// pointer (row or view start) stays in scalar registers and the per-lane
-// offset is one 32-bit register, so a load or store needs no per-lane
-// 64-bit address arithmetic.
-// (The base goes through readfirstlane so that the compiler keeps it
-// scalar instead of folding the row offset into the per-lane address, and
-// the access is made in the global address space.)
-#define GS_GLOBAL __attribute__((address_space(1)))
-template <typename U> __device__ __forceinline__ uint64_t uniform_addr(const U *p)
-{
-    uint64_t a = reinterpret_cast<uint64_t>(p);
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-template <typename U> __device__ __forceinline__ U load_at(const U *base, uint32_t boff)
-{
-    return *(const GS_GLOBAL U *)((const GS_GLOBAL char *)uniform_addr(base) + boff);
-}
-template <typename U> __device__ __forceinline__ void store_at(U *base, uint32_t boff, U v)
-{
-    *(GS_GLOBAL U *)((GS_GLOBAL char *)uniform_addr(base) + boff) = v;
-}
-// four values in one aligned store (a builtin vector type: the HIP vector
-// classes' assignment operators take no address-space-qualified object)
-template <typename T> __device__ __forceinline__ void store4_at(T *base, uint32_t boff, T x, T y, T z, T w)
-{
-    typedef T quad __attribute__((ext_vector_type(4)));
-    store_at(reinterpret_cast<quad *>(base), boff, quad{x, y, z, w});
-}
-
 // One (view, Gaussian) pair. ib = i * sizeof(T) is the lane's byte offset in
 // a parameter row (n * sizeof(T) < 4 GiB); view_out and the side arrays of
 // the view are wave-uniform bases, indexed by the Gaussian (n * 48 B < 4 GiB).
@@ -359,8 +330,9 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
     T gmean[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = T(0);
     for (int v = 0; v < views; v++) {
         if (!((vis >> v) & 1ull)) continue;
-        const V4<T> *dr = reinterpret_cast<const V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
-        V4<T> d0 = dr[0], d1 = dr[1];
+        const T *dr = dproj + (int64_t)v * n * REC;
+        const uint32_t rb = (uint32_t)i * (uint32_t)(REC * sizeof(T));
+        quad_t<T> d0 = load4_at(dr, rb), d1 = load4_at(dr + 4, rb);
         T du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x, dop = d1.y;
         const Camera<T> &k = cs[v];
         Geo<T> g;
@@ -384,7 +356,7 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
         T ex = T(1), ey = T(0);
         if (rr > T(0)) {
             T px = hd >= T(0) ? hd + rr : g.B, py = hd >= T(0) ? g.B : rr - hd;
-            T inv = T(1) / sqrt(px * px + py * py);
+            T inv = rsq_t(px * px + py * py);
             ex = px * inv;
             ey = py * inv;
         }
@@ -392,7 +364,7 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
         T g11 = ex * (da * ex + hdb * ey) + ey * (hdb * ex + dc * ey);
         T g22 = ey * (da * ey - hdb * ex) - ex * (hdb * ey - dc * ex);
         T g12 = ex * (hdb * ex - da * ey) + ey * (dc * ex - hdb * ey);
-        T il1 = T(1) / l1, il2 = T(1) / l2;
+        T il1 = rcp_t(l1), il2 = rcp_t(l2);
         T h11 = -g11 * il1 * il1, h22 = -g22 * il2 * il2, h12 = -g12 * il1 * il2;
         T dN[6];
         for (int c = 0; c < 3; c++) {
@@ -441,7 +413,7 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
     dq[3] = T(2) * (-T(2) * qz * dRq[0] - w * dRq[1] + qx * dRq[2] + w * dRq[3] - T(2) * qz * dRq[4] +
                     qy * dRq[5] + qx * dRq[6] + qy * dRq[7]);
     T dot = dq[0] * S.q[0] + dq[1] * S.q[1] + dq[2] * S.q[2] + dq[3] * S.q[3];
-    T iqn = T(1) / S.qn;
+    T iqn = rcp_t(S.qn);
     for (int c = 0; c < 3; c++) {
         gpos[c] = gmean[c];
         g8[c] = gls[c];
@@ -460,10 +432,11 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
     stage_cameras(cs, cams, views);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const uint32_t ib = (uint32_t)i * (uint32_t)sizeof(T);          // lane offset in a parameter row
     uint64_t vis = 0;
     const uint32_t *tiles = side_tiles<T>(proj, (int64_t)views * n);
     for (int v = 0; v < views; v++)
-        if (tiles[(int64_t)v * n + i] > 0u) vis |= 1ull << v;
+        if (load_at(tiles + (int64_t)v * n, 4u * (uint32_t)i) > 0u) vis |= 1ull << v;
     // Gaussians seen by no view have nothing to add and, with ADAM, take the
     // step with a zero gradient. Seen and unseen Gaussians share wavefronts
     // (visibility is scattered over the index range), so the gradients are
@@ -472,19 +445,19 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
     if (!ADAM && !seen) return;
     T x[3] = {T(0), T(0), T(0)};
     if (seen) {
-        x[0] = P[i];
-        x[1] = P[n + i];
-        x[2] = P[2 * n + i];
+        x[0] = load_at(P, ib);
+        x[1] = load_at(P + n, ib);
+        x[2] = load_at(P + 2 * n, ib);
     }
     T gpos[3] = {T(0), T(0), T(0)};
     {
         T g8[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
         if (seen) geom_grads(P, n, i, x, cs, views, vis, dproj, gpos, g8);
         if (!ADAM) {
-            for (int r = 0; r < 8; r++) grad[(3 + r) * n + i] += g8[r];
+            for (int r = 0; r < 8; r++) store_at(grad + (3 + r) * n, ib, load_at(grad + (3 + r) * n, ib) + g8[r]);
         } else {
             for (int r = 0; r < 8; r++) g8[r] = T(0) + g8[r];   // as += into a zero gradient
-            adam_row_block<T, 8>(P, ad, 3, n, i, g8);           // rows 3-10
+            adam_row_block<T, 8>(P, ad, 3, n, ib, g8);          // rows 3-10
         }
     }
     asm volatile("" ::: "memory");
@@ -495,11 +468,12 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
     if (seen) {
         T sh[3][16];
         for (int k2 = 0; k2 < 16; k2++)
-            for (int c = 0; c < 3; c++) sh[c][k2] = P[(11 + 3 * k2 + c) * n + i];
+            for (int c = 0; c < 3; c++) sh[c][k2] = load_at(P + (11 + 3 * k2 + c) * n, ib);
+        const uint32_t rb = (uint32_t)i * (uint32_t)(REC * sizeof(T));   // lane offset in a view's records
         for (int v = 0; v < views; v++) {
             if (!((vis >> v) & 1ull)) continue;
-            const T *dr = dproj + ((int64_t)v * n + i) * REC;
-            T drgb[3] = {dr[D_RGB], dr[D_RGB + 1], dr[D_RGB + 2]};
+            const T *dr = dproj + (int64_t)v * n * REC;
+            T drgb[3] = {load_at(dr + D_RGB, rb), load_at(dr + D_RGB + 1, rb), load_at(dr + D_RGB + 2, rb)};
             const T *cen = cs[v].cen;
             T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
             T idn = rsq_t(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);   // as the forward, so the clamp agrees
@@ -523,12 +497,15 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
     }
     if (!ADAM) {
         for (int k2 = 0; k2 < 16; k2++)
-            for (int c = 0; c < 3; c++) grad[(11 + 3 * k2 + c) * n + i] += gsh[c][k2];
-        for (int j = 0; j < 3; j++) grad[j * n + i] = (grad[j * n + i] + gpos[j]) + gmean[j];
+            for (int c = 0; c < 3; c++) {
+                T *row = grad + (11 + 3 * k2 + c) * n;
+                store_at(row, ib, load_at(row, ib) + gsh[c][k2]);
+            }
+        for (int j = 0; j < 3; j++) store_at(grad + j * n, ib, (load_at(grad + j * n, ib) + gpos[j]) + gmean[j]);
     } else {
         T g3[3];
         for (int j = 0; j < 3; j++) g3[j] = (T(0) + gpos[j]) + gmean[j];
-        adam_row_block<T, 3>(P, ad, 0, n, i, g3);
+        adam_row_block<T, 3>(P, ad, 0, n, ib, g3);
 #pragma unroll
         for (int b = 0; b < 6; b++) {                   // SH rows 11 .. 58, 8 at a time; row - 11 = 3 k + c
             T gb[8];
@@ -537,18 +514,18 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
                 const int t = 8 * b + r;
                 gb[r] = T(0) + gsh[t % 3][t / 3];
             }
-            adam_row_block<T, 8>(P, ad, 11 + 8 * b, n, i, gb);
+            adam_row_block<T, 8>(P, ad, 11 + 8 * b, n, ib, gb);
             asm volatile("" ::: "memory");              // one block's moments in registers at a time
         }
     }
     if (clear) {
-        const V4<T> zero{T(0), T(0), T(0), T(0)};
+        const uint32_t rb = (uint32_t)i * (uint32_t)(REC * sizeof(T));
         for (int v = 0; v < views; v++)
             if ((vis >> v) & 1ull) {
-                V4<T> *rec = reinterpret_cast<V4<T> *>(dproj + ((int64_t)v * n + i) * REC);
-                rec[0] = zero;
-                rec[1] = zero;
-                rec[2] = zero;
+                T *rec = dproj + (int64_t)v * n * REC;
+                store4_at(rec, rb, T(0), T(0), T(0), T(0));
+                store4_at(rec + 4, rb, T(0), T(0), T(0), T(0));
+                store4_at(rec + 8, rb, T(0), T(0), T(0), T(0));
             }
     }
 }

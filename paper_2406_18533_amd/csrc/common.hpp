@@ -275,7 +275,8 @@ __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // ------------------------------------------------------------------ addressing
-// Element at a 32-bit byte offset from a wave-uniform base: the base pointer
+// Element at a 32-bit byte offset from a wave-uniform base (the base MUST be
+// the same in every active lane: it is taken from the first one): the base pointer
 // (a row or a view's start) stays in scalar registers and the per-lane offset
 // is one 32-bit register, so a load or store needs no per-lane 64-bit address
 // arithmetic. The base goes through readfirstlane so that the compiler keeps
@@ -387,6 +388,47 @@ __device__ __forceinline__ void adam_row_block(T *__restrict__ P, const AdamRef<
         store_at(P + k, ib, p[r]);
         store_at(M + k, ib, m[r]);
         store_at(V + k, ib, v[r]);
+    }
+}
+
+// The same update split in two, so that a caller can issue the next row
+// block's loads before it updates and stores the current one: adam_load
+// reads p, m, v of rows row0 .. row0 + CNT - 1, adam_store updates them with
+// gradients g and writes them back (the arithmetic of adam_row_block). The
+// caller tests adam_skipped once.
+template <typename T, int CNT> struct AdamRows {
+    T p[CNT], m[CNT], v[CNT];
+};
+template <typename T> __device__ __forceinline__ bool adam_skipped(const AdamRef<T> &a) { return a.scratch[0] == 0.0; }
+template <typename T, int CNT>
+__device__ __forceinline__ void adam_load(AdamRows<T, CNT> &b, const T *P, const AdamRef<T> &a, int row0, int64_t n,
+                                          uint32_t ib)
+{
+#pragma unroll
+    for (int r = 0; r < CNT; r++) {
+        int64_t k = (int64_t)(row0 + r) * n;
+        b.p[r] = load_at(P + k, ib);
+        b.m[r] = load_at(a.M + k, ib);
+        b.v[r] = load_at(a.V + k, ib);
+    }
+}
+template <typename T, int CNT>
+__device__ __forceinline__ void adam_store(AdamRows<T, CNT> &b, T *P, const AdamRef<T> &a, int row0, int64_t n,
+                                           uint32_t ib, const T *g)
+{
+    double bc1 = a.scratch[0];
+    T b1 = (T)a.c.b1, b2 = (T)a.c.b2, eps = (T)a.c.eps, ibc2s = adam_inv_bc2s<T>(a.scratch[1]);
+#pragma unroll
+    for (int r = 0; r < CNT; r++) {
+        T step = adam_step_size<T>(a.c.lr[row_group(row0 + r)], bc1);
+        adam_one(b.p[r], g[r], b.m[r], b.v[r], b1, b2, step, ibc2s, eps);
+    }
+#pragma unroll
+    for (int r = 0; r < CNT; r++) {
+        int64_t k = (int64_t)(row0 + r) * n;
+        store_at(P + k, ib, b.p[r]);
+        store_at(a.M + k, ib, b.m[r]);
+        store_at(a.V + k, ib, b.v[r]);
     }
 }
 

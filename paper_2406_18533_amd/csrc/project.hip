@@ -328,11 +328,26 @@ __device__ __forceinline__ void geom_grads(const T *__restrict__ P, int64_t n, i
     Shape<T> S;
     make_shape(P, n, i, S);
     T gmean[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gop = T(0);
+    // each lane's next seen view's record gradient is loaded before the
+    // current view's chain rule, so the loads overlap the arithmetic
+    uint64_t rem = vis;
+    quad_t<T> n0 = {}, n1 = {};
+    // (the view differs between lanes, so these addresses are per lane)
+    auto rec_of = [&](uint64_t r) {
+        return reinterpret_cast<const quad_t<T> *>(dproj + ((int64_t)__builtin_ctzll(r) * n + i) * REC);
+    };
+    if (rem) {
+        n0 = rec_of(rem)[0];
+        n1 = rec_of(rem)[1];
+    }
     for (int v = 0; v < views; v++) {
         if (!((vis >> v) & 1ull)) continue;
-        const T *dr = dproj + (int64_t)v * n * REC;
-        const uint32_t rb = (uint32_t)i * (uint32_t)(REC * sizeof(T));
-        quad_t<T> d0 = load4_at(dr, rb), d1 = load4_at(dr + 4, rb);
+        const quad_t<T> d0 = n0, d1 = n1;
+        rem &= rem - 1ull;
+        if (rem) {
+            n0 = rec_of(rem)[0];
+            n1 = rec_of(rem)[1];
+        }
         T du = d0.x, dv = d0.y, da = d0.z, db = d0.w, dc = d1.x, dop = d1.y;
         const Camera<T> &k = cs[v];
         Geo<T> g;
@@ -469,11 +484,22 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
         T sh[3][16];
         for (int k2 = 0; k2 < 16; k2++)
             for (int c = 0; c < 3; c++) sh[c][k2] = load_at(P + (11 + 3 * k2 + c) * n, ib);
-        const uint32_t rb = (uint32_t)i * (uint32_t)(REC * sizeof(T));   // lane offset in a view's records
+        uint64_t rem = vis;                  // the next seen view's colour gradient is loaded ahead
+        T nrgb[3] = {T(0), T(0), T(0)};
+        // (per-lane addresses: the next seen view differs between lanes)
+        auto rgb_of = [&](uint64_t r) { return dproj + ((int64_t)__builtin_ctzll(r) * n + i) * REC + D_RGB; };
+        if (rem) {
+            const T *dr = rgb_of(rem);
+            for (int c = 0; c < 3; c++) nrgb[c] = dr[c];
+        }
         for (int v = 0; v < views; v++) {
             if (!((vis >> v) & 1ull)) continue;
-            const T *dr = dproj + (int64_t)v * n * REC;
-            T drgb[3] = {load_at(dr + D_RGB, rb), load_at(dr + D_RGB + 1, rb), load_at(dr + D_RGB + 2, rb)};
+            T drgb[3] = {nrgb[0], nrgb[1], nrgb[2]};
+            rem &= rem - 1ull;
+            if (rem) {
+                const T *dr = rgb_of(rem);
+                for (int c = 0; c < 3; c++) nrgb[c] = dr[c];
+            }
             const T *cen = cs[v].cen;
             T d[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
             T idn = rsq_t(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);   // as the forward, so the clamp agrees
@@ -502,20 +528,28 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(T *__restrict__ P, int
                 store_at(row, ib, load_at(row, ib) + gsh[c][k2]);
             }
         for (int j = 0; j < 3; j++) store_at(grad + j * n, ib, (load_at(grad + j * n, ib) + gpos[j]) + gmean[j]);
-    } else {
+    } else if (!adam_skipped(ad)) {
+        // position rows, then the SH rows 11 .. 58 eight at a time (row - 11
+        // = 3 k + c), each block's loads issued before the previous block is
+        // updated and stored: two blocks in flight
         T g3[3];
         for (int j = 0; j < 3; j++) g3[j] = (T(0) + gpos[j]) + gmean[j];
-        adam_row_block<T, 3>(P, ad, 0, n, ib, g3);
+        AdamRows<T, 3> b3;
+        AdamRows<T, 8> cur, nxt;
+        adam_load(b3, P, ad, 0, n, ib);
+        adam_load(cur, P, ad, 11, n, ib);
+        adam_store(b3, P, ad, 0, n, ib, g3);
 #pragma unroll
-        for (int b = 0; b < 6; b++) {                   // SH rows 11 .. 58, 8 at a time; row - 11 = 3 k + c
+        for (int b = 0; b < 6; b++) {
+            if (b < 5) adam_load(nxt, P, ad, 11 + 8 * (b + 1), n, ib);
             T gb[8];
 #pragma unroll
             for (int r = 0; r < 8; r++) {
                 const int t = 8 * b + r;
                 gb[r] = T(0) + gsh[t % 3][t / 3];
             }
-            adam_row_block<T, 8>(P, ad, 11 + 8 * b, n, ib, gb);
-            asm volatile("" ::: "memory");              // one block's moments in registers at a time
+            adam_store(cur, P, ad, 11 + 8 * b, n, ib, gb);
+            if (b < 5) cur = nxt;
         }
     }
     if (clear) {

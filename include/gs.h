@@ -291,8 +291,11 @@ gs_status gs_loss_l1(gs_dtype dtype, const void *rgb, const void *target, const 
  * 16x16 tile and channel, then over those in a fixed order: deterministic).
  * dL_drgb (like rgb) = the exact gradient of that loss with respect to rgb
  * (sign(0) = 0 for the L1 part). lam in [0, 1]. The paper names the two
- * terms but not their weight, window or constants; the values above and
- * lam = 0.2 are those of the original 3D Gaussian splatting loss. rgb/target: [3][H][W] per view, views concatenated; values are not
+ * terms but not their weight, window or constants: the window and
+ * constants are SSIM's definition (Wang, Bovik, Sheikh, Simoncelli, IEEE
+ * Trans. Image Processing 13(4), 2004) and lam = 0.2 the weight of the 3D
+ * Gaussian splatting loss (Kerbl et al., ACM Trans. Graphics 42(4), 2023).
+ * rgb/target: [3][H][W] per view, views concatenated; values are not
  * clamped. workspace: gs_loss_dssim_workspace_bytes; its contents on return
  * are scratch. The gradient is written by a second pass over coefficient
  * maps the first pass leaves in the workspace, so dL_drgb must not alias

@@ -269,9 +269,11 @@ def l1_loss(images: list, targets: list):
 # The loss step of the paper's background section (step 3: L1 and SSIM over
 # pixel windows). Readings: SSIM per colour channel with an 11x11 Gaussian
 # window of standard deviation 1.5 (normalised), zero padding outside the
-# image, C1 = 0.01^2, C2 = 0.03^2, averaged over the 3HW values of a view;
-# loss of a view = (1 - lam) L1 + lam (1 - SSIM), lam = 0.2; batch loss =
-# mean over the views.
+# image, C1 = 0.01^2, C2 = 0.03^2, averaged over the 3HW values of a view
+# (window and constants as SSIM's definition: Wang, Bovik, Sheikh,
+# Simoncelli, IEEE Trans. Image Processing 13(4), 2004); loss of a view =
+# (1 - lam) L1 + lam (1 - SSIM), lam = 0.2 (the weight of Kerbl et al., ACM
+# Trans. Graphics 42(4), 2023); batch loss = mean over the views.
 SSIM_WIN, SSIM_SIGMA, SSIM_C1, SSIM_C2 = 11, 1.5, 0.01 ** 2, 0.03 ** 2
 
 
@@ -353,7 +355,8 @@ def l1_dssim_loss(images: list, targets: list, lam: float = 0.2, with_grad: bool
 # (small ones) or split (large ones, by a scale threshold); Gaussians of low
 # opacity (or too large) are pruned; opacities are reset periodically. The
 # paper names these steps and their hyperparameters, not their arithmetic;
-# the readings follow the original 3D Gaussian splatting procedure:
+# the readings follow the procedure of the 3D Gaussian splatting paper this
+# one builds on (Kerbl et al., ACM Trans. Graphics 42(4), 2023):
 #  - statistic: per (view, Gaussian) visible record, the norm of the loss
 #    gradient w.r.t. the projected centre (u, v) in pixels, times `scale` (the
 #    batch size, so it is the gradient of that view's own loss), summed per

@@ -573,7 +573,8 @@ def aerial_bench(steps: int, warmup: int, plain: bool):
     tr.check_overflow()
     out = {"workload": w.name, "gaussians": P.shape[1], "views": len(w.cameras),
            "views_per_s": round(tr.V * steps / dt, 2), "ms_per_step": round(dt * 1e3 / steps, 3),
-           "instances": int(tr.bins.n_instances.item())}
+           "instances": int(tr.bins.n_instances.item()),
+           "scheduler": {"fwd": list(tr.cfg.fwd_shape), "bwd": list(tr.cfg.bwd_shape), "modes": dict(tr.cfg.extra)}}
     del tr
     torch.cuda.empty_cache()
     if plain:
@@ -604,7 +605,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent)")
+    ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent, 2 XCD split, 3 LPT)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-aerial", action="store_true")
     ap.add_argument("--no-dssim", action="store_true")

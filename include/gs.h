@@ -95,6 +95,8 @@ typedef struct gs_bins {
 #define GS_SCHED_PERSISTENT 1  /* persistent workgroups, cost-balanced chunks + stealing */
 #define GS_SCHED_XCD_SPLIT 2   /* one workgroup per tile; each XCD takes one of 8 cost-balanced
                                   contiguous chunks of the serialised tiles (Algorithm 1, G = 8) */
+#define GS_SCHED_LPT 3         /* one workgroup per tile, tiles in decreasing estimated cost
+                                  (longest processing time first); tile_cost NULL = per-tile */
 
 /* Launch shape of the two render kernels and the state of the persistent
  * scheduler (the single-GPU counterpart of section 3.2 "Iterative Workload
@@ -105,9 +107,12 @@ typedef struct gs_bins {
  * XCD-split mode it runs Algorithm 1 with 8 chunks (queues is ignored) and
  * launches one workgroup per tile, the workgroups of XCD x (b mod 8 = x)
  * taking chunk x: the 8 XCDs, each with its own L2, play the part of the
- * paper's GPUs. */
+ * paper's GPUs. In LPT mode it orders the tiles by decreasing tile_cost (a
+ * counting sort over cost classes 2^(1/4) apart) and workgroup b takes the
+ * b-th: the greedy longest-processing-time-first rule for the makespan of
+ * a queue of tasks on identical workers; the workspace holds the order. */
 typedef struct gs_sched {
-    int32_t mode;             /* GS_SCHED_PER_TILE, GS_SCHED_PERSISTENT or GS_SCHED_XCD_SPLIT */
+    int32_t mode;             /* GS_SCHED_PER_TILE, GS_SCHED_PERSISTENT, GS_SCHED_XCD_SPLIT or GS_SCHED_LPT */
     int32_t px_per_thread;    /* 1, 2 or 4: 256, 128 or 64 threads per 16x16 tile */
     int32_t chunk;            /* records staged in LDS per step: 32, 64, 128 or 256 */
     int32_t workers;          /* persistent workgroups (0 = as many as fit on the GPU at once) */

@@ -4,9 +4,9 @@ Hot path (HIP kernels behind the C ABI of include/gs.h, libgs.so):
 transformation, Z-buffer binning + radix sort, render forward, L1 loss,
 render + transformation backward, fused Adam with the paper's batch scaling
 rules. Above it: an autograd Function, a batched graph-captured trainer
-whose render passes run one workgroup per tile (XCD-aware order) or, where
-the autotuner measures it faster, split over the XCDs by per-tile cost, and a
-continuous-batching render server.
+whose render passes take the tiles heaviest first by the previous step's
+per-tile work (or another launch order where the autotuner measures it
+faster), and a continuous-batching render server.
 """
 from . import _lib  # noqa: F401
 

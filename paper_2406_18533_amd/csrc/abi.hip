@@ -212,7 +212,7 @@ size_t gs_bin_workspace_bytes(int64_t n, int32_t views, int64_t capacity, int64_
 
 // Scheduler workspace: cursor[Q] | dp[Q + 1] | ct[T] (uint64) | scan partials, each 256-byte aligned.
 struct SchedWS {
-    size_t cursor, dp, ct, partial, total;
+    size_t cursor, dp, ct, partial, order, bins, total;
 };
 
 static SchedWS sched_ws(int64_t total_tiles, int32_t q)
@@ -224,7 +224,9 @@ static SchedWS sched_ws(int64_t total_tiles, int32_t q)
     w.dp = al(4 * (size_t)q);
     w.ct = w.dp + al(4 * ((size_t)q + 1));
     w.partial = w.ct + al(8 * t);
-    w.total = w.partial + al(8 * (t / 4096 + 8));
+    w.order = w.partial + al(8 * (t / 4096 + 8));
+    w.bins = w.order + al(4 * t);
+    w.total = w.bins + al(4 * 2 * (size_t)LPT_BINS);
     return w;
 }
 
@@ -328,8 +330,11 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.S.cursor = nullptr;
     sh.S.dp = nullptr;
     sh.S.queues = 0;
+    sh.S.order = nullptr;
+    sh.S.bins = nullptr;
     if (!sc) return true;
-    if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT && sc->mode != GS_SCHED_XCD_SPLIT) {
+    if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT && sc->mode != GS_SCHED_XCD_SPLIT &&
+        sc->mode != GS_SCHED_LPT) {
         why = "bad sched mode";
         return false;
     }
@@ -338,6 +343,17 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.mode = sc->mode;
     sh.px = sc->px_per_thread;
     sh.chunk = sc->chunk;
+    if (sh.mode == GS_SCHED_LPT && !sc->tile_cost) sh.mode = GS_SCHED_PER_TILE;   // no costs: index order
+    if (sh.mode == GS_SCHED_LPT) {
+        if (!sc->workspace || sc->workspace_bytes < gs_sched_workspace_bytes(total_tiles, 8)) {
+            why = "sched workspace too small";
+            return false;
+        }
+        SchedWS L = sched_ws(total_tiles, 8);
+        char *w = (char *)sc->workspace;
+        sh.S.order = (int32_t *)(w + L.order);
+        sh.S.bins = (uint32_t *)(w + L.bins);
+    }
     if (sh.mode == GS_SCHED_PERSISTENT || sh.mode == GS_SCHED_XCD_SPLIT) {
         int q = sh.mode == GS_SCHED_XCD_SPLIT ? 8 : (sc->queues > 0 ? sc->queues : 64);
         if (q % 8 != 0 || q > (1 << 16)) { why = "queues must be a positive multiple of 8"; return false; }
@@ -361,6 +377,7 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
 static hipError_t run_plan(const gs_sched *sc, const LaunchShape &sh, int32_t total_tiles, int32_t *dp_out,
                            hipStream_t s)
 {
+    if (sh.mode == GS_SCHED_LPT) return launch_lpt_plan(sc->tile_cost, total_tiles, sh.S.bins, sh.S.order, s);
     SchedWS L = sched_ws(total_tiles, sh.S.queues);
     char *w = (char *)sc->workspace;
     return launch_plan(sc->tile_cost, total_tiles, sh.S.queues, (uint64_t *)(w + L.ct), (uint64_t *)(w + L.partial),

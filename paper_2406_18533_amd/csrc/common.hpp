@@ -64,7 +64,14 @@ struct SchedState {
     int32_t *cursor;   // [queues] next tile of each queue
     int32_t *dp;       // [queues + 1] division points
     int32_t queues;    // multiple of 8
+    int32_t *order;    // [total_tiles] tiles by decreasing estimated cost (LPT mode)
+    uint32_t *bins;    // [2 * LPT_BINS] the LPT counting sort's histogram and cursors
 };
+
+// Cost classes of the LPT order: 4 per octave of the estimated cost (a class
+// spans a factor 2^(1/4) = 1.19), class 0 the heaviest.
+constexpr int LPT_BINS = 136;
+hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, uint32_t *bins, int32_t *order, hipStream_t s);
 
 // Resolved launch shape of the render kernels.
 struct LaunchShape {

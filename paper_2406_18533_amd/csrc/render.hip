@@ -630,6 +630,30 @@ render_bwd_xcd(ViewTable vt, BwdArgs<T> A, const int32_t *__restrict__ dp)
     }
 }
 
+// LPT order: workgroup b takes the b-th heaviest tile of the previous
+// iteration's per-tile work (order from launch_lpt_plan), so the long tiles
+// start first and the launch ends on short ones; workgroups are dealt to
+// the XCDs round-robin, which spreads the heavy tiles over all of them.
+template <typename T, int PX, int CHUNK, bool STATS>
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(7)))
+render_fwd_lpt(ViewTable vt, FwdArgs<T> A, const int32_t *__restrict__ order)
+{
+    __shared__ Stage<T, CHUNK, false> st;
+    __shared__ uint32_t s_red;
+    if ((int32_t)blockIdx.x >= vt.total_tiles) return;
+    fwd_tile<T, PX, CHUNK, STATS>(order[blockIdx.x], vt, A, st, &s_red);
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(6)))
+render_bwd_lpt(ViewTable vt, BwdArgs<T> A, const int32_t *__restrict__ order)
+{
+    __shared__ Stage<T, CHUNK, true> st;
+    __shared__ uint32_t s_red;
+    if ((int32_t)blockIdx.x >= vt.total_tiles) return;
+    bwd_tile<T, PX, CHUNK>(order[blockIdx.x], vt, A, st, &s_red);
+}
+
 // ------------------------------------------------------------------ launchers
 #define GS_DISPATCH_SHAPE(T, PX, CH, CALL)                                                                   \
     do {                                                                                                     \
@@ -712,6 +736,9 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     else if (sh.mode == GS_SCHED_XCD_SPLIT)                                                                  \
         hipLaunchKernelGGL((render_fwd_xcd<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
                            (const int32_t *)sh.S.dp);                                                        \
+    else if (sh.mode == GS_SCHED_LPT)                                                                        \
+        hipLaunchKernelGGL((render_fwd_lpt<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
+                           (const int32_t *)sh.S.order);                                                     \
     else                                                                                                     \
         hipLaunchKernelGGL((render_fwd_kernel<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
 #define GS_FWD(TT, P, C)                                                                                     \
@@ -750,6 +777,9 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
     else if (sh.mode == GS_SCHED_XCD_SPLIT)                                                                  \
         hipLaunchKernelGGL((render_bwd_xcd<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,          \
                            (const int32_t *)sh.S.dp);                                                        \
+    else if (sh.mode == GS_SCHED_LPT)                                                                        \
+        hipLaunchKernelGGL((render_bwd_lpt<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,          \
+                           (const int32_t *)sh.S.order);                                                     \
     else                                                                                                     \
         hipLaunchKernelGGL((render_bwd_kernel<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
     if (sizeof(T) == 8) {

@@ -132,7 +132,8 @@ class Bins:
 
 
 class Sched:
-    """Launch shape of the render kernels (+ persistent scheduler state)."""
+    """Launch shape of the render kernels (+ the scheduler's workspace for the
+    persistent, XCD-split and LPT modes)."""
 
     def __init__(self, cams: Cameras | None = None, mode: int = _lib.GS_SCHED_PER_TILE, px_per_thread: int = 1,
                  chunk: int = 64, workers: int = 0, queues: int = 64, tile_cost: torch.Tensor | None = None,
@@ -141,9 +142,9 @@ class Sched:
         self.tile_cost = tile_cost
         self.workspace = None
         wsb = 0
-        if mode in (_lib.GS_SCHED_PERSISTENT, _lib.GS_SCHED_XCD_SPLIT):
+        if mode in (_lib.GS_SCHED_PERSISTENT, _lib.GS_SCHED_XCD_SPLIT, _lib.GS_SCHED_LPT):
             assert cams is not None
-            q = 8 if mode == _lib.GS_SCHED_XCD_SPLIT else queues
+            q = queues if mode == _lib.GS_SCHED_PERSISTENT else 8
             wsb = int(_lib.load().gs_sched_workspace_bytes(cams.total_tiles(), q))
             self.workspace = torch.empty(wsb, dtype=torch.uint8, device=device)
         self.struct = GsSched(mode, px_per_thread, chunk, workers, queues, 0,

@@ -4,9 +4,10 @@ BatchedTrainer: the batched step of the paper's training loop (section 2.1:
 transformation, rendering, loss, back-propagation; section 4: Adam with
 lr * sqrt(b) and beta^b) over all b views at once - one projection launch
 for every view, one (view, tile) work list for the whole batch, render
-kernels launched one workgroup per tile or split over the XCDs by the
-previous iteration's per-tile work (whichever the autotuner measured faster
-for that pass), and the whole step captured once as a HIP graph and replayed.
+kernels launched in an order driven by the previous iteration's per-tile work
+(heaviest tiles first, or split over the XCDs: whichever the autotuner
+measured faster for that pass), and the whole step captured once as a HIP
+graph and replayed.
 
 PlainTrainer: the same batched step computed view by view with eager
 launches and one workgroup per tile (the baseline the batched path is

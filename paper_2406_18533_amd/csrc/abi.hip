@@ -226,7 +226,7 @@ static SchedWS sched_ws(int64_t total_tiles, int32_t q)
     w.partial = w.ct + al(8 * t);
     w.order = w.partial + al(8 * (t / 4096 + 8));
     w.bins = w.order + al(4 * t);
-    w.total = w.bins + al(4 * 2 * (size_t)LPT_BINS);
+    w.total = w.bins + al(4 * 2 * (size_t)LPT_SEGS * (size_t)LPT_BINS);
     return w;
 }
 
@@ -334,7 +334,7 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.S.bins = nullptr;
     if (!sc) return true;
     if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT && sc->mode != GS_SCHED_XCD_SPLIT &&
-        sc->mode != GS_SCHED_LPT) {
+        sc->mode != GS_SCHED_LPT && sc->mode != GS_SCHED_XCD_LPT) {
         why = "bad sched mode";
         return false;
     }
@@ -343,8 +343,9 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.mode = sc->mode;
     sh.px = sc->px_per_thread;
     sh.chunk = sc->chunk;
-    if (sh.mode == GS_SCHED_LPT && !sc->tile_cost) sh.mode = GS_SCHED_PER_TILE;   // no costs: index order
-    if (sh.mode == GS_SCHED_LPT) {
+    if ((sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_XCD_LPT) && !sc->tile_cost)
+        sh.mode = GS_SCHED_PER_TILE;   // no costs: index order
+    if (sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_XCD_LPT) {
         if (!sc->workspace || sc->workspace_bytes < gs_sched_workspace_bytes(total_tiles, 8)) {
             why = "sched workspace too small";
             return false;
@@ -354,8 +355,8 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
         sh.S.order = (int32_t *)(w + L.order);
         sh.S.bins = (uint32_t *)(w + L.bins);
     }
-    if (sh.mode == GS_SCHED_PERSISTENT || sh.mode == GS_SCHED_XCD_SPLIT) {
-        int q = sh.mode == GS_SCHED_XCD_SPLIT ? 8 : (sc->queues > 0 ? sc->queues : 64);
+    if (sh.mode == GS_SCHED_PERSISTENT || sh.mode == GS_SCHED_XCD_SPLIT || sh.mode == GS_SCHED_XCD_LPT) {
+        int q = sh.mode == GS_SCHED_PERSISTENT ? (sc->queues > 0 ? sc->queues : 64) : 8;
         if (q % 8 != 0 || q > (1 << 16)) { why = "queues must be a positive multiple of 8"; return false; }
         if (!sc->workspace || sc->workspace_bytes < gs_sched_workspace_bytes(total_tiles, q)) {
             why = "sched workspace too small";
@@ -377,11 +378,14 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
 static hipError_t run_plan(const gs_sched *sc, const LaunchShape &sh, int32_t total_tiles, int32_t *dp_out,
                            hipStream_t s)
 {
-    if (sh.mode == GS_SCHED_LPT) return launch_lpt_plan(sc->tile_cost, total_tiles, sh.S.bins, sh.S.order, s);
+    if (sh.mode == GS_SCHED_LPT)
+        return launch_lpt_plan(sc->tile_cost, total_tiles, nullptr, 1, sh.S.bins, sh.S.order, s);
     SchedWS L = sched_ws(total_tiles, sh.S.queues);
     char *w = (char *)sc->workspace;
-    return launch_plan(sc->tile_cost, total_tiles, sh.S.queues, (uint64_t *)(w + L.ct), (uint64_t *)(w + L.partial),
-                       sh.S.dp, sh.S.cursor, dp_out, s);
+    hipError_t e = launch_plan(sc->tile_cost, total_tiles, sh.S.queues, (uint64_t *)(w + L.ct),
+                               (uint64_t *)(w + L.partial), sh.S.dp, sh.S.cursor, dp_out, s);
+    if (e != hipSuccess || sh.mode != GS_SCHED_XCD_LPT) return e;
+    return launch_lpt_plan(sc->tile_cost, total_tiles, sh.S.dp, 8, sh.S.bins, sh.S.order, s);
 }
 
 gs_status gs_sched_plan(const gs_sched *sched, const gs_camera *cams_host, int32_t views, int32_t *dp_out, void *stream)

@@ -875,9 +875,12 @@ hipError_t launch_plan(const uint32_t *cost, int32_t T_all, int32_t Q, uint64_t 
 
 // LPT order (longest processing time first): the tiles sorted by decreasing
 // estimated cost, by a counting sort over LPT_BINS cost classes (4 per
-// octave; an approximate order is all the greedy rule needs). Within a class
-// the order follows the arrival of the scatter's workgroups (roughly index
-// order; the images do not depend on it).
+// octave; an approximate order is all the greedy rule needs). With nseg > 1
+// the tiles are first cut into nseg contiguous segments at the division
+// points dp (Algorithm 1) and each segment is sorted in place, within its
+// own range of the order. Within a class the order follows the arrival of
+// the scatter's workgroups (roughly index order; the images do not depend
+// on it).
 __device__ __forceinline__ int lpt_bin(uint32_t c)
 {
     int k = c == 0u ? 0 : 1 + (int)floorf(4.0f * __log2f((float)c));
@@ -885,25 +888,36 @@ __device__ __forceinline__ int lpt_bin(uint32_t c)
     return LPT_BINS - 1 - k;                       // class 0 = heaviest
 }
 
+__device__ __forceinline__ int lpt_seg(const int32_t *dp, int nseg, int32_t t)
+{
+    int sg = 0;
+    for (int j = 1; j < nseg; j++) sg += t >= dp[j] ? 1 : 0;
+    return sg;
+}
+
 __global__ void __launch_bounds__(256) lpt_hist_kernel(const uint32_t *__restrict__ cost, int32_t T_all,
+                                                       const int32_t *__restrict__ dp, int nseg,
                                                        uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t h[LPT_BINS];
-    for (int j = threadIdx.x; j < LPT_BINS; j += 256) h[j] = 0u;
+    __shared__ uint32_t h[LPT_SEGS * LPT_BINS];
+    for (int j = threadIdx.x; j < nseg * LPT_BINS; j += 256) h[j] = 0u;
     __syncthreads();
     const int32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t < T_all) atomicAdd(&h[lpt_bin(cost[t])], 1u);
+    if (t < T_all) atomicAdd(&h[lpt_seg(dp, nseg, t) * LPT_BINS + lpt_bin(cost[t])], 1u);
     __syncthreads();
-    for (int j = threadIdx.x; j < LPT_BINS; j += 256)
+    for (int j = threadIdx.x; j < nseg * LPT_BINS; j += 256)
         if (h[j]) atomicAdd(&hist[j], h[j]);
 }
 
-// Exclusive prefix of the class counts, heaviest class first (one block).
-__global__ void __launch_bounds__(256) lpt_scan_kernel(const uint32_t *__restrict__ hist, uint32_t *__restrict__ cur)
+// Exclusive prefix of each segment's class counts, heaviest class first,
+// from the segment's first position (one block per segment).
+__global__ void __launch_bounds__(256) lpt_scan_kernel(const uint32_t *__restrict__ hist, const int32_t *__restrict__ dp,
+                                                       uint32_t *__restrict__ cur)
 {
     __shared__ uint32_t v[256];
-    const int j = threadIdx.x;
-    v[j] = j < LPT_BINS ? hist[j] : 0u;
+    const int j = threadIdx.x, sg = blockIdx.x;
+    const uint32_t hj = j < LPT_BINS ? hist[sg * LPT_BINS + j] : 0u;
+    v[j] = hj;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
         uint32_t a = j >= o ? v[j - o] : 0u;
@@ -911,37 +925,43 @@ __global__ void __launch_bounds__(256) lpt_scan_kernel(const uint32_t *__restric
         v[j] += a;
         __syncthreads();
     }
-    if (j < LPT_BINS) cur[j] = v[j] - (j < LPT_BINS ? hist[j] : 0u);
+    const uint32_t base = dp ? (uint32_t)dp[sg] : 0u;
+    if (j < LPT_BINS) cur[sg * LPT_BINS + j] = base + v[j] - hj;
 }
 
 __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t *__restrict__ cost, int32_t T_all,
+                                                          const int32_t *__restrict__ dp, int nseg,
                                                           uint32_t *__restrict__ cur, int32_t *__restrict__ order)
 {
-    __shared__ uint32_t cnt[LPT_BINS], base[LPT_BINS];
-    for (int j = threadIdx.x; j < LPT_BINS; j += 256) cnt[j] = 0u;
+    __shared__ uint32_t cnt[LPT_SEGS * LPT_BINS], base[LPT_SEGS * LPT_BINS];
+    for (int j = threadIdx.x; j < nseg * LPT_BINS; j += 256) cnt[j] = 0u;
     __syncthreads();
     const int32_t t = blockIdx.x * 256 + threadIdx.x;
     int b = 0;
     uint32_t r = 0;
     if (t < T_all) {
-        b = lpt_bin(cost[t]);
+        b = lpt_seg(dp, nseg, t) * LPT_BINS + lpt_bin(cost[t]);
         r = atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < LPT_BINS; j += 256)
+    for (int j = threadIdx.x; j < nseg * LPT_BINS; j += 256)
         if (cnt[j]) base[j] = atomicAdd(&cur[j], cnt[j]);
     __syncthreads();
     if (t < T_all) order[base[b] + r] = t;
 }
 
-hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, uint32_t *bins, int32_t *order, hipStream_t s)
+hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, const int32_t *dp, int nseg, uint32_t *bins,
+                           int32_t *order, hipStream_t s)
 {
     if (T_all <= 0) return hipSuccess;
+    if (nseg < 1 || nseg > LPT_SEGS || (nseg > 1 && !dp)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)((T_all + 255) / 256);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(2), dim3(256), 0, s, bins, (int64_t)(2 * LPT_BINS), 0u);
-    hipLaunchKernelGGL(lpt_hist_kernel, dim3(g), dim3(256), 0, s, cost, T_all, bins);
-    hipLaunchKernelGGL(lpt_scan_kernel, dim3(1), dim3(256), 0, s, (const uint32_t *)bins, bins + LPT_BINS);
-    hipLaunchKernelGGL(lpt_scatter_kernel, dim3(g), dim3(256), 0, s, cost, T_all, bins + LPT_BINS, order);
+    const int64_t nb = (int64_t)nseg * LPT_BINS;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((2 * nb + 255) / 256)), dim3(256), 0, s, bins, 2 * nb, 0u);
+    hipLaunchKernelGGL(lpt_hist_kernel, dim3(g), dim3(256), 0, s, cost, T_all, dp, nseg, bins);
+    hipLaunchKernelGGL(lpt_scan_kernel, dim3((unsigned)nseg), dim3(256), 0, s, (const uint32_t *)bins,
+                       nseg > 1 ? dp : nullptr, bins + nb);
+    hipLaunchKernelGGL(lpt_scatter_kernel, dim3(g), dim3(256), 0, s, cost, T_all, dp, nseg, bins + nb, order);
     return hipGetLastError();
 }
 

@@ -65,13 +65,16 @@ struct SchedState {
     int32_t *dp;       // [queues + 1] division points
     int32_t queues;    // multiple of 8
     int32_t *order;    // [total_tiles] tiles by decreasing estimated cost (LPT mode)
-    uint32_t *bins;    // [2 * LPT_BINS] the LPT counting sort's histogram and cursors
+    uint32_t *bins;    // [2 * LPT_SEGS * LPT_BINS] the LPT counting sort's histogram and cursors
 };
 
 // Cost classes of the LPT order: 4 per octave of the estimated cost (a class
-// spans a factor 2^(1/4) = 1.19), class 0 the heaviest.
+// spans a factor 2^(1/4) = 1.19), class 0 the heaviest; up to LPT_SEGS
+// segments sorted separately (the XCD chunks of Algorithm 1).
 constexpr int LPT_BINS = 136;
-hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, uint32_t *bins, int32_t *order, hipStream_t s);
+constexpr int LPT_SEGS = 8;
+hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, const int32_t *dp, int nseg, uint32_t *bins,
+                           int32_t *order, hipStream_t s);
 
 // Resolved launch shape of the render kernels.
 struct LaunchShape {

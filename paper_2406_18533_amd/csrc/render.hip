@@ -654,6 +654,37 @@ render_bwd_lpt(ViewTable vt, BwdArgs<T> A, const int32_t *__restrict__ order)
     bwd_tile<T, PX, CHUNK>(order[blockIdx.x], vt, A, st, &s_red);
 }
 
+// XCD split with the LPT order inside each chunk: XCD x takes chunk x of
+// Algorithm 1 (G = 8) as in the XCD split, its tiles heaviest first (order
+// holds each chunk's tiles in decreasing cost, at the chunk's positions).
+template <typename T, int PX, int CHUNK, bool STATS>
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(7)))
+render_fwd_xcd_lpt(ViewTable vt, FwdArgs<T> A, const int32_t *__restrict__ dp, const int32_t *__restrict__ order)
+{
+    __shared__ Stage<T, CHUNK, false> st;
+    __shared__ uint32_t s_red;
+    const int x = blockIdx.x & 7;
+    const int32_t per = (int32_t)(gridDim.x >> 3), hi = dp[x + 1];
+    for (int32_t j = dp[x] + (int32_t)(blockIdx.x >> 3); j < hi; j += per) {
+        fwd_tile<T, PX, CHUNK, STATS>(order[j], vt, A, st, &s_red);
+        __syncthreads();
+    }
+}
+
+template <typename T, int PX, int CHUNK>
+__global__ void __launch_bounds__(256 / PX) __attribute__((amdgpu_waves_per_eu(6)))
+render_bwd_xcd_lpt(ViewTable vt, BwdArgs<T> A, const int32_t *__restrict__ dp, const int32_t *__restrict__ order)
+{
+    __shared__ Stage<T, CHUNK, true> st;
+    __shared__ uint32_t s_red;
+    const int x = blockIdx.x & 7;
+    const int32_t per = (int32_t)(gridDim.x >> 3), hi = dp[x + 1];
+    for (int32_t j = dp[x] + (int32_t)(blockIdx.x >> 3); j < hi; j += per) {
+        bwd_tile<T, PX, CHUNK>(order[j], vt, A, st, &s_red);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 #define GS_DISPATCH_SHAPE(T, PX, CH, CALL)                                                                   \
     do {                                                                                                     \
@@ -739,6 +770,9 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     else if (sh.mode == GS_SCHED_LPT)                                                                        \
         hipLaunchKernelGGL((render_fwd_lpt<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
                            (const int32_t *)sh.S.order);                                                     \
+    else if (sh.mode == GS_SCHED_XCD_LPT)                                                                    \
+        hipLaunchKernelGGL((render_fwd_xcd_lpt<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,  \
+                           (const int32_t *)sh.S.dp, (const int32_t *)sh.S.order);                           \
     else                                                                                                     \
         hipLaunchKernelGGL((render_fwd_kernel<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
 #define GS_FWD(TT, P, C)                                                                                     \
@@ -780,6 +814,9 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
     else if (sh.mode == GS_SCHED_LPT)                                                                        \
         hipLaunchKernelGGL((render_bwd_lpt<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,          \
                            (const int32_t *)sh.S.order);                                                     \
+    else if (sh.mode == GS_SCHED_XCD_LPT)                                                                    \
+        hipLaunchKernelGGL((render_bwd_xcd_lpt<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
+                           (const int32_t *)sh.S.dp, (const int32_t *)sh.S.order);                           \
     else                                                                                                     \
         hipLaunchKernelGGL((render_bwd_kernel<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A);
     if (sizeof(T) == 8) {

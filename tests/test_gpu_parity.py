@@ -472,7 +472,9 @@ def test_image_identical_across_launch_shapes_and_schedulers():
                dict(mode=_lib.GS_SCHED_XCD_SPLIT, px_per_thread=4, chunk=64),
                dict(mode=_lib.GS_SCHED_XCD_SPLIT, px_per_thread=2, chunk=128, tile_cost=skewed),
                dict(mode=_lib.GS_SCHED_LPT, px_per_thread=4, chunk=64, tile_cost=ref["work_fwd"]),
-               dict(mode=_lib.GS_SCHED_LPT, px_per_thread=1, chunk=32, tile_cost=skewed)]:
+               dict(mode=_lib.GS_SCHED_LPT, px_per_thread=1, chunk=32, tile_cost=skewed),
+               dict(mode=_lib.GS_SCHED_XCD_LPT, px_per_thread=4, chunk=64, tile_cost=ref["work_fwd"]),
+               dict(mode=_lib.GS_SCHED_XCD_LPT, px_per_thread=2, chunk=128, tile_cost=skewed)]:
         f = gp.forward(Pd, cams, BG, sched_kw=kw)
         assert torch.equal(f["rgb"], ref["rgb"]) and torch.equal(f["T"], ref["T"]), kw
         assert torch.equal(f["last"], ref["last"]), kw

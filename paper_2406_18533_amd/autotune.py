@@ -3,7 +3,8 @@
 For a trainer's workload it times every launch shape (pixels per thread, LDS
 chunk) of the forward and of the backward render on the per-tile launch with
 HIP events on the real buffers, then the five scheduler modes at the best
-shape in interleaved rounds (a cost-driven mode is taken only when it beats
+shape in interleaved rounds, each pass timed after the kernels that precede
+it in the step (a cost-driven mode is taken only when it beats
 per-tile by 1%), and caches the choice in a JSON file keyed by (architecture,
 resolution class, view count, Gaussian-count bucket).
 """
@@ -34,7 +35,7 @@ def workload_key(cams: R.Cameras, n: int) -> str:
     nb = 2 ** int(math.log2(max(n, 1)))
     props = torch.cuda.get_device_properties(0)
     arch = getattr(props, "gcnArchName", "gfx950").split(":")[0]
-    return f"{arch}|{res}|v{cams.n}|n{nb}|modes{len(MODES)}"
+    return f"{arch}|{res}|v{cams.n}|n{nb}|modes{len(MODES)}-in-step"
 
 
 def _load():
@@ -68,7 +69,8 @@ def tune(tr, reps: int = 3, use_cache: bool = True, verbose: bool = False, mode_
     """Picks (mode, px, chunk) for forward and backward of a BatchedTrainer:
     the launch shape (pixels per thread, LDS chunk) on the per-tile launch,
     then the scheduler mode at that shape, the modes timed in interleaved
-    rounds so that drift between launches does not favour one."""
+    rounds so that drift between launches does not favour one, each pass
+    after the kernels that precede it in the step."""
     key = workload_key(tr.cams, tr.n)
     cache = _load() if use_cache else {}
     if key in cache:
@@ -97,17 +99,27 @@ def tune(tr, reps: int = 3, use_cache: bool = True, verbose: bool = False, mode_
                 results["bwd"].append((tb, _lib.GS_SCHED_PER_TILE, px, ch))
                 if verbose:
                     print(f"autotune px={px} chunk={ch}: fwd {tf:.3f} ms bwd {tb:.3f} ms", flush=True)
+        # the modes at the best shapes, each timed where the step runs it:
+        # after the transformation and binning (which displace the render
+        # kernels' data from the caches) for the forward, after the forward
+        # for the backward; modes interleaved over the rounds
         best = {}
-        for p, mk, cost in (("fwd", fwd, tr.work_fwd), ("bwd", bwd, tr.work_bwd)):
-            _, _, px, ch = min(results[p])
-            fns = {m: mk(sched(m, px, ch, cost)) for m in MODES}
-            acc = {m: 0.0 for m in MODES}
+        _, _, fpx, fch = min(results["fwd"])
+        _, _, bpx, bch = min(results["bwd"])
+        fns = {m: (fwd(sched(m, fpx, fch, tr.work_fwd)), bwd(sched(m, bpx, bch, tr.work_bwd))) for m in MODES}
+        acc = {m: [0.0, 0.0] for m in MODES}
+        for r in range(mode_rounds + 1):
             for m in MODES:
-                fns[m]()
-            for _ in range(mode_rounds):
-                for m in MODES:
-                    acc[m] += _time(fns[m], 1) / mode_rounds
-            rows = [(acc[m], m, px, ch) for m in MODES]
+                R.gs_project(tr.P, tr.cams, tr.proj)
+                R.gs_bin_sort(tr.proj, tr.n, tr.cams, tr.bins, check_capacity=False)
+                tf = _time(fns[m][0], 1)
+                tb = _time(fns[m][1], 1)
+                tr.dproj.zero_()
+                if r > 0:                      # round 0 warms every mode's plan and kernels
+                    acc[m][0] += tf / mode_rounds
+                    acc[m][1] += tb / mode_rounds
+        for j, (p, px, ch) in enumerate((("fwd", fpx, fch), ("bwd", bpx, bch))):
+            rows = [(acc[m][j], m, px, ch) for m in MODES]
             results[p + "_modes"] = rows
             b = _pick(rows)
             best[p] = {"mode": b[1], "px": b[2], "chunk": b[3], "ms": b[0]}

@@ -404,3 +404,27 @@ def test_checkpoint_resume_continues_the_trajectory(tmp_path):
     moved = (ref.P - P0).norm().item()
     print(f"resumed vs straight after 100 steps: parameter distance {(b.P - ref.P).norm().item() / moved:.2e} "
           f"of the displacement", flush=True)
+
+
+def test_autotune_leaves_the_training_state_unchanged():
+    """The autotuner times launch shapes and scheduler modes on the trainer's
+    own buffers without moving its parameters, moments or step counter, and
+    records a valid shape and mode for each pass; a step afterwards equals a
+    step of an untuned trainer that uses the same choices."""
+    from paper_2406_18533_amd import _lib, autotune, train
+    P, cams, tgt = _small_batch()
+    tr = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=False))
+    tr.step_eager()                                  # some state to keep
+    before = [x.clone() for x in (tr.P, tr.m, tr.v, tr.step_dev)]
+    best = autotune.tune(tr, use_cache=False, mode_rounds=2)
+    torch.cuda.synchronize()
+    for a, b in zip(before, (tr.P, tr.m, tr.v, tr.step_dev)):
+        assert torch.equal(a, b)
+    for p in ("fwd", "bwd"):
+        assert best[p]["mode"] in autotune.MODES
+        assert best[p]["px"] in autotune.PX and best[p]["chunk"] in autotune.CHUNKS
+        assert len(best["table"][p + "_modes"]) == len(autotune.MODES)
+    print(f"autotune picked fwd {best['fwd']} bwd {best['bwd']}", flush=True)
+    tr.step_eager()
+    tr.check_overflow()
+    assert torch.isfinite(tr.P).all()

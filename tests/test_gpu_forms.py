@@ -262,16 +262,19 @@ def test_fused_backward_adam_equals_separate_calls(n):
     assert not torch.equal(state["fused"]["P"], P.cuda())
 
 
-@pytest.mark.parametrize("lam", [0.0, 0.2])
-def test_graph_replay_equals_eager_steps(lam):
+@pytest.mark.parametrize("lam,mode", [(0.0, "per_tile"), (0.2, "per_tile"), (0.0, "lpt"), (0.0, "xcd_split")])
+def test_graph_replay_equals_eager_steps(lam, mode):
     """Whole-step graph replays, with eager work and synchronisations in
-    between, track eager steps from the same start (L1 loss, and L1 + D-SSIM):
-    losses within 1e-4 relative at every one of 50 steps."""
-    from paper_2406_18533_amd import train
+    between, track eager steps from the same start (L1 loss, and L1 + D-SSIM;
+    the cost-driven launch orders, whose plans run inside the captured step
+    on the previous replay's tile work): losses within 1e-4 relative at every
+    one of 50 steps."""
+    from paper_2406_18533_amd import _lib, train
+    m = {"per_tile": _lib.GS_SCHED_PER_TILE, "lpt": _lib.GS_SCHED_LPT, "xcd_split": _lib.GS_SCHED_XCD_SPLIT}[mode]
     P, cams, tgt = _small_batch()
     P0 = P.cuda()
-    eager = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=False, ssim_lambda=lam))
-    graph = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=True, ssim_lambda=lam))
+    eager = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=False, ssim_lambda=lam, mode=m))
+    graph = train.BatchedTrainer(P0.clone(), cams, tgt.cuda(), train.TrainConfig(graph=True, ssim_lambda=lam, mode=m))
     for k in range(50):
         eager.step()
         graph.step()
@@ -282,7 +285,7 @@ def test_graph_replay_equals_eager_steps(lam):
     assert graph.graph is not None
     assert graph.step_dev.item() == 50
     moved = (eager.P - P0).norm().item()
-    print(f"graph vs eager after 50 steps (lambda {lam}): parameter distance "
+    print(f"graph vs eager after 50 steps (lambda {lam}, {mode}): parameter distance "
           f"{(graph.P - eager.P).norm().item() / moved:.2e} of the displacement", flush=True)
 
 

@@ -481,6 +481,55 @@ def test_image_identical_across_launch_shapes_and_schedulers():
         assert torch.equal(f["work_bwd"], ref["work_bwd"]), kw
 
 
+def _lpt_workspace(sched, T):
+    """The order and division points a cost-driven launch left in its
+    workspace (layout of the scheduler workspace for 8 chunks: cursors, then
+    division points at byte 256, then the cumulative costs, partial sums, the
+    order and the sort's bins, each region 256-byte aligned)."""
+    al = lambda x: (x + 255) // 256 * 256
+    ws = sched.workspace.cpu().numpy()
+    dp = ws[256:256 + 36].view(np.int32)
+    order_off = 512 + al(8 * T) + al(8 * (T // 4096 + 8))
+    order = ws[order_off:order_off + 4 * T].view(np.int32)
+    return dp, order
+
+
+def test_lpt_orders_are_permutations_by_decreasing_cost():
+    """The LPT launch takes every tile exactly once, in decreasing order of
+    the tile cost it was given (cost classes are 2^(1/4) apart, so along the
+    order the class may rise by at most one where rounding puts a cost on a
+    class boundary); XCD-LPT does the same inside each of Algorithm 1's eight
+    chunks, each chunk keeping exactly its own tiles."""
+    gp = _gp()
+    from paper_2406_18533_amd import _lib
+    P, cams = small_multiview()
+    Pd = gp.to_dev(P)
+    ref = gp.forward(Pd, cams, BG)
+    cost = ref["work_fwd"].clone()
+    cost[::7] *= 40                                  # a few heavy tiles scattered over the views
+    c = cost.cpu().numpy().astype(np.float64)
+    T = c.size
+    cls = np.where(c > 0, 1 + np.floor(4 * np.log2(np.maximum(c, 1))), 0)
+
+    def decreasing(idx):
+        seq = cls[idx]
+        return bool(np.all(seq[1:] <= np.minimum.accumulate(seq)[:-1] + 1))
+
+    f = gp.forward(Pd, cams, BG, sched_kw=dict(mode=_lib.GS_SCHED_LPT, px_per_thread=4, chunk=64, tile_cost=cost))
+    _, order = _lpt_workspace(f["sched"], T)
+    assert np.array_equal(np.sort(order), np.arange(T))
+    assert decreasing(order)
+    assert torch.equal(f["rgb"], ref["rgb"])
+    f = gp.forward(Pd, cams, BG, sched_kw=dict(mode=_lib.GS_SCHED_XCD_LPT, px_per_thread=4, chunk=64, tile_cost=cost))
+    dp, order = _lpt_workspace(f["sched"], T)
+    assert dp[0] == 0 and dp[8] == T and np.all(np.diff(dp) >= 0)
+    for x in range(8):
+        part = order[dp[x]:dp[x + 1]]
+        assert np.array_equal(np.sort(part), np.arange(dp[x], dp[x + 1]))
+        assert decreasing(part)
+    assert torch.equal(f["rgb"], ref["rgb"])
+
+
 def test_view_alone_equals_view_in_batch():
     gp = _gp()
     P, cams = small_multiview()

@@ -605,7 +605,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--mode", type=int, default=None, help="force scheduler mode (0 per-tile, 1 persistent, 2 XCD split, 3 LPT)")
+    ap.add_argument("--mode", type=int, default=None,
+                    help="force scheduler mode of both render passes (0 per-tile, 1 persistent, 2 XCD split, 3 LPT, "
+                         "4 XCD-LPT, 5 LPT-head)")
+    ap.add_argument("--fwd-mode", type=int, default=None, help="force the forward render's scheduler mode")
+    ap.add_argument("--bwd-mode", type=int, default=None, help="force the backward render's scheduler mode")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-aerial", action="store_true")
     ap.add_argument("--no-dssim", action="store_true")
@@ -642,6 +646,12 @@ def main():
         log(f"autotune: fwd {tuned['fwd']} bwd {tuned['bwd']}")
     if args.mode is not None:
         tr.set_shapes(mode=args.mode)
+    if args.fwd_mode is not None or args.bwd_mode is not None:
+        if args.fwd_mode is not None:
+            tr.cfg.extra["fwd_mode"] = args.fwd_mode
+        if args.bwd_mode is not None:
+            tr.cfg.extra["bwd_mode"] = args.bwd_mode
+        tr.set_shapes()
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         tr.step()

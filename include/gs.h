@@ -99,6 +99,8 @@ typedef struct gs_bins {
                                   (longest processing time first); tile_cost NULL = per-tile */
 #define GS_SCHED_XCD_LPT 4     /* the XCD split, each chunk's tiles in decreasing estimated cost;
                                   tile_cost NULL = per-tile */
+#define GS_SCHED_LPT_HEAD 5    /* the heaviest eighth of the tiles first in decreasing estimated
+                                  cost, then the rest in index order; tile_cost NULL = per-tile */
 
 /* Launch shape of the two render kernels and the state of the persistent
  * scheduler (the single-GPU counterpart of section 3.2 "Iterative Workload
@@ -114,9 +116,11 @@ typedef struct gs_bins {
  * b-th: the greedy longest-processing-time-first rule for the makespan of
  * a queue of tasks on identical workers; the workspace holds the order. In
  * XCD-LPT mode it runs Algorithm 1 with 8 chunks as in the XCD split and
- * orders each chunk's tiles by decreasing tile_cost. */
+ * orders each chunk's tiles by decreasing tile_cost. LPT-head mode orders
+ * only the heaviest cost classes holding an eighth of the tiles, the rest
+ * following in index order (their neighbours share L2 lines). */
 typedef struct gs_sched {
-    int32_t mode;             /* GS_SCHED_PER_TILE, _PERSISTENT, _XCD_SPLIT, _LPT or _XCD_LPT */
+    int32_t mode;             /* GS_SCHED_PER_TILE, _PERSISTENT, _XCD_SPLIT, _LPT, _XCD_LPT or _LPT_HEAD */
     int32_t px_per_thread;    /* 1, 2 or 4: 256, 128 or 64 threads per 16x16 tile */
     int32_t chunk;            /* records staged in LDS per step: 32, 64, 128 or 256 */
     int32_t workers;          /* persistent workgroups (0 = as many as fit on the GPU at once) */

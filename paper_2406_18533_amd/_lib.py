@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libgs.so")
 GS_OK, GS_ERR_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 GS_F32, GS_F64 = 0, 1
 GS_SCHED_PER_TILE, GS_SCHED_PERSISTENT, GS_SCHED_XCD_SPLIT, GS_SCHED_LPT, GS_SCHED_XCD_LPT = 0, 1, 2, 3, 4
+GS_SCHED_LPT_HEAD = 5
 GS_REC = 12
 GS_MAX_VIEWS = 64
 

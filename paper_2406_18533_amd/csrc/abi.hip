@@ -226,7 +226,7 @@ static SchedWS sched_ws(int64_t total_tiles, int32_t q)
     w.partial = w.ct + al(8 * t);
     w.order = w.partial + al(8 * (t / 4096 + 8));
     w.bins = w.order + al(4 * t);
-    w.total = w.bins + al(4 * 2 * (size_t)LPT_SEGS * (size_t)LPT_BINS);
+    w.total = w.bins + al(4 * (2 * (size_t)LPT_SEGS * (size_t)LPT_BINS + (size_t)LPT_SEGS));
     return w;
 }
 
@@ -334,7 +334,7 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.S.bins = nullptr;
     if (!sc) return true;
     if (sc->mode != GS_SCHED_PER_TILE && sc->mode != GS_SCHED_PERSISTENT && sc->mode != GS_SCHED_XCD_SPLIT &&
-        sc->mode != GS_SCHED_LPT && sc->mode != GS_SCHED_XCD_LPT) {
+        sc->mode != GS_SCHED_LPT && sc->mode != GS_SCHED_XCD_LPT && sc->mode != GS_SCHED_LPT_HEAD) {
         why = "bad sched mode";
         return false;
     }
@@ -343,9 +343,9 @@ static bool sched_shape(const gs_sched *sc, int64_t total_tiles, LaunchShape &sh
     sh.mode = sc->mode;
     sh.px = sc->px_per_thread;
     sh.chunk = sc->chunk;
-    if ((sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_XCD_LPT) && !sc->tile_cost)
-        sh.mode = GS_SCHED_PER_TILE;   // no costs: index order
-    if (sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_XCD_LPT) {
+    const bool lpt = sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_XCD_LPT || sh.mode == GS_SCHED_LPT_HEAD;
+    if (lpt && !sc->tile_cost) sh.mode = GS_SCHED_PER_TILE;   // no costs: index order
+    if (lpt && sc->tile_cost) {
         if (!sc->workspace || sc->workspace_bytes < gs_sched_workspace_bytes(total_tiles, 8)) {
             why = "sched workspace too small";
             return false;
@@ -379,13 +379,16 @@ static hipError_t run_plan(const gs_sched *sc, const LaunchShape &sh, int32_t to
                            hipStream_t s)
 {
     if (sh.mode == GS_SCHED_LPT)
-        return launch_lpt_plan(sc->tile_cost, total_tiles, nullptr, 1, sh.S.bins, sh.S.order, s);
+        return launch_lpt_plan(sc->tile_cost, total_tiles, nullptr, 1, 0u, sh.S.bins, sh.S.order, s);
+    if (sh.mode == GS_SCHED_LPT_HEAD)   // the heaviest eighth of the tiles first, the rest in index order
+        return launch_lpt_plan(sc->tile_cost, total_tiles, nullptr, 1, (uint32_t)((total_tiles + 7) / 8), sh.S.bins,
+                               sh.S.order, s);
     SchedWS L = sched_ws(total_tiles, sh.S.queues);
     char *w = (char *)sc->workspace;
     hipError_t e = launch_plan(sc->tile_cost, total_tiles, sh.S.queues, (uint64_t *)(w + L.ct),
                                (uint64_t *)(w + L.partial), sh.S.dp, sh.S.cursor, dp_out, s);
     if (e != hipSuccess || sh.mode != GS_SCHED_XCD_LPT) return e;
-    return launch_lpt_plan(sc->tile_cost, total_tiles, sh.S.dp, 8, sh.S.bins, sh.S.order, s);
+    return launch_lpt_plan(sc->tile_cost, total_tiles, sh.S.dp, 8, 0u, sh.S.bins, sh.S.order, s);
 }
 
 gs_status gs_sched_plan(const gs_sched *sched, const gs_camera *cams_host, int32_t views, int32_t *dp_out, void *stream)

@@ -910,14 +910,20 @@ __global__ void __launch_bounds__(256) lpt_hist_kernel(const uint32_t *__restric
 }
 
 // Exclusive prefix of each segment's class counts, heaviest class first,
-// from the segment's first position (one block per segment).
+// from the segment's first position (one block per segment). With head > 0
+// only the heaviest classes that together hold at least `head` tiles keep
+// their order; the classes after them form one bucket (cstar[segment] = the
+// last ordered class), so the light tiles keep roughly their index order.
 __global__ void __launch_bounds__(256) lpt_scan_kernel(const uint32_t *__restrict__ hist, const int32_t *__restrict__ dp,
-                                                       uint32_t *__restrict__ cur)
+                                                       uint32_t *__restrict__ cur, int32_t *__restrict__ cstar,
+                                                       uint32_t head)
 {
     __shared__ uint32_t v[256];
+    __shared__ int cs;
     const int j = threadIdx.x, sg = blockIdx.x;
     const uint32_t hj = j < LPT_BINS ? hist[sg * LPT_BINS + j] : 0u;
     v[j] = hj;
+    if (j == 0) cs = LPT_BINS - 1;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
         uint32_t a = j >= o ? v[j - o] : 0u;
@@ -925,13 +931,18 @@ __global__ void __launch_bounds__(256) lpt_scan_kernel(const uint32_t *__restric
         v[j] += a;
         __syncthreads();
     }
+    if (head > 0u && j < LPT_BINS && v[j] >= head) atomicMin(&cs, j);
+    __syncthreads();
     const uint32_t base = dp ? (uint32_t)dp[sg] : 0u;
-    if (j < LPT_BINS) cur[sg * LPT_BINS + j] = base + v[j] - hj;
+    if (j < LPT_BINS && j <= cs) cur[sg * LPT_BINS + j] = base + v[j] - hj;
+    if (j < LPT_BINS && j == cs + 1) cur[sg * LPT_BINS + j] = base + v[cs];   // the merged light bucket
+    if (j == 0) cstar[sg] = cs;
 }
 
 __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t *__restrict__ cost, int32_t T_all,
                                                           const int32_t *__restrict__ dp, int nseg,
-                                                          uint32_t *__restrict__ cur, int32_t *__restrict__ order)
+                                                          uint32_t *__restrict__ cur, const int32_t *__restrict__ cstar,
+                                                          int32_t *__restrict__ order)
 {
     __shared__ uint32_t cnt[LPT_SEGS * LPT_BINS], base[LPT_SEGS * LPT_BINS];
     for (int j = threadIdx.x; j < nseg * LPT_BINS; j += 256) cnt[j] = 0u;
@@ -940,7 +951,8 @@ __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t *__rest
     int b = 0;
     uint32_t r = 0;
     if (t < T_all) {
-        b = lpt_seg(dp, nseg, t) * LPT_BINS + lpt_bin(cost[t]);
+        const int sg = lpt_seg(dp, nseg, t);
+        b = sg * LPT_BINS + min(lpt_bin(cost[t]), cstar[sg] + 1);
         r = atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
@@ -950,18 +962,20 @@ __global__ void __launch_bounds__(256) lpt_scatter_kernel(const uint32_t *__rest
     if (t < T_all) order[base[b] + r] = t;
 }
 
-hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, const int32_t *dp, int nseg, uint32_t *bins,
-                           int32_t *order, hipStream_t s)
+hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, const int32_t *dp, int nseg, uint32_t head,
+                           uint32_t *bins, int32_t *order, hipStream_t s)
 {
     if (T_all <= 0) return hipSuccess;
     if (nseg < 1 || nseg > LPT_SEGS || (nseg > 1 && !dp)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)((T_all + 255) / 256);
     const int64_t nb = (int64_t)nseg * LPT_BINS;
+    int32_t *cstar = (int32_t *)(bins + 2 * (int64_t)LPT_SEGS * LPT_BINS);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((2 * nb + 255) / 256)), dim3(256), 0, s, bins, 2 * nb, 0u);
     hipLaunchKernelGGL(lpt_hist_kernel, dim3(g), dim3(256), 0, s, cost, T_all, dp, nseg, bins);
     hipLaunchKernelGGL(lpt_scan_kernel, dim3((unsigned)nseg), dim3(256), 0, s, (const uint32_t *)bins,
-                       nseg > 1 ? dp : nullptr, bins + nb);
-    hipLaunchKernelGGL(lpt_scatter_kernel, dim3(g), dim3(256), 0, s, cost, T_all, dp, nseg, bins + nb, order);
+                       nseg > 1 ? dp : nullptr, bins + nb, cstar, head);
+    hipLaunchKernelGGL(lpt_scatter_kernel, dim3(g), dim3(256), 0, s, cost, T_all, dp, nseg, bins + nb,
+                       (const int32_t *)cstar, order);
     return hipGetLastError();
 }
 

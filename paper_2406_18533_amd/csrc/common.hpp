@@ -65,7 +65,8 @@ struct SchedState {
     int32_t *dp;       // [queues + 1] division points
     int32_t queues;    // multiple of 8
     int32_t *order;    // [total_tiles] tiles by decreasing estimated cost (LPT mode)
-    uint32_t *bins;    // [2 * LPT_SEGS * LPT_BINS] the LPT counting sort's histogram and cursors
+    uint32_t *bins;    // [2 * LPT_SEGS * LPT_BINS + LPT_SEGS] the LPT counting sort's histogram,
+                       // cursors and last ordered class per segment
 };
 
 // Cost classes of the LPT order: 4 per octave of the estimated cost (a class
@@ -73,8 +74,8 @@ struct SchedState {
 // segments sorted separately (the XCD chunks of Algorithm 1).
 constexpr int LPT_BINS = 136;
 constexpr int LPT_SEGS = 8;
-hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, const int32_t *dp, int nseg, uint32_t *bins,
-                           int32_t *order, hipStream_t s);
+hipError_t launch_lpt_plan(const uint32_t *cost, int32_t T_all, const int32_t *dp, int nseg, uint32_t head,
+                           uint32_t *bins, int32_t *order, hipStream_t s);
 
 // Resolved launch shape of the render kernels.
 struct LaunchShape {

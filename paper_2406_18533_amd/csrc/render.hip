@@ -767,7 +767,7 @@ hipError_t launch_render_fwd(const ViewTable &vt, const void *proj, int64_t n, c
     else if (sh.mode == GS_SCHED_XCD_SPLIT)                                                                  \
         hipLaunchKernelGGL((render_fwd_xcd<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
                            (const int32_t *)sh.S.dp);                                                        \
-    else if (sh.mode == GS_SCHED_LPT)                                                                        \
+    else if (sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_LPT_HEAD)                                        \
         hipLaunchKernelGGL((render_fwd_lpt<TT, P, C, ST>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,      \
                            (const int32_t *)sh.S.order);                                                     \
     else if (sh.mode == GS_SCHED_XCD_LPT)                                                                    \
@@ -811,7 +811,7 @@ hipError_t launch_render_bwd(const ViewTable &vt, const void *proj, int64_t n, c
     else if (sh.mode == GS_SCHED_XCD_SPLIT)                                                                  \
         hipLaunchKernelGGL((render_bwd_xcd<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,          \
                            (const int32_t *)sh.S.dp);                                                        \
-    else if (sh.mode == GS_SCHED_LPT)                                                                        \
+    else if (sh.mode == GS_SCHED_LPT || sh.mode == GS_SCHED_LPT_HEAD)                                        \
         hipLaunchKernelGGL((render_bwd_lpt<TT, P, C>), dim3(grid_tiles), dim3(256 / P), 0, s, vt, A,          \
                            (const int32_t *)sh.S.order);                                                     \
     else if (sh.mode == GS_SCHED_XCD_LPT)                                                                    \

@@ -142,7 +142,8 @@ class Sched:
         self.tile_cost = tile_cost
         self.workspace = None
         wsb = 0
-        if mode in (_lib.GS_SCHED_PERSISTENT, _lib.GS_SCHED_XCD_SPLIT, _lib.GS_SCHED_LPT, _lib.GS_SCHED_XCD_LPT):
+        if mode in (_lib.GS_SCHED_PERSISTENT, _lib.GS_SCHED_XCD_SPLIT, _lib.GS_SCHED_LPT, _lib.GS_SCHED_XCD_LPT,
+                    _lib.GS_SCHED_LPT_HEAD):
             assert cams is not None
             q = queues if mode == _lib.GS_SCHED_PERSISTENT else 8
             wsb = int(_lib.load().gs_sched_workspace_bytes(cams.total_tiles(), q))

@@ -289,13 +289,13 @@ def test_graph_replay_equals_eager_steps(lam, mode):
           f"{(graph.P - eager.P).norm().item() / moved:.2e} of the displacement", flush=True)
 
 
-@pytest.mark.parametrize("mode", ["persistent", "xcd_split", "lpt", "xcd_lpt"])
+@pytest.mark.parametrize("mode", ["persistent", "xcd_split", "lpt", "xcd_lpt", "lpt_head"])
 def test_cost_driven_scheduler_gradients_match_per_tile(mode):
     from paper_2406_18533_amd import _lib, train
     P, cams, tgt = _small_batch()
     a = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig(graph=False, mode=_lib.GS_SCHED_PER_TILE))
     m = {"persistent": _lib.GS_SCHED_PERSISTENT, "xcd_split": _lib.GS_SCHED_XCD_SPLIT, "lpt": _lib.GS_SCHED_LPT,
-         "xcd_lpt": _lib.GS_SCHED_XCD_LPT}[mode]
+         "xcd_lpt": _lib.GS_SCHED_XCD_LPT, "lpt_head": _lib.GS_SCHED_LPT_HEAD}[mode]
     b = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(),
                              train.TrainConfig(graph=False, mode=m, fwd_shape=(4, 128), bwd_shape=(2, 32), queues=16))
     b.step_eager()            # a cost history for the division points, then the parameters back

@@ -474,7 +474,9 @@ def test_image_identical_across_launch_shapes_and_schedulers():
                dict(mode=_lib.GS_SCHED_LPT, px_per_thread=4, chunk=64, tile_cost=ref["work_fwd"]),
                dict(mode=_lib.GS_SCHED_LPT, px_per_thread=1, chunk=32, tile_cost=skewed),
                dict(mode=_lib.GS_SCHED_XCD_LPT, px_per_thread=4, chunk=64, tile_cost=ref["work_fwd"]),
-               dict(mode=_lib.GS_SCHED_XCD_LPT, px_per_thread=2, chunk=128, tile_cost=skewed)]:
+               dict(mode=_lib.GS_SCHED_XCD_LPT, px_per_thread=2, chunk=128, tile_cost=skewed),
+               dict(mode=_lib.GS_SCHED_LPT_HEAD, px_per_thread=4, chunk=64, tile_cost=ref["work_fwd"]),
+               dict(mode=_lib.GS_SCHED_LPT_HEAD, px_per_thread=1, chunk=128, tile_cost=skewed)]:
         f = gp.forward(Pd, cams, BG, sched_kw=kw)
         assert torch.equal(f["rgb"], ref["rgb"]) and torch.equal(f["T"], ref["T"]), kw
         assert torch.equal(f["last"], ref["last"]), kw
@@ -527,6 +529,25 @@ def test_lpt_orders_are_permutations_by_decreasing_cost():
         part = order[dp[x]:dp[x + 1]]
         assert np.array_equal(np.sort(part), np.arange(dp[x], dp[x + 1]))
         assert decreasing(part)
+    assert torch.equal(f["rgb"], ref["rgb"])
+    # LPT-head: the heaviest classes that hold at least an eighth of the
+    # tiles first, by decreasing class; then every other tile (in whatever
+    # order the scatter's workgroups arrived). Costs sit mid-class
+    # (4 log2 c = k + 0.5 up to 0.02) so that the expected split is exact.
+    rng = np.random.default_rng(5)
+    k = np.minimum(rng.geometric(0.15, T) - 1, 40)
+    c = np.floor(2.0 ** ((k + 0.5) / 4 + 8)).astype(np.int64)
+    cls = 1 + np.floor(4 * np.log2(c))
+    assert np.all(np.abs(4 * np.log2(c) - np.round(4 * np.log2(c) - 0.5) - 0.5) < 0.05)
+    f = gp.forward(Pd, cams, BG, sched_kw=dict(mode=_lib.GS_SCHED_LPT_HEAD, px_per_thread=4, chunk=64,
+                                                tile_cost=torch.from_numpy(c.astype(np.int32)).cuda()))
+    _, order = _lpt_workspace(f["sched"], T)
+    assert np.array_equal(np.sort(order), np.arange(T))
+    cstar = np.sort(cls)[::-1][(T + 7) // 8 - 1]     # the lightest class kept in order
+    head = cls >= cstar
+    n_head = int(head.sum())
+    assert np.all(head[order[:n_head]]) and not np.any(head[order[n_head:]])
+    assert np.all(np.diff(cls[order[:n_head]]) <= 0)
     assert torch.equal(f["rgb"], ref["rgb"])
 
 

@@ -161,8 +161,12 @@ template <typename T> __device__ __forceinline__ ColTerms<T> col_terms(T pxc, T 
 
 // One (pixel, Gaussian) pair, evaluated without branches: row offset dy,
 // falloff G, opacity times falloff og, alpha = min(0.99, og), and whether
-// the pair counts (centre inside the radius circle, exponent <= 0,
-// alpha >= 1/255). The exponent is qx + dy (nb dx + nc dy) in log2 units.
+// the pair counts (centre inside the radius circle, alpha >= 1/255). The
+// exponent is qx + dy (nb dx + nc dy) in log2 units. Its sign test (skip a
+// pair with a positive exponent) is left out: the conic is positive
+// definite, so the exponent is positive only by rounding, within a few ulps
+// of the sum of its terms' magnitudes, where G rounds to 1 as it does at
+// the centre.
 // Invalid lanes may hold inf or NaN in G/og/alpha; callers select on `ok`,
 // never multiply by it. The forward and backward kernels both call this, so
 // their decisions agree bit for bit.
@@ -176,7 +180,7 @@ __device__ __forceinline__ bool eval_alpha(const ColTerms<T> &c, T pyc, T v, T r
     G = exp2_t(p2);
     og = o * G;
     alpha = fmin(og, K<T>::alpha_max);
-    return (d2 <= r2) & (p2 <= T(0)) & (alpha >= K<T>::alpha_min);
+    return (d2 <= r2) & (alpha >= K<T>::alpha_min);
 }
 
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }

@@ -23,8 +23,6 @@
 //    (division points) computed from per-tile costs; queue q belongs to XCD
 //    q div (Q/8). A workgroup drains its home queue, then steals from the
 //    other queues of its XCD, then from the other XCDs.
-#include <type_traits>
-
 #include "common.hpp"
 
 namespace gs {
@@ -65,16 +63,26 @@ template <typename T> struct BwdArgs {
 // BWD: the backward also needs the raw conic and the Gaussian index; the
 // forward leaves them out, which keeps its LDS per workgroup small enough
 // for eight workgroups of one wavefront per SIMD.
+// The fourth slot of b, c and d carries an integer's bits, so one 16-byte
+// load per vector brings every per-record value.
 template <typename T, int CHUNK, bool BWD> struct Stage {
     V4<T> a[CHUNK];               // u, v, r^2, opacity
-    V4<T> b[BWD ? CHUNK : 1];     // conic a, b, c, -
-    V4<T> c[CHUNK];               // r, g, b, -
-    V4<T> d[CHUNK];               // scaled conic na, nb, nc (see scaled_conic), -
-    uint32_t id[BWD ? CHUNK : 1];
-    uint32_t pos[CHUNK];   // position of the record in the tile's list
-    uint32_t band[CHUNK];  // bit k: the record may touch pixel rows 4k..4k+3 of the tile
+    V4<T> b[BWD ? CHUNK : 1];     // conic a, b, c, Gaussian index
+    V4<T> c[CHUNK];               // r, g, b, 1 + position of the record in the tile's list
+    V4<T> d[CHUNK];               // scaled conic na, nb, nc (see scaled_conic), bands
+                                  // (bit k: the record may touch pixel rows 4k..4k+3 of the tile)
     uint32_t wcnt[4];
 };
+
+__device__ __forceinline__ float u32_bits(uint32_t x, float) { return __uint_as_float(x); }
+__device__ __forceinline__ double u32_bits(uint32_t x, double) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ uint32_t bits_u32(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t bits_u32(double v) { return (uint32_t)__double_as_longlong(v); }
+// the integer carried in a staged vector's fourth slot, read as a wave-uniform value
+template <typename T> __device__ __forceinline__ uint32_t staged_u32(T v)
+{
+    return __builtin_amdgcn_readfirstlane(bits_u32(v));
+}
 
 // Per-record constants of the culling tests below.
 template <typename T> struct CullRec {
@@ -221,12 +229,9 @@ __device__ __forceinline__ int commit_records(Stage<T, CHUNK, BWD> &st, const Fe
             T na, nb, nc;
             scaled_conic(sb.x, sb.y, sb.z, na, nb, nc);
             st.a[slot] = sa;
-            if constexpr (BWD) st.b[slot] = sb;
-            st.c[slot] = sc;
-            st.d[slot] = V4<T>{na, nb, nc, T(0)};
-            if constexpr (BWD) st.id[slot] = f.id[rr];
-            st.pos[slot] = f.pos0 + (uint32_t)q;
-            st.band[slot] = bands;
+            if constexpr (BWD) st.b[slot] = V4<T>{sb.x, sb.y, sb.z, u32_bits(f.id[rr], T(0))};
+            st.c[slot] = V4<T>{sc.x, sc.y, sc.z, u32_bits(f.pos0 + (uint32_t)q + 1u, T(0))};
+            st.d[slot] = V4<T>{na, nb, nc, u32_bits(bands, T(0))};
         }
     }
     return kept;
@@ -282,8 +287,8 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         if (live_bands == 0) kept = 0;            // this wavefront's pixels are all finished
         for (int q = 0; q < kept; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
-            uint32_t bm = (__builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id) & live_bands;   // wave-uniform
-            uint32_t pos1 = st.pos[q] + 1;
+            uint32_t bm = (staged_u32(rd.w) >> wave_id) & live_bands;   // wave-uniform
+            uint32_t pos1 = staged_u32(rc.w);
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             for (int j = 0; j < PX; j++) {
                 if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
@@ -442,10 +447,10 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, (int64_t)s + lo2, (int)(lo - lo2), (uint32_t)lo2);
         }
         for (int q = kept - 1; q >= 0; q--) {
-            uint32_t k = __builtin_amdgcn_readfirstlane(st.pos[q]);                  // wave-uniform
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
-            const uint32_t act = (uint32_t)__ballot(k < Lv);                          // k < largest last of band j
-            uint32_t bm = (__builtin_amdgcn_readfirstlane(st.band[q]) >> wave_id) & act;
+            const uint32_t k1 = staged_u32(rc.w);                 // 1 + the record's position (wave-uniform)
+            const uint32_t act = (uint32_t)__ballot(k1 <= Lv);    // the position is below the largest last of band j
+            uint32_t bm = (staged_u32(rd.w) >> wave_id) & act;
             // dL/d(exponent) moments over this thread's pixels: they share the column
             // (one dx), so the position and conic sums factor through
             // D0 = sum d, D1 = sum d dy, D2 = sum d dy^2 (d = dL/d exponent)
@@ -454,44 +459,37 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             bool any = false;
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             const T dx = col.dx;
-            // The pairs of this record over the thread's pixels. Only a record
-            // whose opacity exceeds 0.99 can reach the alpha clamp (alpha <=
-            // opacity), so the clamp's zero gradient is tested only for those
-            // (a wave-uniform choice between two copies of the loop).
-            auto pairs = [&](auto clamp) {
-                for (int j = 0; j < PX; j++) {
-                    if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
-                    T dy, G, og, alpha;
-                    bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
-                    if (ok && k < L[j]) {   // lanes whose pixel blended this Gaussian
-                        any = true;
-                        T Tk = Tr[j] * rcp_t(T(1) - alpha);   // transmittance in front of this Gaussian
-                        T w = alpha * Tk;
-                        T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
-                        acc[6] = fma(w, gx, acc[6]);
-                        acc[7] = fma(w, gy, acc[7]);
-                        acc[8] = fma(w, gz, acc[8]);
-                        T cg = fma(rc.x, gx, fma(rc.y, gy, rc.z * gz));
-                        T diff = cg - Sg[j];
-                        T dalpha = diff * Tk;
-                        Sg[j] = fma(alpha, diff, Sg[j]);      // alpha c + (1 - alpha) S
-                        Tr[j] = Tk;
-                        T live = dalpha;
-                        if constexpr (decltype(clamp)::value)
-                            live = og <= K<T>::alpha_max ? dalpha : T(0);   // the 0.99 clamp has no gradient
-                        T dpow = live * og;
-                        T hy = dpow * dy;
-                        acc[5] = fma(live, G, acc[5]);
-                        D0 += dpow;
-                        D1 += hy;
-                        D2 = fma(hy, dy, D2);
-                    }
+            // The pairs of this record over the thread's pixels. The 0.99 clamp
+            // of alpha has no gradient; it is tested in every pair (one loop
+            // for every record: a second copy for records that cannot reach
+            // the clamp made the compiler copy the loop-carried T and S at
+            // every record).
+            for (int j = 0; j < PX; j++) {
+                if (!((bm >> (j * (NT / 64))) & 1u)) continue;     // wave-uniform band skip
+                T dy, G, og, alpha;
+                bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
+                if (ok && k1 <= L[j]) {   // lanes whose pixel blended this Gaussian
+                    any = true;
+                    T Tk = Tr[j] * rcp_t(T(1) - alpha);   // transmittance in front of this Gaussian
+                    T w = alpha * Tk;
+                    T gx = gr[j][0], gy = gr[j][1], gz = gr[j][2];
+                    acc[6] = fma(w, gx, acc[6]);
+                    acc[7] = fma(w, gy, acc[7]);
+                    acc[8] = fma(w, gz, acc[8]);
+                    T cg = fma(rc.x, gx, fma(rc.y, gy, rc.z * gz));
+                    T diff = cg - Sg[j];
+                    T dalpha = diff * Tk;
+                    Sg[j] = fma(alpha, diff, Sg[j]);      // alpha c + (1 - alpha) S
+                    Tr[j] = Tk;
+                    T live = og <= K<T>::alpha_max ? dalpha : T(0);   // the clamped pair passes no gradient
+                    T dpow = live * og;
+                    T hy = dpow * dy;
+                    acc[5] = fma(live, G, acc[5]);
+                    D0 += dpow;
+                    D1 += hy;
+                    D2 = fma(hy, dy, D2);
                 }
-            };
-            if (__builtin_amdgcn_readfirstlane(__float_as_uint((float)ra.w)) > __float_as_uint((float)K<T>::alpha_max))
-                pairs(std::true_type{});
-            else
-                pairs(std::false_type{});
+            }
             // d/du, d/dv through (dx, dy) and d/d(a, b, c) (times -1/2, -1, -1/2 after the reduction)
             T hx = dx * D0;
             acc[0] = fma(rb.x, hx, rb.y * D1);
@@ -500,7 +498,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
             acc[3] = dx * D1;
             acc[4] = D2;
             if (__ballot(any) == 0) continue;
-            wave_sum9_atomic(acc, A.dproj + (vbase + st.id[q]) * REC, sc, T(1));
+            wave_sum9_atomic(acc, A.dproj + (vbase + staged_u32(rb.w)) * REC, sc, T(1));
         }
     }
 }

@@ -288,7 +288,7 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         for (int q = 0; q < kept; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
             uint32_t bm = (staged_u32(rd.w) >> wave_id) & live_bands;   // wave-uniform
-            uint32_t pos1 = staged_u32(rc.w);
+            uint32_t pos1 = bits_u32(rc.w);
             ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
             for (int j = 0; j < PX; j++) {
                 if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
@@ -312,7 +312,7 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
                     }
                 }
             }
-            if ((q & 3) == 3) {   // drop finished bands; leave once every pixel of the wavefront is finished
+            if ((q & 7) == 7) {   // drop finished bands; leave once every pixel of the wavefront is finished
                 live_bands = 0;
                 for (int j = 0; j < PX; j++)
                     live_bands |= (__ballot(Tr[j] > T(0)) != 0 ? 1u : 0u) << (j * (NT / 64));
@@ -448,7 +448,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         }
         for (int q = kept - 1; q >= 0; q--) {
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
-            const uint32_t k1 = staged_u32(rc.w);                 // 1 + the record's position (wave-uniform)
+            const uint32_t k1 = bits_u32(rc.w);                   // 1 + the record's position
             const uint32_t act = (uint32_t)__ballot(k1 <= Lv);    // the position is below the largest last of band j
             uint32_t bm = (staged_u32(rd.w) >> wave_id) & act;
             // dL/d(exponent) moments over this thread's pixels: they share the column

@@ -309,3 +309,46 @@ def test_error_bound_covers_an_fp32_evaluation():
             assert (err[ok] <= out["bound"][ok] + 2.4e-7).all(), trial
             worst = max(worst, float((err[ok] / (out["bound"][ok] + 2.4e-7)).max()))
     assert worst > 0.05             # and is not loose by orders of magnitude (measured 0.19)
+
+
+def test_exponent_positive_only_within_rounding_of_zero():
+    """The render kernels leave out the exponent-sign test (skip a pair whose
+    exponent is positive). With a positive definite conic the exponent they
+    form in FP32 -- na dx^2 + dy (nb dx + nc dy), (na, nb, nc) the conic
+    scaled by -log2(e) (1/2, 1, 1/2), two fused multiply-adds -- is positive
+    only by rounding. Thin conics (eigenvalue ratio down to 3e-8) laid along
+    the pixel grid, centres near a pixel centre: wherever that FP32 value is
+    positive, the exact exponent is within 1e-6 S of zero (S = |qa| + |qb| +
+    |qc|), the band in which the oracle takes either branch of its own sign
+    test."""
+    f32 = np.float32
+
+    def fma32(a, b, c):   # one rounding: the FP64 product of two FP32 values is exact
+        return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(f32)
+
+    l2e = f32(1.4426950408889634)
+    half_l2e = f32(-0.5) * l2e
+    rng = np.random.default_rng(7)
+    ys, xs = np.mgrid[100:141, 100:141]
+    pxc, pyc = xs.astype(f32) + f32(0.5), ys.astype(f32) + f32(0.5)
+    positive, worst = 0, 0.0
+    for _ in range(1500):
+        k, eps = 10.0 ** rng.uniform(-2, 2), 10.0 ** rng.uniform(-7.5, -3)
+        th = rng.choice([0.0, math.pi / 4, math.pi / 2, 3 * math.pi / 4]) + rng.normal(0, 1e-4)
+        cth, sth = math.cos(th), math.sin(th)
+        a, b, c = (f32(k * (cth * cth + eps * sth * sth)), f32(-k * (1 - eps) * cth * sth),
+                   f32(k * (sth * sth + eps * cth * cth)))
+        assert float(a) * float(c) - float(b) * float(b) > 0          # positive definite as stored
+        u, v = f32(120.5 + rng.normal(0, 1e-3)), f32(120.5 + rng.normal(0, 1e-3))
+        na, nb, nc = half_l2e * a, -l2e * b, half_l2e * c
+        dx, dy = pxc - u, pyc - v
+        p2 = fma32(dy, fma32(np.full_like(dy, nc), dy, nb * dx), (na * dx) * dx)
+        dxe, dye = dx.astype(np.float64), dy.astype(np.float64)
+        qa, qb, qc = 0.5 * float(a) * dxe * dxe, float(b) * dxe * dye, 0.5 * float(c) * dye * dye
+        power, S = -(qa + qb + qc), np.abs(qa) + np.abs(qb) + np.abs(qc)
+        m = p2 > 0
+        if m.any():
+            positive += int(m.sum())
+            worst = max(worst, float((np.abs(power[m]) / S[m]).max()))
+    assert positive > 20                     # the FP32 form does go positive (measured: 68 pixels)
+    assert worst <= 1e-6, worst              # measured 7e-8, about 1.2 unit roundoffs

@@ -182,8 +182,16 @@ __device__ __forceinline__ void fetch_records(Fetched<T, CHUNK, NT> &f, const T 
 // returns how many were kept. A band is exactly one wavefront's pixels in
 // every launch shape, so the render loops skip a band with a wave-uniform
 // branch.
+// Bands a commit may keep: bit k of `allow`, and only for records whose
+// 1 + position is at most last[k] (the backward's largest last of band k).
+struct BandLimit {
+    uint32_t allow;
+    uint32_t last[4];
+};
+
 template <typename T, int CHUNK, int NT, bool BWD>
-__device__ __forceinline__ int commit_records(Stage<T, CHUNK, BWD> &st, const Fetched<T, CHUNK, NT> &f, T bx0, T by0)
+__device__ __forceinline__ int commit_records(Stage<T, CHUNK, BWD> &st, const Fetched<T, CHUNK, NT> &f, T bx0, T by0,
+                                              const BandLimit &lim)
 {
     constexpr int NW = NT / 64;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -202,8 +210,10 @@ __device__ __forceinline__ int commit_records(Stage<T, CHUNK, BWD> &st, const Fe
             sc = V4<T>{r1.z, r1.w, r2.x, T(0)};
             if (sa.w >= K<T>::alpha_min) {   // alpha <= opacity everywhere
                 CullRec<T> k = cull_rec(sa.x, sa.y, sa.z, sb.x, sb.y, sb.z, sa.w);
+                const uint32_t k1 = f.pos0 + (uint32_t)q + 1u;
                 for (int band = 0; band < 4; band++)
-                    if (!box_culls(k, bx0, bx0 + T(15), by0 + T(4 * band), by0 + T(4 * band + 3)))
+                    if (((lim.allow >> band) & 1u) && k1 <= lim.last[band] &&
+                        !box_culls(k, bx0, bx0 + T(15), by0 + T(4 * band), by0 + T(4 * band + 3)))
                         bands |= 1u << band;
             }
         }
@@ -275,15 +285,17 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
     if (s < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, s, (int)min((uint32_t)CHUNK, e - s), 0u);
     for (uint32_t base = s; base < e; base += CHUNK) {
         __syncthreads();
-        int kept = commit_records<T, CHUNK, NT>(st, fr, bx0, by0);
-        int cnt = fr.cnt;
-        __syncthreads();
-        uint32_t nb = base + CHUNK;
-        if (nb < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, nb, (int)min((uint32_t)CHUNK, e - nb), nb - s);
         // bit j (NT/64): slot j of this wavefront still has an unfinished pixel
         uint32_t live_bands = 0;
         for (int j = 0; j < PX; j++)
             live_bands |= (__ballot(Tr[j] > T(0)) != 0 ? 1u : 0u) << (j * (NT / 64));
+        // one wavefront per tile: its finished bands need no staged records
+        const BandLimit lim{NT == 64 ? live_bands : 0xfu, {~0u, ~0u, ~0u, ~0u}};
+        int kept = commit_records<T, CHUNK, NT>(st, fr, bx0, by0, lim);
+        int cnt = fr.cnt;
+        __syncthreads();
+        uint32_t nb = base + CHUNK;
+        if (nb < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, nb, (int)min((uint32_t)CHUNK, e - nb), nb - s);
         if (live_bands == 0) kept = 0;            // this wavefront's pixels are all finished
         for (int q = 0; q < kept; q++) {
             V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
@@ -437,9 +449,13 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         int64_t lo0 = (int64_t)Lmax - CHUNK > 0 ? (int64_t)Lmax - CHUNK : 0;
         fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, (int64_t)s + lo0, (int)(Lmax - lo0), (uint32_t)lo0);
     }
+    // one wavefront per tile: a band takes no record past its largest last
+    BandLimit lim{0xfu, {~0u, ~0u, ~0u, ~0u}};
+    if (NT == 64)
+        for (int j = 0; j < PX && j < 4; j++) lim.last[j] = __builtin_amdgcn_readlane(Lv, j);
     for (int64_t hi = Lmax; hi > 0; hi -= CHUNK) {
         __syncthreads();
-        int kept = commit_records<T, CHUNK, NT>(st, fr, bx0, by0);
+        int kept = commit_records<T, CHUNK, NT>(st, fr, bx0, by0, lim);
         __syncthreads();
         int64_t lo = hi - CHUNK > 0 ? hi - CHUNK : 0;
         if (lo > 0) {
@@ -449,8 +465,9 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
         for (int q = kept - 1; q >= 0; q--) {
             V4<T> ra = st.a[q], rb = st.b[q], rc = st.c[q], rd = st.d[q];
             const uint32_t k1 = bits_u32(rc.w);                   // 1 + the record's position
-            const uint32_t act = (uint32_t)__ballot(k1 <= Lv);    // the position is below the largest last of band j
-            uint32_t bm = (staged_u32(rd.w) >> wave_id) & act;
+            uint32_t bm = staged_u32(rd.w) >> wave_id;
+            if constexpr (NT != 64)   // (one wavefront per tile: the commit already dropped such bands)
+                bm &= (uint32_t)__ballot(k1 <= Lv);               // the position is below the largest last of band j
             // dL/d(exponent) moments over this thread's pixels: they share the column
             // (one dx), so the position and conic sums factor through
             // D0 = sum d, D1 = sum d dy, D2 = sum d dy^2 (d = dL/d exponent)

@@ -154,7 +154,7 @@ template <typename T> __device__ __forceinline__ ColTerms<T> col_terms(T pxc, T 
     ColTerms<T> c;
     c.dx = pxc - u;
     c.dx2 = c.dx * c.dx;
-    c.qx = (na * c.dx) * c.dx;
+    c.qx = na * c.dx2;
     c.nbdx = nb * c.dx;
     return c;
 }

@@ -297,39 +297,42 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
         uint32_t nb = base + CHUNK;
         if (nb < e) fetch_records<T, CHUNK, NT>(fr, A.proj, vbase, A.ids, nb, (int)min((uint32_t)CHUNK, e - nb), nb - s);
         if (live_bands == 0) kept = 0;            // this wavefront's pixels are all finished
-        for (int q = 0; q < kept; q++) {
-            V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
-            uint32_t bm = (staged_u32(rd.w) >> wave_id) & live_bands;   // wave-uniform
-            uint32_t pos1 = bits_u32(rc.w);
-            ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
-            for (int j = 0; j < PX; j++) {
-                if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
-                    T dy, G, og, alpha;
-                    bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
-                    // A finished pixel holds -T: then Tn < 0 fails the blend
-                    // test below and -|T| leaves it unchanged, so `ok` needs
-                    // no separate live test.
-                    T Tj = Tr[j];
-                    T Tn = fma(-alpha, Tj, Tj);                 // T (1 - alpha)
-                    bool bl = ok && (Tn >= K<T>::t_min);   // (Tn is finite wherever ok holds)
-                    T w = bl ? alpha * Tj : T(0);
-                    C[j][0] = fma(rc.x, w, C[j][0]);
-                    C[j][1] = fma(rc.y, w, C[j][1]);
-                    C[j][2] = fma(rc.z, w, C[j][2]);
-                    Tr[j] = bl ? Tn : (ok ? -fabs(Tj) : Tj);   // stop: mark finished
-                    lastp[j] = bl ? pos1 : lastp[j];
-                    if (STATS) {
-                        n_eval += Tj > T(0) ? 1u : 0u;
-                        n_blend += bl ? 1u : 0u;
+        // records in groups of eight; between groups, drop finished bands and
+        // leave once every pixel of the wavefront is finished
+        for (int q0 = 0; q0 < kept; q0 += 8) {
+            const int q1 = min(q0 + 8, kept);
+            for (int q = q0; q < q1; q++) {
+                V4<T> ra = st.a[q], rd = st.d[q], rc = st.c[q];
+                uint32_t bm = (staged_u32(rd.w) >> wave_id) & live_bands;   // wave-uniform
+                uint32_t pos1 = bits_u32(rc.w);
+                ColTerms<T> col = col_terms(pxc, ra.x, rd.x, rd.y);
+                for (int j = 0; j < PX; j++) {
+                    if ((bm >> (j * (NT / 64))) & 1u) {   // wave-uniform: the record can touch this band
+                        T dy, G, og, alpha;
+                        bool ok = eval_alpha(col, pyc[j], ra.y, ra.z, rd.z, ra.w, dy, G, og, alpha);
+                        // A finished pixel holds -T: then Tn < 0 fails the blend
+                        // test below and -|T| leaves it unchanged, so `ok` needs
+                        // no separate live test.
+                        T Tj = Tr[j];
+                        T Tn = fma(-alpha, Tj, Tj);                 // T (1 - alpha)
+                        bool bl = ok && (Tn >= K<T>::t_min);   // (Tn is finite wherever ok holds)
+                        T w = bl ? alpha * Tj : T(0);
+                        C[j][0] = fma(rc.x, w, C[j][0]);
+                        C[j][1] = fma(rc.y, w, C[j][1]);
+                        C[j][2] = fma(rc.z, w, C[j][2]);
+                        Tr[j] = bl ? Tn : (ok ? -fabs(Tj) : Tj);   // stop: mark finished
+                        lastp[j] = bl ? pos1 : lastp[j];
+                        if (STATS) {
+                            n_eval += Tj > T(0) ? 1u : 0u;
+                            n_blend += bl ? 1u : 0u;
+                        }
                     }
                 }
             }
-            if ((q & 7) == 7) {   // drop finished bands; leave once every pixel of the wavefront is finished
-                live_bands = 0;
-                for (int j = 0; j < PX; j++)
-                    live_bands |= (__ballot(Tr[j] > T(0)) != 0 ? 1u : 0u) << (j * (NT / 64));
-                if (live_bands == 0) break;
-            }
+            live_bands = 0;
+            for (int j = 0; j < PX; j++)
+                live_bands |= (__ballot(Tr[j] > T(0)) != 0 ? 1u : 0u) << (j * (NT / 64));
+            if (live_bands == 0) break;
         }
         bool alldone = true;
         for (int j = 0; j < PX; j++) alldone &= Tr[j] < T(0);

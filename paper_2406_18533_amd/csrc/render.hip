@@ -253,8 +253,8 @@ __device__ void fwd_tile(int32_t g, const ViewTable &vt, const FwdArgs<T> &A, St
                          uint32_t *s_red)
 {
     uint32_t n_eval = 0, n_blend = 0;
-    const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NT = 256 / PX;
+    const int wave_id = NT == 64 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int v = view_of_tile(vt, g);
     int local = g - vt.tile_base[v];
     int TX = vt.tiles_x[v];
@@ -406,7 +406,7 @@ __device__ void bwd_tile(int32_t g, const ViewTable &vt, const BwdArgs<T> &A, St
     int TX = vt.tiles_x[v];
     int tx = local % TX, ty = local / TX;
     int W = vt.width[v], H = vt.height[v];
-    const int wave_id = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave_id = NT == 64 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const T pxc = (T)(tx * TILE + (threadIdx.x & 15)) + T(0.5);   // one column per thread
     // Sg: the colour composited behind the current Gaussian, dotted with the
     // pixel's colour gradient (only that product enters the gradients)

@@ -18,7 +18,9 @@ stream.
 """
 from __future__ import annotations
 
+import json
 import math
+import time
 from dataclasses import dataclass, field
 
 import torch
@@ -45,6 +47,25 @@ class TrainConfig:
     fused_loss: bool = True         # L1 loss in the render forward's output stage (gs_render_fwd_l1)
     ssim_lambda: float = 0.0        # > 0: loss (1 - lambda) L1 + lambda (1 - SSIM) (gs_loss_l1_dssim)
     extra: dict = field(default_factory=dict)
+
+
+class StepLog:
+    """Per-step training metrics as JSON lines appended to `path`: the
+    optimizer step count, the batch loss, milliseconds per step and views
+    per second since the previous record, overflow re-runs so far and the
+    number of Gaussians."""
+
+    def __init__(self, path: str, every: int = 1):
+        assert every >= 1
+        self.path, self.every = path, every
+
+    def write(self, tr, steps: int, seconds: float) -> dict:
+        rec = {"step": int(tr.step_dev.item()), "loss": tr.loss(), "ms_per_step": seconds * 1e3 / max(steps, 1),
+               "views_per_s": tr.V * steps / seconds if seconds > 0 else None, "overflow_redos": int(tr.overflows),
+               "gaussians": int(tr.n)}
+        with open(self.path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+        return rec
 
 
 class BatchedTrainer:
@@ -271,6 +292,21 @@ class BatchedTrainer:
 
     def loss(self) -> float:
         return float(self.loss_buf.loss.item())
+
+    def train(self, steps: int, log: "StepLog | None" = None) -> None:
+        """Runs `steps` steps, each followed by the overflow check (one small
+        device-to-host read); with a StepLog, appends a record every
+        log.every steps (timed from the previous record, after a device
+        synchronisation)."""
+        t0, done = time.perf_counter(), 0
+        for k in range(1, steps + 1):
+            self.step()
+            self.check_overflow()
+            if log is not None and k % log.every == 0:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                log.write(self, k - done, t - t0)
+                t0, done = t, k
 
     # -- checkpoint / resume --------------------------------------------------------------------
     def state_dict(self) -> dict:

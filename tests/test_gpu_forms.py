@@ -373,6 +373,21 @@ def test_server_result_alone_equals_result_in_the_mix():
     assert np.array_equal(again[0], keep)
 
 
+def test_train_loop_writes_a_step_log(tmp_path):
+    """BatchedTrainer.train with a StepLog: one JSON record every `every`
+    steps, carrying the optimizer's step count and the batch loss."""
+    import json
+    from paper_2406_18533_amd import train
+    P, cams, tgt = _small_batch()
+    tr = train.BatchedTrainer(P.cuda(), cams, tgt.cuda(), train.TrainConfig())
+    path = str(tmp_path / "steps.jsonl")
+    tr.train(6, train.StepLog(path, every=3))
+    recs = [json.loads(s) for s in open(path).read().splitlines()]
+    assert [r["step"] for r in recs] == [3, 6]
+    assert all(r["loss"] > 0 and r["views_per_s"] > 0 for r in recs)
+    assert recs[1]["loss"] == tr.loss()
+
+
 def test_checkpoint_resume_continues_the_trajectory(tmp_path):
     """50 steps, save, load into a fresh trainer, 50 more == 100 steps
     straight. The saved state round-trips exactly; the two continuations then

@@ -193,6 +193,41 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
+// ------------------------------------------------------------------ addressing
+// Element at a 32-bit byte offset from a wave-uniform base (the base MUST be
+// the same in every active lane: it is taken from the first one): the base pointer
+// (a row or a view's start) stays in scalar registers and the per-lane offset
+// is one 32-bit register, so a load or store needs no per-lane 64-bit address
+// arithmetic. The base goes through readfirstlane so that the compiler keeps
+// it scalar instead of folding a row offset into the per-lane address, and
+// the access is made in the global address space.
+#define GS_GLOBAL __attribute__((address_space(1)))
+template <typename U> __device__ __forceinline__ uint64_t uniform_addr(const U *p)
+{
+    uint64_t a = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename U> __device__ __forceinline__ U load_at(const U *base, uint32_t boff)
+{
+    return *(const GS_GLOBAL U *)((const GS_GLOBAL char *)uniform_addr(base) + boff);
+}
+template <typename U> __device__ __forceinline__ void store_at(U *base, uint32_t boff, U v)
+{
+    *(GS_GLOBAL U *)((GS_GLOBAL char *)uniform_addr(base) + boff) = v;
+}
+// four values in one aligned access (a builtin vector type: the HIP vector
+// classes' operators take no address-space-qualified object)
+template <typename T> using quad_t = T __attribute__((ext_vector_type(4)));
+template <typename T> __device__ __forceinline__ void store4_at(T *base, uint32_t boff, T x, T y, T z, T w)
+{
+    store_at(reinterpret_cast<quad_t<T> *>(base), boff, quad_t<T>{x, y, z, w});
+}
+template <typename T> __device__ __forceinline__ quad_t<T> load4_at(const T *base, uint32_t boff)
+{
+    return load_at(reinterpret_cast<const quad_t<T> *>(base), boff);
+}
+
 template <int CTRL, int ROW_MASK> __device__ __forceinline__ float dpp_move(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
@@ -245,7 +280,8 @@ __device__ __forceinline__ float fold16(float a, float b)
 // times a factor, with two global atomic instructions: v[0..7] go through a
 // transposed reduction (permlane32 and permlane16 swaps, a swap of row
 // halves, a three-step row scan) that leaves component sum9_comp(lane) in
-// every lane l with l % 8 == 7; v[8] goes through a plain DPP reduction.
+// every lane l with l % 8 == 7; v[8] goes through a plain DPP reduction and
+// lane 6 adds it.
 // sc is the factor for the component of the calling lane, sc8 the one of v[8].
 __device__ __forceinline__ int sum9_comp(int lane)
 {
@@ -270,8 +306,13 @@ __device__ __forceinline__ void wave_sum9_atomic(const float (&v)[9], float *dst
     r += dpp_move<0x112, 0xf>(r);                   // row_shr:2
     r += dpp_move<0x114, 0xf>(r);                   // row_shr:4: lane 8k+7 holds its 8 lanes' sum
     float s8 = wave_sum(v[8]);
-    if ((lane & 7) == 7) unsafeAtomicAdd(dst + sum9_comp(lane), r * sc);
-    if (lane == 0) unsafeAtomicAdd(dst + 8, s8 * sc8);
+    // one atomic instruction for all nine: lane 6 adds v[8] (a lane-dependent
+    // address, so the compiler does not rewrite it as a wave-wide atomic)
+    const bool l8 = lane == 6;
+    const float val = l8 ? s8 * sc8 : r * sc;
+    const uint32_t boff = 4u * (uint32_t)(l8 ? 8 : sum9_comp(lane));
+    if ((lane & 7) == 7 || l8)
+        __builtin_amdgcn_global_atomic_fadd_f32((GS_GLOBAL float *)((GS_GLOBAL char *)uniform_addr(dst) + boff), val);
 }
 
 // FP64: lane c (c < 9) adds component c, times sc (sc8 unused).
@@ -288,41 +329,6 @@ __device__ __forceinline__ void wave_sum9_atomic(const double (&v)[9], double *d
 
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
-
-// ------------------------------------------------------------------ addressing
-// Element at a 32-bit byte offset from a wave-uniform base (the base MUST be
-// the same in every active lane: it is taken from the first one): the base pointer
-// (a row or a view's start) stays in scalar registers and the per-lane offset
-// is one 32-bit register, so a load or store needs no per-lane 64-bit address
-// arithmetic. The base goes through readfirstlane so that the compiler keeps
-// it scalar instead of folding a row offset into the per-lane address, and
-// the access is made in the global address space.
-#define GS_GLOBAL __attribute__((address_space(1)))
-template <typename U> __device__ __forceinline__ uint64_t uniform_addr(const U *p)
-{
-    uint64_t a = reinterpret_cast<uint64_t>(p);
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-template <typename U> __device__ __forceinline__ U load_at(const U *base, uint32_t boff)
-{
-    return *(const GS_GLOBAL U *)((const GS_GLOBAL char *)uniform_addr(base) + boff);
-}
-template <typename U> __device__ __forceinline__ void store_at(U *base, uint32_t boff, U v)
-{
-    *(GS_GLOBAL U *)((GS_GLOBAL char *)uniform_addr(base) + boff) = v;
-}
-// four values in one aligned access (a builtin vector type: the HIP vector
-// classes' operators take no address-space-qualified object)
-template <typename T> using quad_t = T __attribute__((ext_vector_type(4)));
-template <typename T> __device__ __forceinline__ void store4_at(T *base, uint32_t boff, T x, T y, T z, T w)
-{
-    store_at(reinterpret_cast<quad_t<T> *>(base), boff, quad_t<T>{x, y, z, w});
-}
-template <typename T> __device__ __forceinline__ quad_t<T> load4_at(const T *base, uint32_t boff)
-{
-    return load_at(reinterpret_cast<const quad_t<T> *>(base), boff);
-}
 
 // ------------------------------------------------------------------ Adam
 // Hyper-parameters of one Adam step after the batch scaling rules of paper

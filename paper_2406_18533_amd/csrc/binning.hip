@@ -628,32 +628,37 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t value)
     if (j < n) p[j] = value;
 }
 
-// Start and end of every tile's run in the sorted keys. Each thread checks
-// four consecutive keys (one 16-byte load) against their neighbours.
-__global__ void ranges_kernel(const uint32_t *__restrict__ tiles, const int64_t *k_dev, int64_t cap,
-                              int64_t n_tiles, uint32_t *__restrict__ ranges)
+// Start and end of every tile's run in the sorted keys by binary search: a
+// thread per tile finds the first key not below its tile; the run ends where
+// the next tile's begins (the neighbouring lane's result; the last lane of a
+// wavefront searches once more). An empty run is written as [0, 0).
+__device__ __forceinline__ uint32_t first_not_below(const uint32_t *__restrict__ keys, uint32_t K, uint32_t x)
 {
-    int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    int64_t K = count_of(k_dev, cap);
-    if (k0 >= K) return;
-    uint32_t t[4];
-    if (k0 + 4 <= K && (reinterpret_cast<uintptr_t>(tiles) & 15) == 0) {
-        uint4 q = *reinterpret_cast<const uint4 *>(tiles + k0);   // k0 is a multiple of 4
-        t[0] = q.x; t[1] = q.y; t[2] = q.z; t[3] = q.w;
-    } else {
-        for (int i = 0; i < 4; i++) t[i] = k0 + i < K ? tiles[k0 + i] : 0u;
+    uint32_t lo = 0, n = K;
+    while (n > 0) {
+        const uint32_t h = n >> 1;
+        if (keys[lo + h] < x) {
+            lo += h + 1;
+            n -= h + 1;
+        } else {
+            n = h;
+        }
     }
-    uint32_t prev = k0 > 0 ? tiles[k0 - 1] : 0u;
-    uint32_t next = k0 + 4 < K ? tiles[k0 + 4] : 0u;
-    for (int i = 0; i < 4; i++) {
-        int64_t k = k0 + i;
-        if (k >= K) break;
-        uint32_t ti = t[i];
-        if (ti >= (uint32_t)n_tiles) continue;
-        uint32_t before = i == 0 ? prev : t[i - 1];
-        uint32_t after = i == 3 ? next : t[i + 1];
-        if (k == 0 || before != ti) ranges[2 * (int64_t)ti] = (uint32_t)k;
-        if (k == K - 1 || after != ti) ranges[2 * (int64_t)ti + 1] = (uint32_t)(k + 1);
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) ranges_search_kernel(const uint32_t *__restrict__ tiles, const int64_t *k_dev,
+                                                            int64_t cap, int64_t n_tiles, uint32_t *__restrict__ ranges)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t K = (uint32_t)count_of(k_dev, cap);
+    const uint32_t st = t < n_tiles ? first_not_below(tiles, K, (uint32_t)t) : K;
+    uint32_t en = __shfl_down(st, 1, 64);
+    if ((threadIdx.x & 63) == 63 && t < n_tiles) en = first_not_below(tiles, K, (uint32_t)(t + 1));
+    if (t < n_tiles) {
+        const bool any = en > st;
+        ranges[2 * t] = any ? st : 0u;
+        ranges[2 * t + 1] = any ? en : 0u;
     }
 }
 
@@ -797,8 +802,8 @@ hipError_t launch_bin_sort(const void *projv, int64_t n, const ViewTable &vt, gs
         e = seg_radix_sort(ek, ei, ak, ai, ws.iplan, vt.nviews, cap, bits, ws.hist, (uint32_t *)ws.partial, s);
         if (e != hipSuccess) return e;
     }
-    if (cap > 0)
-        hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((cap + 1023) / 1024)), dim3(256), 0, s,
+    if (cap > 0 && T_all > 0)
+        hipLaunchKernelGGL(ranges_search_kernel, dim3((unsigned)((T_all + 255) / 256)), dim3(256), 0, s,
                            (const uint32_t *)b->tile_keys, (const int64_t *)b->n_instances, cap, T_all, b->ranges);
     return hipGetLastError();
 }
